@@ -1,0 +1,41 @@
+"""Real-time evolution with the classic fourth-order Runge-Kutta method
+(oracle; test infrastructure).
+
+Sec. II.A, eq. (8): d psi~/dt = -i (T~ + V~(t) + g |psi~|^2) psi~ (hbar = 1),
+integrated with an explicit Runge-Kutta method without splitting.  Eq. (9):
+k_i = f(t + c_i dt, y^(i)) with y^(i) = y_0 + dt sum_{j<i} a_ij k_j.
+
+This is the standard k-form of RK4 (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3,
+1/6), deliberately not the memory-optimised form of App. A.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .operator import apply
+
+
+def rhs(T, V, g, y):
+    dens = y.real ** 2 + y.imag ** 2
+    return -1j * (apply(T, y) + (V + g * dens) * y)
+
+
+def rk4_step(T, y, t, dt, potential, g):
+    k1 = rhs(T, potential(t), g, y)
+    k2 = rhs(T, potential(t + dt / 2.0), g, y + (dt / 2.0) * k1)
+    k3 = rhs(T, potential(t + dt / 2.0), g, y + (dt / 2.0) * k2)
+    k4 = rhs(T, potential(t + dt), g, y + dt * k3)
+    return y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+
+def real_time(T, psi0, potential, g, dt, t0, steps, observe=None, observe_every=0):
+    """Run `steps` RK4 steps from time t0.  `potential(t)` returns V~ at time t.
+    Step n starts at t0 + n*dt.  If `observe` is given it is called as
+    observe(n, t, y) every `observe_every` steps (before the step)."""
+    y = np.array(psi0, dtype=np.complex128, copy=True)
+    for n in range(steps):
+        t = t0 + n * dt
+        if observe is not None and observe_every and n % observe_every == 0:
+            observe(n, t, y)
+        y = rk4_step(T, y, t, dt, potential, g)
+    return y
