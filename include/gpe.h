@@ -1,0 +1,270 @@
+/*
+ * gpe.h - C ABI of the MI355X (gfx950) solver for the Gross-Pitaevskii
+ * equation on a selectively sampled, semi-structured grid.
+ *
+ * Method: Beregi, Gerent, Lundblad, "Efficient simulation of Bose-Einstein
+ * condensates in nontrivial topologies" (arXiv:2603.05447).
+ *
+ * Problem (Sec. II, eqs. (1)-(3)), hbar = m = 1:
+ *   i d(psi)/dt = -1/2 Lap psi + V(x,t) psi + g |psi|^2 psi,   dV sum |psi|^2 = N.
+ * The grid is a Cartesian box of n[0] x n[1] x n[2] points at spacing h;
+ * only the sites of an active set A (the region of interest of Sec. II.A,
+ * e.g. the Thomas-Fermi region {V < cutoff}) are stored.  Rows/columns of
+ * the 7-point Laplacian (App. B, eq. (B1)) outside A are removed, i.e. psi
+ * is zero (Dirichlet) outside A and outside the box.
+ *
+ * Layout conventions used by every call:
+ *   - site (i,j,k) sits at x0 + (i,j,k).*h; box linear index (i*n1 + j)*n2 + k
+ *     (z fastest);
+ *   - "compact" arrays hold one entry per active site, in increasing box
+ *     linear index order; n_active < 2^31;
+ *   - complex arrays are interleaved (re, im): GPE_C128 = 2 x double per
+ *     site, GPE_C64 = 2 x float per site; real per-site arrays (potential
+ *     fields) use double for GPE_C128 and float for GPE_C64;
+ *   - device pointers are caller-owned and must be 16-byte aligned; the
+ *     library never frees them;
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
+ *     are stream-ordered and asynchronous, except that a call writing to a
+ *     *_host output synchronises `stream` before returning.
+ *
+ * Errors: every call returns a gpe_status.  Arguments are validated before
+ * anything is launched, so a call that fails validation has no effect.  A
+ * failure is described by gpe_last_error() (thread-local, valid until the
+ * next gpe_* call on the same thread).  No call aborts or throws.
+ * Handles must not be used from several threads at once.
+ */
+#ifndef GPE_H
+#define GPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPE_ABI_VERSION 1
+#define GPE_MAX_KNOTS 32
+
+typedef enum {
+  GPE_OK = 0,
+  GPE_ERR_ARG = 1,        /* invalid argument (null pointer, bad size, bad geometry, ...) */
+  GPE_ERR_ALLOC = 2,      /* host or device allocation failed */
+  GPE_ERR_DEVICE = 3,     /* a HIP call failed (including a device fault surfacing at a sync) */
+  GPE_ERR_STATE = 4,      /* handle not usable for this call (e.g. a host-only grid) */
+  GPE_ERR_UNSTABLE = 5,   /* dt above the explicit-scheme stability bound (when checking is on) */
+  GPE_ERR_NONFINITE = 6   /* a norm observed during the run was NaN/Inf */
+} gpe_status;
+
+typedef enum { GPE_C128 = 0, GPE_C64 = 1 } gpe_dtype;
+
+typedef enum { GPE_MODE_ITP = 0, GPE_MODE_RT = 1, GPE_MODE_ADJ = 2 } gpe_mode;
+
+typedef struct {
+  int64_t n[3];   /* points per axis, each >= 1 */
+  double h[3];    /* spacing per axis, each > 0 */
+  double x0[3];   /* coordinates of site (0,0,0) */
+} gpe_geometry;
+
+typedef struct gpe_grid_s* gpe_grid;
+typedef struct gpe_batch_s* gpe_batch;
+
+/* Potential (Sec. V, eq. (10)).
+ *   STATIC : V(x) = field[x].
+ *   RF_RAMP: V(x,t) = sqrt((field[x] - Delta(t))^2 + omega^2), the RF-dressed
+ *            potential with bare trap U = field; Delta(t) is the
+ *            piecewise-linear interpolant of (knot_t[k], knot_delta[k]),
+ *            constant before the first and after the last knot.
+ * `field` is a device pointer to n_active reals (double for GPE_C128, float
+ * for GPE_C64).  knot_t/knot_delta are host arrays of n_knots (1..GPE_MAX_KNOTS)
+ * entries, knot_t strictly increasing; ignored for STATIC. */
+typedef enum { GPE_POT_STATIC = 0, GPE_POT_RF_RAMP = 1 } gpe_pot_kind;
+
+typedef struct {
+  int32_t kind;
+  int32_t n_knots;
+  const void* field;
+  double omega;
+  const double* knot_t;
+  const double* knot_delta;
+} gpe_potential;
+
+typedef struct {
+  double g;               /* interaction constant of eqs. (1)-(2) */
+  double dt;              /* time step, > 0 */
+  double norm_target;     /* N of eq. (3) for imaginary time; <= 0 means 1 */
+  int64_t obs_every;      /* > 0: record an observation every obs_every steps */
+  int32_t check_stability;/* nonzero: fail with GPE_ERR_UNSTABLE above the bound */
+  int32_t reserved;       /* must be 0 */
+} gpe_params;
+
+typedef struct { double norm, energy, mu; } gpe_obs;
+
+const char* gpe_last_error(void);
+int gpe_abi_version(void);
+
+/* Build the compact layout of a grid (Sec. II.A: flatten, drop the sites
+ * outside the region of interest; the "normal point" structure of the
+ * paper's CPU kernel, generalised to runs along z split into segments with
+ * constant lateral neighbour offsets).
+ *   mask_host: n0*n1*n2 bytes, nonzero = active, box linear order.
+ *   device   : HIP device ordinal; -1 builds a host-only grid (tables only,
+ *              no device memory; compute calls on it return GPE_ERR_STATE).
+ * On success *out owns host and device tables; free with gpe_grid_destroy.
+ * Errors: GPE_ERR_ARG for bad geometry, an empty active set or more than
+ * 2^31-1 active sites; GPE_ERR_ALLOC/GPE_ERR_DEVICE on allocation/copy failure. */
+gpe_status gpe_grid_create(const gpe_geometry* geom, const uint8_t* mask_host, int device, gpe_grid* out);
+
+/* Same, from a host list of z-runs: runs_host holds nruns x {i, j, k0, k1}
+ * (int64, k1 exclusive), sorted by (i, j, k0), non-overlapping; runs that
+ * touch (k0 == previous k1 in the same column) are merged.  Suitable for
+ * boxes whose dense mask would be too large (e.g. 2^32 points). */
+gpe_status gpe_grid_create_runs(const gpe_geometry* geom, int64_t nruns, const int64_t* runs_host,
+                                int device, gpe_grid* out);
+
+gpe_status gpe_grid_info(gpe_grid grid, int64_t* n_active, int64_t* n_runs, int64_t* n_segments);
+
+/* Host copy of the segment table: n_segments x 8 int32 per segment
+ * {start, length, flags, off_xm, off_xp, off_ym, off_yp, 0}.  `start` is the
+ * compact index of the segment's first site; off_* is the constant compact
+ * offset of the (i-1), (i+1), (j-1), (j+1) neighbour of every site of the
+ * segment, 0 when that neighbour is outside A; flags bit 0 = the segment
+ * begins a z-run (its first site has no k-1 neighbour), bit 1 = it ends a
+ * z-run (its last site has no k+1 neighbour). */
+gpe_status gpe_grid_segments(gpe_grid grid, int32_t* out_host);
+
+/* Host copy of the run table: n_runs x 5 int64 {i, j, k0, k1, start}. */
+gpe_status gpe_grid_runs(gpe_grid grid, int64_t* out_host);
+
+gpe_status gpe_grid_destroy(gpe_grid grid);
+
+/* Size in bytes of the device work buffer a call needs.
+ *   mode GPE_MODE_ITP: gpe_imag_time; GPE_MODE_RT: gpe_real_time;
+ *   GPE_MODE_ADJ: gpe_fidelity_grad with nsteps and ckpt_every as given. */
+gpe_status gpe_work_bytes(gpe_grid grid, gpe_dtype dtype, int32_t mode, int64_t nsteps, int64_t ckpt_every,
+                          size_t* bytes);
+
+/* Box <-> compact copies.  box_dev holds n0*n1*n2 complex values of dtype;
+ * gpe_unpack writes zeros at inactive box points. */
+gpe_status gpe_pack(gpe_grid grid, gpe_dtype dtype, const void* box_dev, void* compact_dev, void* stream);
+gpe_status gpe_unpack(gpe_grid grid, gpe_dtype dtype, const void* compact_dev, void* box_dev, void* stream);
+
+/* Imaginary-time propagation with renormalisation (Sec. II.A, eqs. (6)-(7)).
+ * Each step: psi <- psi exp(-V dt/2)(1 - g|psi|^2 dt/2); two forward-Euler
+ * kinetic substeps of dt/2 (chi = phi - dt/2 T phi, twice); the diagonal
+ * half-step again; renormalise to dV sum |psi|^2 = norm_target.  The
+ * renormalisation factor is reduced in FP64 on the device and applied when
+ * the next step loads psi; psi as returned is normalised.  V is taken at
+ * time 0 for RF_RAMP.
+ *   psi       : device, n_active complex, in/out.
+ *   work      : device, >= gpe_work_bytes(.., GPE_MODE_ITP, ..) bytes.
+ *   final_host: optional (may be NULL) observation of the returned psi.
+ *   history_dev: optional device array of ceil(nsteps/obs_every) gpe_obs,
+ *               observation before steps 0, obs_every, ...
+ * check_stability: dt/2 * lambda_max(T) <= 2 for the Euler substeps. */
+gpe_status gpe_imag_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                         const gpe_params* params, int64_t nsteps, void* work, size_t work_bytes,
+                         void* stream, gpe_obs* final_host, gpe_obs* history_dev);
+
+/* Real-time evolution with RK4 (Sec. II.A eq. (8)), in the memory-optimised
+ * form of App. A (stored stage states y2, y3, y4; final combination
+ * b* = (-1/3, 1/3, 2/3, 1/3) plus dt/6 k4).  Step n starts at t0 + n dt;
+ * stage times t + (0, 1/2, 1/2, 1) dt.
+ * check_stability: dt * (lambda_max(T) + max V) <= 2 sqrt(2). */
+gpe_status gpe_real_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                         const gpe_params* params, double t0, int64_t nsteps, void* work, size_t work_bytes,
+                         void* stream, gpe_obs* final_host, gpe_obs* history_dev);
+
+/* Particle number (eq. (3)), energy and chemical potential of psi at time t:
+ * E = dV[Re psi^H T psi + sum V|psi|^2 + g/2 sum|psi|^4]/N, mu the same with g. */
+gpe_status gpe_observe(gpe_grid grid, gpe_dtype dtype, const void* psi, const gpe_potential* pot, double t,
+                       double g, void* stream, gpe_obs* out_host);
+
+/* <a|b> = dV sum conj(a) b, written as {re, im} to out_host. */
+gpe_status gpe_overlap(gpe_grid grid, gpe_dtype dtype, const void* a, const void* b, void* stream,
+                       double* out_host);
+
+/* Fidelity loss L = 1 - |<psi_target|psi(T)>|^2 after nsteps RK4 steps from
+ * psi0 at t0 under an RF_RAMP potential, and dL/dDelta_k for every knot, by
+ * the discrete adjoint of the RK4 map (the paper optimises the ramp without
+ * gradients, Sec. V; this is the gradient of the same forward scheme).
+ * Forward states are checkpointed every ckpt_every steps (0 = ceil(sqrt(nsteps)))
+ * and recomputed per segment in the reverse sweep.
+ *   psi_final: optional device output of psi(T) (may be NULL).
+ *   grad_host: n_knots doubles. */
+gpe_status gpe_fidelity_grad(gpe_grid grid, gpe_dtype dtype, const void* psi0, const void* psi_target,
+                             const gpe_potential* pot, const gpe_params* params, double t0, int64_t nsteps,
+                             int64_t ckpt_every, void* work, size_t work_bytes, void* stream,
+                             double* loss_host, double* grad_host, void* psi_final);
+
+/* ---- Batched instances ----------------------------------------------
+ * A batch concatenates the compact layouts of n grids (instance i occupies
+ * compact sites [offsets[i], offsets[i+1])) so one kernel launch advances
+ * every instance.  All per-site buffers passed to batch calls (psi, field,
+ * psi_target) are concatenated the same way. */
+typedef struct {
+  double omega;
+  int32_t n_knots;
+  int32_t reserved;
+  const double* knot_t;      /* host */
+  const double* knot_delta;  /* host */
+} gpe_ramp;
+
+gpe_status gpe_batch_create(int32_t n, const gpe_grid* grids, int device, gpe_batch* out);
+gpe_status gpe_batch_offsets(gpe_batch batch, int64_t* offsets_host /* n+1 */);
+gpe_status gpe_batch_destroy(gpe_batch batch);
+gpe_status gpe_batch_work_bytes(gpe_batch batch, gpe_dtype dtype, int32_t mode, int64_t nsteps,
+                                int64_t ckpt_every, size_t* bytes);
+
+/* RK4 real time for every instance: instance i uses ramps[i] (RF_RAMP, with
+ * field = its U) and params[i] (g, dt); all instances take nsteps steps from
+ * t0.  use_graph != 0 captures one step (all stage kernels of all instances)
+ * into a hipGraph on first use and replays it; the step counter lives in
+ * device memory so one graph serves every step.  final_host: optional n
+ * observations (per-instance FP64 reductions). */
+gpe_status gpe_batch_real_time(gpe_batch batch, gpe_dtype dtype, void* psi, const void* field,
+                               const gpe_ramp* ramps, const gpe_params* params, double t0, int64_t nsteps,
+                               int32_t use_graph, void* work, size_t work_bytes, void* stream,
+                               gpe_obs* final_host);
+
+/* Batched gpe_fidelity_grad: loss_host[n], grad_host[n x GPE_MAX_KNOTS]
+ * (instance i's gradient at grad_host + i*GPE_MAX_KNOTS, n_knots entries). */
+gpe_status gpe_batch_fidelity_grad(gpe_batch batch, gpe_dtype dtype, const void* psi0, const void* psi_target,
+                                   const void* field, const gpe_ramp* ramps, const gpe_params* params,
+                                   double t0, int64_t nsteps, int64_t ckpt_every, int32_t use_graph,
+                                   void* work, size_t work_bytes, void* stream, double* loss_host,
+                                   double* grad_host);
+
+/* ---- Launch configuration and autotuning -----------------------------
+ * A launch configuration is an index into the table of compiled kernel
+ * variants (workgroup size x sites per lane x chunk-to-XCD mapping);
+ * gpe_config_count/gpe_config_describe list them.  The grid's (or batch's)
+ * configuration is used by every later call on it. */
+int32_t gpe_config_count(void);
+gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* sites_per_lane, int32_t* xcd_map);
+gpe_status gpe_grid_set_config(gpe_grid grid, int32_t config);
+gpe_status gpe_grid_get_config(gpe_grid grid, int32_t* config);
+gpe_status gpe_batch_set_config(gpe_batch batch, int32_t config);
+
+/* Time every configuration on `reps` real-time RK4 steps of psi (contents
+ * are advanced; pass a scratch copy), select the fastest and store it on the
+ * grid.  times_ms_host: optional gpe_config_count() doubles (mean ms per
+ * step, or -1 for variants that could not run). */
+gpe_status gpe_grid_autotune(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                             const gpe_params* params, int32_t reps, void* work, size_t work_bytes,
+                             void* stream, int32_t* best_config, double* times_ms_host);
+
+/* ---- Per-kernel timing -----------------------------------------------
+ * When enabled, every kernel launch of the library is bracketed by HIP
+ * events on its stream and the elapsed time is accumulated per kernel
+ * family (names from gpe_timing_name).  Reading the totals synchronises. */
+gpe_status gpe_timing_enable(int32_t enable);
+gpe_status gpe_timing_reset(void);
+int32_t gpe_timing_count(void);
+const char* gpe_timing_name(int32_t family);
+gpe_status gpe_timing_read(int32_t family, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPE_H */

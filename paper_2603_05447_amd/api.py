@@ -1,0 +1,402 @@
+"""Python binding of the C ABI: argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every step of the solver
+runs in the HIP kernels of libgpe.so.  There is no CPU fallback: if the
+library is missing, importing this module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check
+
+_CDT = {torch.complex128: L.GPE_C128, torch.complex64: L.GPE_C64}
+_RDT = {L.GPE_C128: torch.float64, L.GPE_C64: torch.float32}
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dtype_of(psi: torch.Tensor) -> int:
+    if psi.dtype not in _CDT:
+        raise TypeError("psi must be complex128 or complex64")
+    if not psi.is_cuda or not psi.is_contiguous():
+        raise ValueError("psi must be a contiguous CUDA/HIP tensor")
+    return _CDT[psi.dtype]
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _dbl(a) -> C.Array:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return (C.c_double * a.size)(*a.tolist())
+
+
+class Potential:
+    """Static V(x) or RF-dressed ramp V = sqrt((U - Delta(t))^2 + omega^2)."""
+
+    def __init__(self, kind: int, field: torch.Tensor, omega: float = 0.0, knot_t=None, knot_delta=None):
+        self.kind = kind
+        self.field = field
+        self.omega = float(omega)
+        self.knot_t = None if knot_t is None else np.asarray(knot_t, np.float64)
+        self.knot_delta = None if knot_delta is None else np.asarray(knot_delta, np.float64)
+
+    @staticmethod
+    def static(V: torch.Tensor) -> "Potential":
+        return Potential(L.GPE_POT_STATIC, V)
+
+    @staticmethod
+    def rf(U: torch.Tensor, omega: float, knot_t, knot_delta) -> "Potential":
+        return Potential(L.GPE_POT_RF_RAMP, U, omega, knot_t, knot_delta)
+
+    def with_knots(self, knot_delta) -> "Potential":
+        return Potential(self.kind, self.field, self.omega, self.knot_t, knot_delta)
+
+    def as_c(self, dtype: int):
+        want = _RDT[dtype]
+        if self.field.dtype != want or not self.field.is_cuda or not self.field.is_contiguous():
+            raise TypeError(f"potential field must be a contiguous CUDA tensor of {want}")
+        p = L.Potential()
+        p.kind = self.kind
+        p.field = self.field.data_ptr()
+        p.omega = self.omega
+        keep = []
+        if self.kind == L.GPE_POT_RF_RAMP:
+            kt, kd = _dbl(self.knot_t), _dbl(self.knot_delta)
+            keep = [kt, kd]
+            p.n_knots = len(self.knot_t)
+            p.knot_t = C.cast(kt, C.POINTER(C.c_double))
+            p.knot_delta = C.cast(kd, C.POINTER(C.c_double))
+        else:
+            p.n_knots = 0
+        return p, keep
+
+
+def make_params(g: float, dt: float, norm_target: float = 1.0, obs_every: int = 0, check_stability: bool = False):
+    p = L.Params()
+    p.g, p.dt, p.norm_target = float(g), float(dt), float(norm_target)
+    p.obs_every = int(obs_every)
+    p.check_stability = 1 if check_stability else 0
+    p.reserved = 0
+    return p
+
+
+def _obs_dict(o: L.Obs) -> dict:
+    return {"norm": o.norm, "energy": o.energy, "mu": o.mu}
+
+
+class Grid:
+    """Compact layout of one masked grid (gpe_grid)."""
+
+    def __init__(self, n, h, x0, runs=None, mask=None, device: int = 0):
+        lib = L.load()
+        geom = L.Geometry()
+        for d in range(3):
+            geom.n[d], geom.h[d], geom.x0[d] = int(n[d]), float(h[d]), float(x0[d])
+        handle = C.c_void_p()
+        if runs is not None:
+            r = np.ascontiguousarray(np.asarray(runs, dtype=np.int64))
+            check(lib.gpe_grid_create_runs(C.byref(geom), r.shape[0], r.ctypes.data, int(device), C.byref(handle)))
+        elif mask is not None:
+            m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+            check(lib.gpe_grid_create(C.byref(geom), m.ctypes.data, int(device), C.byref(handle)))
+        else:
+            raise ValueError("need runs or mask")
+        self._h = handle
+        self.device = int(device)
+        self.n = tuple(int(v) for v in n)
+        self.h = tuple(float(v) for v in h)
+        self.dV = self.h[0] * self.h[1] * self.h[2]
+        na, nr, ns = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib.gpe_grid_info(handle, C.byref(na), C.byref(nr), C.byref(ns)))
+        self.n_active, self.n_runs, self.n_segments = na.value, nr.value, ns.value
+        self._work = {}
+
+    @staticmethod
+    def from_box(box, runs=None, mask=None, device: int = 0) -> "Grid":
+        return Grid(box.n, box.h, box.x0, runs=runs, mask=mask, device=device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                L.load().gpe_grid_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ---- host tables ----------------------------------------------------
+    def segments(self) -> np.ndarray:
+        out = np.zeros((self.n_segments, 8), np.int32)
+        check(L.load().gpe_grid_segments(self._h, out.ctypes.data))
+        return out
+
+    def runs(self) -> np.ndarray:
+        out = np.zeros((self.n_runs, 5), np.int64)
+        check(L.load().gpe_grid_runs(self._h, out.ctypes.data))
+        return out
+
+    # ---- work buffers ---------------------------------------------------
+    def work_bytes(self, dtype: int, mode: int, nsteps: int = 0, ckpt_every: int = 0) -> int:
+        b = C.c_size_t()
+        check(L.load().gpe_work_bytes(self._h, dtype, mode, int(nsteps), int(ckpt_every), C.byref(b)))
+        return b.value
+
+    def work(self, dtype: int, mode: int, nsteps: int = 0, ckpt_every: int = 0) -> torch.Tensor:
+        nb = self.work_bytes(dtype, mode, nsteps, ckpt_every)
+        key = (dtype, mode)
+        w = self._work.get(key)
+        if w is None or w.numel() < nb:
+            w = torch.empty(max(nb, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._work[key] = w
+        return w
+
+    def release_work(self):
+        self._work.clear()
+
+    # ---- solver calls ---------------------------------------------------
+    def imag_time(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, steps: int,
+                  norm_target: float = 1.0, obs_every: int = 0, history: Optional[torch.Tensor] = None,
+                  stream=None, observe: bool = True, check_stability: bool = False) -> Optional[dict]:
+        dt_ = _dtype_of(psi)
+        cp, keep = pot.as_c(dt_)
+        prm = make_params(g, dt, norm_target, obs_every, check_stability)
+        w = self.work(dt_, L.GPE_MODE_ITP, steps)
+        o = L.Obs()
+        check(L.load().gpe_imag_time(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), int(steps),
+                                     w.data_ptr(), w.numel(), _stream(stream), C.byref(o) if observe else None,
+                                     _ptr(history)))
+        return _obs_dict(o) if observe else None
+
+    def real_time(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, steps: int, t0: float = 0.0,
+                  obs_every: int = 0, history: Optional[torch.Tensor] = None, stream=None, observe: bool = True,
+                  check_stability: bool = False) -> Optional[dict]:
+        dt_ = _dtype_of(psi)
+        cp, keep = pot.as_c(dt_)
+        prm = make_params(g, dt, 1.0, obs_every, check_stability)
+        w = self.work(dt_, L.GPE_MODE_RT, steps)
+        o = L.Obs()
+        check(L.load().gpe_real_time(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), float(t0),
+                                     int(steps), w.data_ptr(), w.numel(), _stream(stream),
+                                     C.byref(o) if observe else None, _ptr(history)))
+        return _obs_dict(o) if observe else None
+
+    def observe(self, psi: torch.Tensor, pot: Potential, t: float, g: float, stream=None) -> dict:
+        dt_ = _dtype_of(psi)
+        cp, keep = pot.as_c(dt_)
+        o = L.Obs()
+        check(L.load().gpe_observe(self._h, dt_, psi.data_ptr(), C.byref(cp), float(t), float(g), _stream(stream),
+                                   C.byref(o)))
+        return _obs_dict(o)
+
+    def overlap(self, a: torch.Tensor, b: torch.Tensor, stream=None) -> complex:
+        dt_ = _dtype_of(a)
+        if b.dtype != a.dtype:
+            raise TypeError("a and b must have the same dtype")
+        out = (C.c_double * 2)()
+        check(L.load().gpe_overlap(self._h, dt_, a.data_ptr(), b.data_ptr(), _stream(stream), out))
+        return complex(out[0], out[1])
+
+    def fidelity_grad(self, psi0: torch.Tensor, target: torch.Tensor, pot: Potential, g: float, dt: float,
+                      steps: int, t0: float = 0.0, ckpt_every: int = 0, psi_final: Optional[torch.Tensor] = None,
+                      stream=None, check_stability: bool = False):
+        dt_ = _dtype_of(psi0)
+        cp, keep = pot.as_c(dt_)
+        prm = make_params(g, dt, 1.0, 0, check_stability)
+        nb = self.work_bytes(dt_, L.GPE_MODE_ADJ, steps, ckpt_every)
+        w = torch.empty(max(nb, 256), dtype=torch.uint8, device=psi0.device)
+        loss = C.c_double()
+        grad = (C.c_double * L.GPE_MAX_KNOTS)()
+        check(L.load().gpe_fidelity_grad(self._h, dt_, psi0.data_ptr(), target.data_ptr(), C.byref(cp),
+                                         C.byref(prm), float(t0), int(steps), int(ckpt_every), w.data_ptr(),
+                                         w.numel(), _stream(stream), C.byref(loss), grad, _ptr(psi_final)))
+        n = len(pot.knot_t)
+        return loss.value, np.array(grad[:n])
+
+    def pack(self, box: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        dt_ = _dtype_of(box)
+        if out is None:
+            out = torch.empty(self.n_active, dtype=box.dtype, device=box.device)
+        check(L.load().gpe_pack(self._h, dt_, box.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    def unpack(self, compact: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        dt_ = _dtype_of(compact)
+        if out is None:
+            out = torch.empty(self.n, dtype=compact.dtype, device=compact.device)
+        check(L.load().gpe_unpack(self._h, dt_, compact.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
+
+    # ---- launch configuration -------------------------------------------
+    def set_config(self, config: int) -> None:
+        check(L.load().gpe_grid_set_config(self._h, int(config)))
+
+    def get_config(self) -> int:
+        c = C.c_int32()
+        check(L.load().gpe_grid_get_config(self._h, C.byref(c)))
+        return c.value
+
+    def autotune(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, reps: int = 5, stream=None):
+        dt_ = _dtype_of(psi)
+        cp, keep = pot.as_c(dt_)
+        prm = make_params(g, dt)
+        w = self.work(dt_, L.GPE_MODE_RT, reps)
+        n = config_count()
+        times = (C.c_double * n)(*([-1.0] * n))
+        best = C.c_int32()
+        check(L.load().gpe_grid_autotune(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), int(reps),
+                                         w.data_ptr(), w.numel(), _stream(stream), C.byref(best), times))
+        return best.value, list(times)
+
+
+class Batch:
+    """Several grids concatenated into one compact layout (gpe_batch)."""
+
+    def __init__(self, grids: Sequence[Grid], device: int = 0):
+        lib = L.load()
+        arr = (C.c_void_p * len(grids))(*[g.handle.value for g in grids])
+        h = C.c_void_p()
+        check(lib.gpe_batch_create(len(grids), arr, int(device), C.byref(h)))
+        self._h = h
+        self.grids = list(grids)
+        self.device = int(device)
+        off = (C.c_int64 * (len(grids) + 1))()
+        check(lib.gpe_batch_offsets(h, off))
+        self.offsets = np.array(off[:], dtype=np.int64)
+        self.total = int(self.offsets[-1])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                L.load().gpe_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def work_bytes(self, dtype: int, mode: int, nsteps: int = 0, ckpt_every: int = 0) -> int:
+        b = C.c_size_t()
+        check(L.load().gpe_batch_work_bytes(self._h, dtype, mode, int(nsteps), int(ckpt_every), C.byref(b)))
+        return b.value
+
+    def set_config(self, config: int) -> None:
+        check(L.load().gpe_batch_set_config(self._h, int(config)))
+
+    @staticmethod
+    def _ramps(ramps):
+        n = len(ramps)
+        arr = (L.Ramp * n)()
+        keep = []
+        for i, (omega, kt, kd) in enumerate(ramps):
+            a, b = _dbl(kt), _dbl(kd)
+            keep += [a, b]
+            arr[i].omega = float(omega)
+            arr[i].n_knots = len(kt)
+            arr[i].reserved = 0
+            arr[i].knot_t = C.cast(a, C.POINTER(C.c_double))
+            arr[i].knot_delta = C.cast(b, C.POINTER(C.c_double))
+        return arr, keep
+
+    @staticmethod
+    def _params(gs, dts):
+        arr = (L.Params * len(gs))()
+        for i, (g, dt) in enumerate(zip(gs, dts)):
+            arr[i] = make_params(g, dt)
+        return arr
+
+    def real_time(self, psi: torch.Tensor, field: torch.Tensor, ramps, gs, dts, steps: int, t0: float = 0.0,
+                  use_graph: bool = True, work: Optional[torch.Tensor] = None, stream=None, observe: bool = True):
+        dt_ = _dtype_of(psi)
+        ra, keep = self._ramps(ramps)
+        pa = self._params(gs, dts)
+        nb = self.work_bytes(dt_, L.GPE_MODE_RT, steps)
+        if work is None or work.numel() < nb:
+            work = torch.empty(max(nb, 256), dtype=torch.uint8, device=psi.device)
+        obs = (L.Obs * len(self.grids))()
+        check(L.load().gpe_batch_real_time(self._h, dt_, psi.data_ptr(), field.data_ptr(), ra, pa, float(t0),
+                                           int(steps), 1 if use_graph else 0, work.data_ptr(), work.numel(),
+                                           _stream(stream), obs if observe else None))
+        return [_obs_dict(o) for o in obs] if observe else None
+
+    def fidelity_grad(self, psi0: torch.Tensor, target: torch.Tensor, field: torch.Tensor, ramps, gs, dts,
+                      steps: int, t0: float = 0.0, ckpt_every: int = 0, stream=None):
+        dt_ = _dtype_of(psi0)
+        ra, keep = self._ramps(ramps)
+        pa = self._params(gs, dts)
+        nb = self.work_bytes(dt_, L.GPE_MODE_ADJ, steps, ckpt_every)
+        w = torch.empty(max(nb, 256), dtype=torch.uint8, device=psi0.device)
+        n = len(self.grids)
+        loss = (C.c_double * n)()
+        grad = (C.c_double * (n * L.GPE_MAX_KNOTS))()
+        check(L.load().gpe_batch_fidelity_grad(self._h, dt_, psi0.data_ptr(), target.data_ptr(), field.data_ptr(),
+                                               ra, pa, float(t0), int(steps), int(ckpt_every), 0, w.data_ptr(),
+                                               w.numel(), _stream(stream), loss, grad))
+        g = np.array(grad[:], dtype=np.float64).reshape(n, L.GPE_MAX_KNOTS)
+        return np.array(loss[:]), [g[i, :len(ramps[i][1])] for i in range(n)]
+
+
+class FidelityGrad(torch.autograd.Function):
+    """loss = 1 - |<target|psi(T)>|^2 as a differentiable function of the ramp
+    knot values; forward runs the RK4 forward sweep and the adjoint sweep on
+    the device (one ABI call) and caches dL/dknots for backward."""
+
+    @staticmethod
+    def forward(ctx, knots: torch.Tensor, grid: Grid, psi0: torch.Tensor, target: torch.Tensor, U: torch.Tensor,
+                omega: float, knot_t, g: float, dt: float, steps: int, ckpt_every: int = 0):
+        kd = knots.detach().to("cpu", torch.float64).numpy()
+        pot = Potential.rf(U, omega, knot_t, kd)
+        loss, grad = grid.fidelity_grad(psi0, target, pot, g, dt, steps, 0.0, ckpt_every)
+        ctx.save_for_backward(torch.as_tensor(grad, dtype=knots.dtype, device=knots.device))
+        return torch.tensor(loss, dtype=knots.dtype, device=knots.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (grad,) = ctx.saved_tensors
+        return (grad_out * grad,) + (None,) * 10
+
+
+def config_count() -> int:
+    return int(L.load().gpe_config_count())
+
+
+def config_describe(i: int):
+    b, s, x = C.c_int32(), C.c_int32(), C.c_int32()
+    check(L.load().gpe_config_describe(int(i), C.byref(b), C.byref(s), C.byref(x)))
+    return {"block": b.value, "sites_per_lane": s.value, "xcd_map": x.value}
+
+
+class KernelTimer:
+    """Per-kernel-family HIP-event timing inside the library."""
+
+    def __enter__(self):
+        L.load().gpe_timing_reset()
+        L.load().gpe_timing_enable(1)
+        return self
+
+    def __exit__(self, *exc):
+        L.load().gpe_timing_enable(0)
+
+    @staticmethod
+    def read() -> dict:
+        lib = L.load()
+        out = {}
+        for f in range(lib.gpe_timing_count()):
+            n, ms = C.c_int64(), C.c_double()
+            check(lib.gpe_timing_read(f, C.byref(n), C.byref(ms)))
+            out[lib.gpe_timing_name(f).decode()] = {"launches": n.value, "total_ms": ms.value}
+        return out

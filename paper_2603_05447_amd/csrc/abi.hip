@@ -1,0 +1,1410 @@
+// C ABI of the solver: argument validation, device tables, work-buffer
+// layout and the host-side step drivers.  Every step of the method runs in
+// the kernels of kernels.hip; this file only orders launches on the caller's
+// stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+
+using namespace gpe;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_err;
+
+static gpe_status fail(gpe_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return st;
+}
+
+static gpe_status hip_fail(hipError_t e, const char* what) {
+  return fail(GPE_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);   \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (dev >= 0 && dev != prev) ok = (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+// ---------------------------------------------------------------------------
+namespace {
+struct TimingState {
+  bool enabled = false;
+  int64_t launches[FAM_COUNT] = {0};
+  double ms[FAM_COUNT] = {0};
+  struct Pending { int fam; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open_a = nullptr;
+  int open_fam = -1;
+};
+TimingState g_tim;
+
+hipEvent_t pool_get() {
+  if (!g_tim.pool.empty()) {
+    hipEvent_t e = g_tim.pool.back();
+    g_tim.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void resolve_pending(size_t keep) {
+  while (g_tim.pending.size() > keep) {
+    TimingState::Pending p = g_tim.pending.front();
+    g_tim.pending.erase(g_tim.pending.begin());
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      g_tim.ms[p.fam] += ms;
+      g_tim.launches[p.fam] += 1;
+    }
+    g_tim.pool.push_back(p.a);
+    g_tim.pool.push_back(p.b);
+  }
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+}  // namespace
+
+namespace gpe {
+void timing_before(int fam, hipStream_t s) {
+  if (!g_tim.enabled || capturing(s)) return;
+  hipEvent_t a = pool_get();
+  if (!a) return;
+  if (hipEventRecord(a, s) != hipSuccess) {
+    g_tim.pool.push_back(a);
+    return;
+  }
+  g_tim.open_a = a;
+  g_tim.open_fam = fam;
+}
+void timing_after(int fam, hipStream_t s) {
+  if (!g_tim.enabled || g_tim.open_a == nullptr || g_tim.open_fam != fam) return;
+  hipEvent_t b = pool_get();
+  if (!b || hipEventRecord(b, s) != hipSuccess) {
+    g_tim.pool.push_back(g_tim.open_a);
+    if (b) g_tim.pool.push_back(b);
+    g_tim.open_a = nullptr;
+    return;
+  }
+  g_tim.pending.push_back({fam, g_tim.open_a, b});
+  g_tim.open_a = nullptr;
+  if (g_tim.pending.size() > 16384) resolve_pending(8192);
+}
+}  // namespace gpe
+
+// ---------------------------------------------------------------------------
+// problem: one or more instances in one concatenated compact layout
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+struct ChunkSet {
+  int capacity = 0;
+  int n_chunks = 0;
+  Chunk* d_chunks = nullptr;
+  std::vector<int> inst_begin, inst_count;
+};
+
+struct Problem {
+  int device = -1;
+  int n_inst = 0;
+  int64_t total = 0;
+  int64_t n_segs = 0;
+  std::vector<int64_t> inst_site;      // n_inst + 1
+  std::vector<int64_t> inst_seg;       // n_inst + 1
+  std::vector<double> inst_h;          // 3 per instance
+  std::vector<SegHead> heads;          // host copy (n_segs + 1)
+  SegHead* d_heads = nullptr;
+  SegNb* d_nbs = nullptr;
+  std::map<int, ChunkSet> chunksets;
+  InstParams* d_inst = nullptr;
+  InstOut* d_out = nullptr;
+  int64_t* d_step = nullptr;
+  double* d_partials = nullptr;
+  double* d_knot_acc = nullptr;
+  double* d_grads = nullptr;
+  int64_t max_chunks = 0;
+  InstParams* h_inst = nullptr;        // pinned staging
+  hipEvent_t upload_done = nullptr;
+  int config = 0;
+  // captured forward-step graphs, keyed by buffer pointers
+  struct GraphKey {
+    const void *psi, *field, *work;
+    int dtype, config;
+    bool operator<(const GraphKey& o) const {
+      return std::tie(psi, field, work, dtype, config) < std::tie(o.psi, o.field, o.work, o.dtype, o.config);
+    }
+  };
+  std::map<GraphKey, hipGraphExec_t> graphs;
+
+  ~Problem() { release(); }
+  void release() {
+    if (device < 0) return;
+    DeviceGuard g(device);
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    for (auto& kv : chunksets) (void)hipFree(kv.second.d_chunks);
+    chunksets.clear();
+    (void)hipFree(d_heads);
+    (void)hipFree(d_nbs);
+    (void)hipFree(d_inst);
+    (void)hipFree(d_out);
+    (void)hipFree(d_step);
+    (void)hipFree(d_partials);
+    (void)hipFree(d_knot_acc);
+    (void)hipFree(d_grads);
+    if (h_inst) (void)hipHostFree(h_inst);
+    if (upload_done) (void)hipEventDestroy(upload_done);
+    d_heads = nullptr;
+    d_nbs = nullptr;
+    d_inst = nullptr;
+    d_out = nullptr;
+    d_step = nullptr;
+    d_partials = d_knot_acc = d_grads = nullptr;
+    h_inst = nullptr;
+    upload_done = nullptr;
+    device = -1;
+  }
+
+  // Build from instance layouts (concatenated in order).
+  gpe_status build(int dev, const std::vector<const Layout*>& lays) {
+    device = dev;
+    n_inst = (int)lays.size();
+    inst_site.assign(n_inst + 1, 0);
+    inst_seg.assign(n_inst + 1, 0);
+    inst_h.assign(3 * n_inst, 0.0);
+    for (int i = 0; i < n_inst; ++i) {
+      inst_site[i + 1] = inst_site[i] + lays[i]->n_active;
+      inst_seg[i + 1] = inst_seg[i] + lays[i]->n_segments();
+      for (int d = 0; d < 3; ++d) inst_h[3 * i + d] = lays[i]->h[d];
+    }
+    total = inst_site[n_inst];
+    n_segs = inst_seg[n_inst];
+    if (total > (int64_t)INT32_MAX - 1) return fail(GPE_ERR_ARG, "more than 2^31-2 active sites in total");
+    heads.resize(n_segs + 1);
+    std::vector<SegNb> nbs(n_segs);
+    for (int i = 0; i < n_inst; ++i) {
+      const Layout& L = *lays[i];
+      for (int64_t q = 0; q < L.n_segments(); ++q) {
+        SegHead h = L.heads[q];
+        h.start += (int32_t)inst_site[i];
+        heads[inst_seg[i] + q] = h;
+        nbs[inst_seg[i] + q] = L.nbs[q];
+      }
+    }
+    heads[n_segs] = {(int32_t)total, 0};
+    DeviceGuard g(device);
+    if (!g.ok) return fail(GPE_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+    max_chunks = 0;
+    for (int i = 0; i < n_inst; ++i) max_chunks += (lays[i]->n_active + 255) / 256;
+    if (dalloc(&d_heads, n_segs + 1) != hipSuccess || dalloc(&d_nbs, n_segs) != hipSuccess ||
+        dalloc(&d_inst, n_inst) != hipSuccess || dalloc(&d_out, n_inst) != hipSuccess ||
+        dalloc(&d_step, 1) != hipSuccess || dalloc(&d_partials, max_chunks * NPART) != hipSuccess ||
+        dalloc(&d_knot_acc, max_chunks * GPE_MAX_KNOTS) != hipSuccess ||
+        dalloc(&d_grads, (size_t)n_inst * GPE_MAX_KNOTS) != hipSuccess) {
+      release();
+      return fail(GPE_ERR_ALLOC, "device allocation of grid tables failed");
+    }
+    if (hipHostMalloc((void**)&h_inst, sizeof(InstParams) * n_inst) != hipSuccess) {
+      h_inst = nullptr;
+      release();
+      return fail(GPE_ERR_ALLOC, "pinned host allocation failed");
+    }
+    if (hipEventCreateWithFlags(&upload_done, hipEventDisableTiming) != hipSuccess) {
+      upload_done = nullptr;
+      release();
+      return fail(GPE_ERR_DEVICE, "hipEventCreate failed");
+    }
+    hipError_t e = hipMemcpy(d_heads, heads.data(), sizeof(SegHead) * (n_segs + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_segs > 0)
+      e = hipMemcpy(d_nbs, nbs.data(), sizeof(SegNb) * n_segs, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_out, 0, sizeof(InstOut) * n_inst);
+    if (e == hipSuccess) e = hipMemset(d_step, 0, sizeof(int64_t));
+    if (e != hipSuccess) {
+      gpe_status st = hip_fail(e, "upload of grid tables");
+      release();
+      return st;
+    }
+    return GPE_OK;
+  }
+
+  // chunk table for a chunk capacity (built on first use)
+  gpe_status chunks_for(int capacity, ChunkSet** out) {
+    auto it = chunksets.find(capacity);
+    if (it != chunksets.end()) {
+      *out = &it->second;
+      return GPE_OK;
+    }
+    ChunkSet cs;
+    cs.capacity = capacity;
+    std::vector<Chunk> tab;
+    cs.inst_begin.resize(n_inst);
+    cs.inst_count.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      cs.inst_begin[i] = (int)tab.size();
+      int64_t seg = inst_seg[i];
+      for (int64_t b = inst_site[i]; b < inst_site[i + 1]; b += capacity) {
+        const int64_t e = std::min<int64_t>(b + capacity, inst_site[i + 1]);
+        while (heads[seg + 1].start <= b) ++seg;
+        int64_t last = seg;
+        while (heads[last + 1].start <= e - 1) ++last;
+        Chunk c;
+        c.site_begin = (int32_t)b;
+        c.count = (int32_t)(e - b);
+        c.seg_begin = (int32_t)seg;
+        c.seg_count = (int32_t)(last - seg + 1);
+        c.inst = i;
+        c.pad[0] = c.pad[1] = c.pad[2] = 0;
+        tab.push_back(c);
+      }
+      cs.inst_count[i] = (int)tab.size() - cs.inst_begin[i];
+    }
+    cs.n_chunks = (int)tab.size();
+    if ((int64_t)cs.n_chunks > max_chunks) return fail(GPE_ERR_STATE, "internal: chunk count exceeds scratch");
+    DeviceGuard g(device);
+    if (dalloc(&cs.d_chunks, tab.size()) != hipSuccess) return fail(GPE_ERR_ALLOC, "chunk table allocation failed");
+    hipError_t e = hipMemcpy(cs.d_chunks, tab.data(), sizeof(Chunk) * tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(cs.d_chunks);
+      return hip_fail(e, "chunk table upload");
+    }
+    auto res = chunksets.emplace(capacity, std::move(cs));
+    *out = &res.first->second;
+    return GPE_OK;
+  }
+
+  Plan plan(const ChunkSet& cs, const LaunchConfig& cfg) const {
+    Plan p;
+    p.heads = d_heads;
+    p.nbs = d_nbs;
+    p.chunks = cs.d_chunks;
+    p.inst = d_inst;
+    p.partials = d_partials;
+    p.knot_acc = d_knot_acc;
+    p.out = d_out;
+    p.step = d_step;
+    p.n_chunks = cs.n_chunks;
+    p.n_inst = n_inst;
+    p.xcd_map = cfg.xcd;
+    p.pad = 0;
+    return p;
+  }
+
+  // Fill and upload the per-instance parameters.
+  gpe_status upload(const ChunkSet& cs, const std::vector<InstParams>& ps, hipStream_t s) {
+    if (hipEventSynchronize(upload_done) != hipSuccess) return fail(GPE_ERR_DEVICE, "hipEventSynchronize failed");
+    for (int i = 0; i < n_inst; ++i) {
+      h_inst[i] = ps[i];
+      h_inst[i].chunk_begin = cs.inst_begin[i];
+      h_inst[i].chunk_count = cs.inst_count[i];
+      h_inst[i].site_begin = inst_site[i];
+      h_inst[i].n_sites = inst_site[i + 1] - inst_site[i];
+      const double* h = &inst_h[3 * i];
+      h_inst[i].cx = -0.5 / (h[0] * h[0]);
+      h_inst[i].cy = -0.5 / (h[1] * h[1]);
+      h_inst[i].cz = -0.5 / (h[2] * h[2]);
+      h_inst[i].cd = 1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]);
+      h_inst[i].dV = h[0] * h[1] * h[2];
+    }
+    HIP_TRY(hipMemcpyAsync(d_inst, h_inst, sizeof(InstParams) * n_inst, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(upload_done, s));
+    return GPE_OK;
+  }
+};
+
+// work buffer carving (256-byte aligned sub-buffers)
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  void* take(size_t bytes) {
+    void* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~size_t(255);
+    return p;
+  }
+};
+
+size_t csize(int dtype) { return dtype == GPE_C128 ? 16 : 8; }
+size_t rsize(int dtype) { return dtype == GPE_C128 ? 8 : 4; }
+
+int64_t ckpt_interval(int64_t nsteps, int64_t ckpt_every) {
+  if (ckpt_every > 0) return ckpt_every;
+  int64_t k = (int64_t)std::ceil(std::sqrt((double)std::max<int64_t>(nsteps, 1)));
+  while (k * k < nsteps) ++k;
+  return std::max<int64_t>(k, 1);
+}
+
+size_t work_bytes_for(int64_t n, int dtype, int mode, int64_t nsteps, int64_t ckpt_every) {
+  Carver c(nullptr);
+  const size_t st = (size_t)n * csize(dtype);
+  if (mode == GPE_MODE_ITP) {
+    c.take(st);
+    c.take((size_t)n * rsize(dtype));
+  } else if (mode == GPE_MODE_RT) {
+    for (int i = 0; i < 3; ++i) c.take(st);
+  } else {
+    const int64_t K = ckpt_interval(nsteps, ckpt_every);
+    const int64_t nck = (std::max<int64_t>(nsteps, 1) + K - 1) / K;
+    for (int64_t i = 0; i < nck + K + 8; ++i) c.take(st);
+  }
+  return c.off;
+}
+
+}  // namespace
+
+struct gpe_grid_s {
+  Layout lay;
+  int device = -1;
+  std::unique_ptr<Problem> prob;
+  int64_t* d_run_base = nullptr;
+  int32_t* d_run_start = nullptr;
+  ~gpe_grid_s() {
+    if (device >= 0) {
+      DeviceGuard g(device);
+      (void)hipFree(d_run_base);
+      (void)hipFree(d_run_start);
+    }
+  }
+};
+
+struct gpe_batch_s {
+  std::vector<gpe_grid> grids;
+  int device = -1;
+  std::unique_ptr<Problem> prob;
+};
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+namespace {
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+gpe_status check_dtype(int dtype) {
+  if (dtype != GPE_C128 && dtype != GPE_C64) return fail(GPE_ERR_ARG, "dtype must be GPE_C128 or GPE_C64");
+  return GPE_OK;
+}
+
+gpe_status check_ptr(const void* p, const char* name) {
+  if (!p) return fail(GPE_ERR_ARG, "%s is NULL", name);
+  if (!aligned16(p)) return fail(GPE_ERR_ARG, "%s is not 16-byte aligned", name);
+  return GPE_OK;
+}
+
+gpe_status check_knots(int32_t n, const double* kt, const double* kv, const char* who) {
+  if (n < 1 || n > GPE_MAX_KNOTS) return fail(GPE_ERR_ARG, "%s: n_knots must be in [1, %d]", who, GPE_MAX_KNOTS);
+  if (!kt || !kv) return fail(GPE_ERR_ARG, "%s: knot arrays are NULL", who);
+  for (int k = 0; k < n; ++k) {
+    if (!std::isfinite(kt[k]) || !std::isfinite(kv[k])) return fail(GPE_ERR_ARG, "%s: non-finite knot", who);
+    if (k > 0 && !(kt[k] > kt[k - 1])) return fail(GPE_ERR_ARG, "%s: knot_t must be strictly increasing", who);
+  }
+  return GPE_OK;
+}
+
+gpe_status check_pot(const gpe_potential* pot) {
+  if (!pot) return fail(GPE_ERR_ARG, "potential is NULL");
+  if (pot->kind != GPE_POT_STATIC && pot->kind != GPE_POT_RF_RAMP) return fail(GPE_ERR_ARG, "unknown potential kind");
+  gpe_status st = check_ptr(pot->field, "potential field");
+  if (st != GPE_OK) return st;
+  if (pot->kind == GPE_POT_RF_RAMP) {
+    if (!std::isfinite(pot->omega)) return fail(GPE_ERR_ARG, "omega must be finite");
+    return check_knots(pot->n_knots, pot->knot_t, pot->knot_delta, "potential");
+  }
+  return GPE_OK;
+}
+
+gpe_status check_params(const gpe_params* p) {
+  if (!p) return fail(GPE_ERR_ARG, "params is NULL");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(GPE_ERR_ARG, "dt must be finite and > 0");
+  if (!std::isfinite(p->g)) return fail(GPE_ERR_ARG, "g must be finite");
+  if (!std::isfinite(p->norm_target)) return fail(GPE_ERR_ARG, "norm_target must be finite");
+  if (p->obs_every < 0) return fail(GPE_ERR_ARG, "obs_every must be >= 0");
+  if (p->reserved != 0) return fail(GPE_ERR_ARG, "params.reserved must be 0");
+  return GPE_OK;
+}
+
+gpe_status check_grid(gpe_grid g) {
+  if (!g) return fail(GPE_ERR_ARG, "grid is NULL");
+  if (g->device < 0 || !g->prob) return fail(GPE_ERR_STATE, "grid is host-only (created with device -1)");
+  return GPE_OK;
+}
+
+InstParams make_params(const gpe_potential* pot, const gpe_params* prm, double t0) {
+  InstParams ip;
+  std::memset(&ip, 0, sizeof ip);
+  ip.g = prm ? prm->g : 0.0;
+  ip.dt = prm ? prm->dt : 1.0;
+  ip.t0 = t0;
+  ip.norm_target = (prm && prm->norm_target > 0.0) ? prm->norm_target : 1.0;
+  ip.pot_kind = pot ? pot->kind : GPE_POT_STATIC;
+  ip.omega = (pot && pot->kind == GPE_POT_RF_RAMP) ? pot->omega : 0.0;
+  ip.n_knots = 1;
+  if (pot && pot->kind == GPE_POT_RF_RAMP) {
+    ip.n_knots = pot->n_knots;
+    for (int k = 0; k < pot->n_knots; ++k) {
+      ip.knot_t[k] = pot->knot_t[k];
+      ip.knot_v[k] = pot->knot_delta[k];
+    }
+  }
+  return ip;
+}
+
+double kinetic_bound(const Problem& P) {
+  double m = 0.0;
+  for (int i = 0; i < P.n_inst; ++i) {
+    const double* h = &P.inst_h[3 * i];
+    m = std::max(m, 2.0 * (1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2])));
+  }
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// drivers
+// ---------------------------------------------------------------------------
+struct Ctx {
+  Problem* P;
+  ChunkSet* cs;
+  LaunchConfig cfg;
+  Plan pl;
+  hipStream_t s;
+};
+
+gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
+  c.P = P;
+  c.cfg = config_get(config);
+  gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs);
+  if (st != GPE_OK) return st;
+  c.pl = P->plan(*c.cs, c.cfg);
+  c.s = s;
+  return GPE_OK;
+}
+
+#define LTRY(expr)                                          \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return hip_fail(_e, #expr);       \
+  } while (0)
+
+template <typename R>
+gpe_status rk_step(const Ctx& c, const void* y0, const void* field, void* y2, void* y3, void* y4, void* out,
+                   bool obs, gpe_obs* obs_dev) {
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, obs, y0, y0, nullptr, nullptr, field, y2, c.s));
+  if (obs) LTRY(run_finalize(c.pl, FIN_OBS, obs_dev, c.s));
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, y0, nullptr, nullptr, field, y3, c.s));
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, y0, nullptr, nullptr, field, y4, c.s));
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 4, false, y4, y0, y2, y3, field, out, c.s));
+  LTRY(run_tick(c.pl.step, 1, c.s));
+  return GPE_OK;
+}
+
+template <typename R>
+gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps, void* work, int64_t obs_every,
+                     gpe_obs* hist) {
+  Carver cv(work);
+  void* tmp = cv.take((size_t)c.P->total * 2 * sizeof(R));
+  void* prop = cv.take((size_t)c.P->total * sizeof(R));
+  LTRY(run_set_step(c.pl.step, 0, c.s));
+  LTRY(run_make_prop<R>(c.pl, c.cfg, field, prop, c.s));
+  LTRY(run_set_scale_one(c.pl, c.s));
+  int64_t k = 0;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    if (hist && obs_every > 0 && n % obs_every == 0) {
+      LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, true, c.s));
+      LTRY(run_finalize(c.pl, FIN_OBS, hist + k * c.P->n_inst, c.s));
+      ++k;
+    }
+    LTRY(run_itp_pass1<R>(c.pl, c.cfg, psi, prop, tmp, c.s));
+    LTRY(run_itp_pass2<R>(c.pl, c.cfg, tmp, prop, psi, c.s));
+    LTRY(run_finalize(c.pl, FIN_NORM_SCALE, nullptr, c.s));
+  }
+  if (nsteps > 0) LTRY(run_apply_scale<R>(c.pl, c.cfg, psi, c.s));
+  return GPE_OK;
+}
+
+template <typename R>
+gpe_status drive_rt(const Ctx& c, void* psi, const void* field, int64_t nsteps, void* work, int64_t obs_every,
+                    gpe_obs* hist) {
+  Carver cv(work);
+  const size_t st = (size_t)c.P->total * 2 * sizeof(R);
+  void* y2 = cv.take(st);
+  void* y3 = cv.take(st);
+  void* y4 = cv.take(st);
+  LTRY(run_set_step(c.pl.step, 0, c.s));
+  int64_t k = 0;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const bool obs = hist && obs_every > 0 && n % obs_every == 0;
+    gpe_status r = rk_step<R>(c, psi, field, y2, y3, y4, psi, obs, obs ? hist + k * c.P->n_inst : nullptr);
+    if (r != GPE_OK) return r;
+    if (obs) ++k;
+  }
+  return GPE_OK;
+}
+
+template <typename R>
+gpe_status drive_observe(const Ctx& c, const void* psi, const void* field, bool use_scale) {
+  LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, use_scale, c.s));
+  LTRY(run_finalize(c.pl, FIN_OBS, nullptr, c.s));
+  return GPE_OK;
+}
+
+gpe_status read_obs(Problem& P, gpe_obs* out_host, hipStream_t s) {
+  std::vector<InstOut> o(P.n_inst);
+  HIP_TRY(hipMemcpyAsync(o.data(), P.d_out, sizeof(InstOut) * P.n_inst, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  bool finite = true;
+  for (int i = 0; i < P.n_inst; ++i) {
+    out_host[i].norm = o[i].norm;
+    out_host[i].energy = o[i].energy;
+    out_host[i].mu = o[i].mu;
+    finite = finite && std::isfinite(o[i].norm) && std::isfinite(o[i].energy);
+  }
+  if (!finite) return fail(GPE_ERR_NONFINITE, "observed norm/energy is not finite");
+  return GPE_OK;
+}
+
+// adjoint: loss and knot gradients, fully on the device
+template <typename R>
+gpe_status drive_adjoint(const Ctx& c, const void* psi0, const void* target, const void* field, int64_t nsteps,
+                         int64_t ckpt_every, void* work, void* psi_final) {
+  const int64_t K = ckpt_interval(nsteps, ckpt_every);
+  const int64_t nck = (std::max<int64_t>(nsteps, 1) + K - 1) / K;
+  const size_t st = (size_t)c.P->total * 2 * sizeof(R);
+  Carver cv(work);
+  std::vector<void*> ck(nck), seg(K);
+  for (auto& p : ck) p = cv.take(st);
+  for (auto& p : seg) p = cv.take(st);
+  void* y2 = cv.take(st);
+  void* y3 = cv.take(st);
+  void* y4 = cv.take(st);
+  void* lam = cv.take(st);
+  void* lacc = cv.take(st);
+  void* uA = cv.take(st);
+  void* uB = cv.take(st);
+  void* cur = cv.take(st);
+
+  LTRY(hipMemcpyAsync(cur, psi0, st, hipMemcpyDeviceToDevice, c.s));
+  LTRY(run_set_step(c.pl.step, 0, c.s));
+  for (int64_t n = 0; n < nsteps; ++n) {
+    if (n % K == 0) LTRY(hipMemcpyAsync(ck[n / K], cur, st, hipMemcpyDeviceToDevice, c.s));
+    gpe_status r = rk_step<R>(c, cur, field, y2, y3, y4, cur, false, nullptr);
+    if (r != GPE_OK) return r;
+  }
+  if (psi_final) LTRY(hipMemcpyAsync(psi_final, cur, st, hipMemcpyDeviceToDevice, c.s));
+  LTRY(run_overlap<R>(c.pl, c.cfg, target, cur, c.s));
+  LTRY(run_finalize(c.pl, FIN_OVERLAP, nullptr, c.s));
+  LTRY(run_finalize(c.pl, FIN_LOSS, nullptr, c.s));
+  LTRY(run_seed_lambda<R>(c.pl, c.cfg, target, lam, c.s));
+  LTRY(run_zero_doubles(c.pl.knot_acc, (int64_t)c.cs->n_chunks * GPE_MAX_KNOTS, c.s));
+  for (int64_t m = nck - 1; m >= 0; --m) {
+    const int64_t n0 = m * K, n1 = std::min(n0 + K, nsteps);
+    seg[0] = ck[m];
+    LTRY(run_set_step(c.pl.step, n0, c.s));
+    for (int64_t r = 0; r + 1 < n1 - n0; ++r) {
+      gpe_status q = rk_step<R>(c, seg[r], field, y2, y3, y4, seg[r + 1], false, nullptr);
+      if (q != GPE_OK) return q;
+    }
+    for (int64_t n = n1 - 1; n >= n0; --n) {
+      void* Y1 = seg[n - n0];
+      LTRY(run_set_step(c.pl.step, n, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, false, Y1, Y1, nullptr, nullptr, field, y2, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, Y1, nullptr, nullptr, field, y3, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, Y1, nullptr, nullptr, field, y4, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 4, lam, y4, field, nullptr, lacc, uA, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 3, uA, y3, field, lam, lacc, uB, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 2, uB, y2, field, lam, lacc, uA, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 1, uA, Y1, field, nullptr, lacc, lam, c.s));
+    }
+  }
+  LTRY(run_knot_finalize(c.pl, c.P->d_grads, c.s));
+  return GPE_OK;
+}
+
+gpe_status read_loss_grad(Problem& P, double* loss_host, double* grad_host, int n_knots_single) {
+  std::vector<InstOut> o(P.n_inst);
+  std::vector<double> gr((size_t)P.n_inst * GPE_MAX_KNOTS);
+  HIP_TRY(hipMemcpy(o.data(), P.d_out, sizeof(InstOut) * P.n_inst, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(gr.data(), P.d_grads, sizeof(double) * gr.size(), hipMemcpyDeviceToHost));
+  bool finite = true;
+  for (int i = 0; i < P.n_inst; ++i) {
+    if (loss_host) loss_host[i] = o[i].loss;
+    finite = finite && std::isfinite(o[i].loss);
+  }
+  if (grad_host) {
+    if (n_knots_single > 0) {
+      for (int k = 0; k < n_knots_single; ++k) grad_host[k] = gr[k];
+    } else {
+      std::memcpy(grad_host, gr.data(), sizeof(double) * gr.size());
+    }
+  }
+  if (!finite) return fail(GPE_ERR_NONFINITE, "loss is not finite");
+  return GPE_OK;
+}
+
+// device range of the field -> stability bound for RK4
+template <typename R>
+gpe_status field_vmax(const Ctx& c, const void* field, const std::vector<InstParams>& ps, double* vmax) {
+  LTRY(run_field_range<R>(c.pl, c.cfg, field, c.s));
+  LTRY(run_finalize(c.pl, FIN_RANGE, nullptr, c.s));
+  std::vector<InstOut> o(c.P->n_inst);
+  HIP_TRY(hipMemcpyAsync(o.data(), c.P->d_out, sizeof(InstOut) * c.P->n_inst, hipMemcpyDeviceToHost, c.s));
+  HIP_TRY(hipStreamSynchronize(c.s));
+  double m = 0.0;
+  for (int i = 0; i < c.P->n_inst; ++i) {
+    const InstParams& ip = ps[i];
+    if (ip.pot_kind == GPE_POT_RF_RAMP) {
+      for (int k = 0; k < ip.n_knots; ++k) {
+        const double d = std::max(std::fabs(o[i].fmax - ip.knot_v[k]), std::fabs(o[i].fmin - ip.knot_v[k]));
+        m = std::max(m, std::sqrt(d * d + ip.omega * ip.omega));
+      }
+    } else {
+      m = std::max(m, std::max(std::fabs(o[i].fmin), std::fabs(o[i].fmax)));
+    }
+  }
+  *vmax = m;
+  return GPE_OK;
+}
+
+}  // namespace
+
+template <typename R>
+static gpe_status rt_stability(const Ctx& c, const std::vector<InstParams>& ps, const void* field, double dt_max_g) {
+  double vmax = 0.0;
+  gpe_status st = field_vmax<R>(c, field, ps, &vmax);
+  if (st != GPE_OK) return st;
+  const double lam = kinetic_bound(*c.P) + vmax;
+  if (dt_max_g * lam > 2.0 * std::sqrt(2.0))
+    return fail(GPE_ERR_UNSTABLE, "dt = %g exceeds the RK4 bound 2*sqrt(2)/lambda = %g (lambda = %g)", dt_max_g,
+                2.0 * std::sqrt(2.0) / lam, lam);
+  return GPE_OK;
+}
+
+template <typename R>
+static gpe_status batch_rt_graph(gpe_batch b, const Ctx& c, int dtype, void* psi, const void* field, int64_t nsteps,
+                                 void* work) {
+  Problem& P = *b->prob;
+  Problem::GraphKey key{psi, field, work, dtype, P.config};
+  hipGraphExec_t exec = nullptr;
+  auto it = P.graphs.find(key);
+  if (it != P.graphs.end()) {
+    exec = it->second;
+  } else {
+    Carver cv(work);
+    const size_t st = (size_t)P.total * 2 * sizeof(R);
+    void* y2 = cv.take(st);
+    void* y3 = cv.take(st);
+    void* y4 = cv.take(st);
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    gpe_status r = GPE_OK;
+    if (e == hipSuccess) {
+      Ctx cc = c;
+      cc.s = cap;
+      r = rk_step<R>(cc, psi, field, y2, y3, y4, psi, false, nullptr);
+      hipError_t e2 = hipStreamEndCapture(cap, &graph);
+      if (r == GPE_OK && e2 != hipSuccess) r = hip_fail(e2, "hipStreamEndCapture");
+    } else {
+      r = hip_fail(e, "hipStreamBeginCapture");
+    }
+    if (r == GPE_OK) {
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) r = hip_fail(e, "hipGraphInstantiate");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (r != GPE_OK) return r;
+    P.graphs[key] = exec;
+  }
+  HIP_TRY(run_set_step(c.pl.step, 0, c.s));
+  for (int64_t n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(exec, c.s));
+  return GPE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* gpe_last_error(void) { return t_err.c_str(); }
+int gpe_abi_version(void) { return GPE_ABI_VERSION; }
+
+static gpe_status finish_grid(const gpe_geometry* geom, Layout&& lay, int device, gpe_grid* out) {
+  for (int d = 0; d < 3; ++d) {
+    lay.h[d] = geom->h[d];
+    lay.x0[d] = geom->x0[d];
+  }
+  gpe_grid g = new (std::nothrow) gpe_grid_s();
+  if (!g) return fail(GPE_ERR_ALLOC, "out of host memory");
+  g->lay = std::move(lay);
+  g->device = device;
+  if (device >= 0) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) {
+      delete g;
+      return fail(GPE_ERR_DEVICE, "device %d not available", device);
+    }
+    g->prob.reset(new (std::nothrow) Problem());
+    if (!g->prob) {
+      delete g;
+      return fail(GPE_ERR_ALLOC, "out of host memory");
+    }
+    std::vector<const Layout*> lays{&g->lay};
+    gpe_status st = g->prob->build(device, lays);
+    if (st != GPE_OK) {
+      g->device = -1;
+      delete g;
+      return st;
+    }
+    DeviceGuard dg(device);
+    const Layout& L = g->lay;
+    const int64_t nr = L.n_runs();
+    std::vector<int64_t> base(nr);
+    std::vector<int32_t> start(nr);
+    for (int64_t r = 0; r < nr; ++r) {
+      base[r] = (L.run_i[r] * L.n[1] + L.run_j[r]) * L.n[2] + L.run_k0[r];
+      start[r] = (int32_t)L.run_start[r];
+    }
+    if (dalloc(&g->d_run_base, nr) != hipSuccess || dalloc(&g->d_run_start, nr) != hipSuccess ||
+        hipMemcpy(g->d_run_base, base.data(), sizeof(int64_t) * nr, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g->d_run_start, start.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice) != hipSuccess) {
+      delete g;
+      return fail(GPE_ERR_ALLOC, "run table allocation/upload failed");
+    }
+  }
+  *out = g;
+  return GPE_OK;
+}
+
+static gpe_status check_geom(const gpe_geometry* geom) {
+  if (!geom) return fail(GPE_ERR_ARG, "geometry is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (geom->n[d] < 1) return fail(GPE_ERR_ARG, "geometry: n[%d] must be >= 1", d);
+    if (!(geom->h[d] > 0.0) || !std::isfinite(geom->h[d])) return fail(GPE_ERR_ARG, "geometry: h[%d] must be > 0", d);
+    if (!std::isfinite(geom->x0[d])) return fail(GPE_ERR_ARG, "geometry: x0[%d] must be finite", d);
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_create(const gpe_geometry* geom, const uint8_t* mask_host, int device, gpe_grid* out) {
+  if (!out) return fail(GPE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  gpe_status st = check_geom(geom);
+  if (st != GPE_OK) return st;
+  if (!mask_host) return fail(GPE_ERR_ARG, "mask is NULL");
+  if (device < -1) return fail(GPE_ERR_ARG, "device must be >= -1");
+  Layout lay;
+  std::string err = layout_from_mask(geom->n, mask_host, lay);
+  if (!err.empty()) return fail(GPE_ERR_ARG, "%s", err.c_str());
+  return finish_grid(geom, std::move(lay), device, out);
+}
+
+gpe_status gpe_grid_create_runs(const gpe_geometry* geom, int64_t nruns, const int64_t* runs_host, int device,
+                                gpe_grid* out) {
+  if (!out) return fail(GPE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  gpe_status st = check_geom(geom);
+  if (st != GPE_OK) return st;
+  if (!runs_host || nruns < 1) return fail(GPE_ERR_ARG, "runs must be non-empty");
+  if (device < -1) return fail(GPE_ERR_ARG, "device must be >= -1");
+  Layout lay;
+  std::string err = layout_from_runs(geom->n, nruns, runs_host, lay);
+  if (!err.empty()) return fail(GPE_ERR_ARG, "%s", err.c_str());
+  return finish_grid(geom, std::move(lay), device, out);
+}
+
+gpe_status gpe_grid_info(gpe_grid g, int64_t* n_active, int64_t* n_runs, int64_t* n_segments) {
+  if (!g) return fail(GPE_ERR_ARG, "grid is NULL");
+  if (n_active) *n_active = g->lay.n_active;
+  if (n_runs) *n_runs = g->lay.n_runs();
+  if (n_segments) *n_segments = g->lay.n_segments();
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_segments(gpe_grid g, int32_t* out) {
+  if (!g || !out) return fail(GPE_ERR_ARG, "grid or out is NULL");
+  const Layout& L = g->lay;
+  for (int64_t q = 0; q < L.n_segments(); ++q) {
+    int32_t* o = out + 8 * q;
+    o[0] = L.heads[q].start;
+    o[1] = L.heads[q + 1].start - L.heads[q].start;
+    o[2] = L.heads[q].flags;
+    o[3] = L.nbs[q].xm;
+    o[4] = L.nbs[q].xp;
+    o[5] = L.nbs[q].ym;
+    o[6] = L.nbs[q].yp;
+    o[7] = 0;
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_runs(gpe_grid g, int64_t* out) {
+  if (!g || !out) return fail(GPE_ERR_ARG, "grid or out is NULL");
+  const Layout& L = g->lay;
+  for (int64_t r = 0; r < L.n_runs(); ++r) {
+    out[5 * r] = L.run_i[r];
+    out[5 * r + 1] = L.run_j[r];
+    out[5 * r + 2] = L.run_k0[r];
+    out[5 * r + 3] = L.run_k1[r];
+    out[5 * r + 4] = L.run_start[r];
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_destroy(gpe_grid g) {
+  delete g;
+  return GPE_OK;
+}
+
+gpe_status gpe_work_bytes(gpe_grid g, gpe_dtype dtype, int32_t mode, int64_t nsteps, int64_t ckpt_every,
+                          size_t* bytes) {
+  if (!g || !bytes) return fail(GPE_ERR_ARG, "grid or bytes is NULL");
+  gpe_status st = check_dtype(dtype);
+  if (st != GPE_OK) return st;
+  if (mode < GPE_MODE_ITP || mode > GPE_MODE_ADJ) return fail(GPE_ERR_ARG, "unknown mode");
+  if (nsteps < 0 || ckpt_every < 0) return fail(GPE_ERR_ARG, "nsteps and ckpt_every must be >= 0");
+  *bytes = work_bytes_for(g->lay.n_active, dtype, mode, nsteps, ckpt_every);
+  return GPE_OK;
+}
+
+gpe_status gpe_pack(gpe_grid g, gpe_dtype dtype, const void* box_dev, void* compact_dev, void* stream) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(box_dev, "box");
+  if (st == GPE_OK) st = check_ptr(compact_dev, "compact");
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = dtype == GPE_C128
+                     ? run_pack<double>(g->d_run_base, g->d_run_start, g->lay.n_runs(), g->lay.n_active, box_dev,
+                                        compact_dev, false, s)
+                     : run_pack<float>(g->d_run_base, g->d_run_start, g->lay.n_runs(), g->lay.n_active, box_dev,
+                                       compact_dev, false, s);
+  if (e != hipSuccess) return hip_fail(e, "pack");
+  return GPE_OK;
+}
+
+gpe_status gpe_unpack(gpe_grid g, gpe_dtype dtype, const void* compact_dev, void* box_dev, void* stream) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(box_dev, "box");
+  if (st == GPE_OK) st = check_ptr(compact_dev, "compact");
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t nbox = g->lay.n[0] * g->lay.n[1] * g->lay.n[2];
+  hipError_t e = dtype == GPE_C128 ? run_fill_zero<double>(box_dev, nbox, s) : run_fill_zero<float>(box_dev, nbox, s);
+  if (e == hipSuccess)
+    e = dtype == GPE_C128 ? run_pack<double>(g->d_run_base, g->d_run_start, g->lay.n_runs(), g->lay.n_active,
+                                             compact_dev, box_dev, true, s)
+                          : run_pack<float>(g->d_run_base, g->d_run_start, g->lay.n_runs(), g->lay.n_active,
+                                            compact_dev, box_dev, true, s);
+  if (e != hipSuccess) return hip_fail(e, "unpack");
+  return GPE_OK;
+}
+
+static gpe_status check_work(const void* work, size_t have, size_t need) {
+  if (need > 0) {
+    gpe_status st = check_ptr(work, "work");
+    if (st != GPE_OK) return st;
+  }
+  if (have < need) return fail(GPE_ERR_ARG, "work buffer too small: %zu bytes given, %zu needed", have, need);
+  return GPE_OK;
+}
+
+gpe_status gpe_imag_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
+                         int64_t nsteps, void* work, size_t work_bytes, void* stream, gpe_obs* final_host,
+                         gpe_obs* history_dev) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi, "psi");
+  if (st == GPE_OK) st = check_pot(pot);
+  if (st == GPE_OK) st = check_params(prm);
+  if (st != GPE_OK) return st;
+  if (nsteps < 0) return fail(GPE_ERR_ARG, "nsteps must be >= 0");
+  if (prm->obs_every > 0 && !history_dev) return fail(GPE_ERR_ARG, "obs_every > 0 needs history_dev");
+  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, GPE_MODE_ITP, nsteps, 0));
+  if (st != GPE_OK) return st;
+  if (prm->check_stability) {
+    const double lt = kinetic_bound(*g->prob);
+    if (prm->dt * lt > 4.0)
+      return fail(GPE_ERR_UNSTABLE, "dt = %g exceeds the Euler-substep bound 4/lambda_T = %g", prm->dt, 4.0 / lt);
+  }
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  st = make_ctx(g->prob.get(), g->prob->config, s, c);
+  if (st != GPE_OK) return st;
+  std::vector<InstParams> ps{make_params(pot, prm, 0.0)};
+  st = g->prob->upload(*c.cs, ps, s);
+  if (st != GPE_OK) return st;
+  st = dtype == GPE_C128 ? drive_itp<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev)
+                         : drive_itp<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev);
+  if (st != GPE_OK) return st;
+  if (final_host) {
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false)
+                           : drive_observe<float>(c, psi, pot->field, false);
+    if (st != GPE_OK) return st;
+    return read_obs(*g->prob, final_host, s);
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_real_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
+                         double t0, int64_t nsteps, void* work, size_t work_bytes, void* stream, gpe_obs* final_host,
+                         gpe_obs* history_dev) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi, "psi");
+  if (st == GPE_OK) st = check_pot(pot);
+  if (st == GPE_OK) st = check_params(prm);
+  if (st != GPE_OK) return st;
+  if (!std::isfinite(t0)) return fail(GPE_ERR_ARG, "t0 must be finite");
+  if (nsteps < 0) return fail(GPE_ERR_ARG, "nsteps must be >= 0");
+  if (prm->obs_every > 0 && !history_dev) return fail(GPE_ERR_ARG, "obs_every > 0 needs history_dev");
+  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, GPE_MODE_RT, nsteps, 0));
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  st = make_ctx(g->prob.get(), g->prob->config, s, c);
+  if (st != GPE_OK) return st;
+  std::vector<InstParams> ps{make_params(pot, prm, t0)};
+  st = g->prob->upload(*c.cs, ps, s);
+  if (st != GPE_OK) return st;
+  if (prm->check_stability) {
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, pot->field, prm->dt)
+                           : rt_stability<float>(c, ps, pot->field, prm->dt);
+    if (st != GPE_OK) return st;
+  }
+  st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev)
+                         : drive_rt<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev);
+  if (st != GPE_OK) return st;
+  if (final_host) {
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false)
+                           : drive_observe<float>(c, psi, pot->field, false);
+    if (st != GPE_OK) return st;
+    return read_obs(*g->prob, final_host, s);
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_observe(gpe_grid g, gpe_dtype dtype, const void* psi, const gpe_potential* pot, double t, double gg,
+                       void* stream, gpe_obs* out_host) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi, "psi");
+  if (st == GPE_OK) st = check_pot(pot);
+  if (st != GPE_OK) return st;
+  if (!out_host) return fail(GPE_ERR_ARG, "out_host is NULL");
+  if (!std::isfinite(t) || !std::isfinite(gg)) return fail(GPE_ERR_ARG, "t and g must be finite");
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  st = make_ctx(g->prob.get(), g->prob->config, s, c);
+  if (st != GPE_OK) return st;
+  gpe_params prm;
+  std::memset(&prm, 0, sizeof prm);
+  prm.g = gg;
+  prm.dt = 1.0;
+  std::vector<InstParams> ps{make_params(pot, &prm, t)};
+  st = g->prob->upload(*c.cs, ps, s);
+  if (st != GPE_OK) return st;
+  if (run_set_step(c.pl.step, 0, s) != hipSuccess) return fail(GPE_ERR_DEVICE, "set_step launch failed");
+  st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false)
+                         : drive_observe<float>(c, psi, pot->field, false);
+  if (st != GPE_OK) return st;
+  return read_obs(*g->prob, out_host, s);
+}
+
+gpe_status gpe_overlap(gpe_grid g, gpe_dtype dtype, const void* a, const void* b, void* stream, double* out_host) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(a, "a");
+  if (st == GPE_OK) st = check_ptr(b, "b");
+  if (st != GPE_OK) return st;
+  if (!out_host) return fail(GPE_ERR_ARG, "out_host is NULL");
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  st = make_ctx(g->prob.get(), g->prob->config, s, c);
+  if (st != GPE_OK) return st;
+  std::vector<InstParams> ps{make_params(nullptr, nullptr, 0.0)};
+  st = g->prob->upload(*c.cs, ps, s);
+  if (st != GPE_OK) return st;
+  hipError_t e = dtype == GPE_C128 ? run_overlap<double>(c.pl, c.cfg, a, b, s) : run_overlap<float>(c.pl, c.cfg, a, b, s);
+  if (e == hipSuccess) e = run_finalize(c.pl, FIN_OVERLAP, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "overlap");
+  InstOut o;
+  HIP_TRY(hipMemcpyAsync(&o, g->prob->d_out, sizeof(InstOut), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  out_host[0] = o.ov_re;
+  out_host[1] = o.ov_im;
+  return GPE_OK;
+}
+
+gpe_status gpe_fidelity_grad(gpe_grid g, gpe_dtype dtype, const void* psi0, const void* psi_target,
+                             const gpe_potential* pot, const gpe_params* prm, double t0, int64_t nsteps,
+                             int64_t ckpt_every, void* work, size_t work_bytes, void* stream, double* loss_host,
+                             double* grad_host, void* psi_final) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi0, "psi0");
+  if (st == GPE_OK) st = check_ptr(psi_target, "psi_target");
+  if (st == GPE_OK) st = check_pot(pot);
+  if (st == GPE_OK) st = check_params(prm);
+  if (st != GPE_OK) return st;
+  if (pot->kind != GPE_POT_RF_RAMP) return fail(GPE_ERR_ARG, "fidelity gradient needs an RF_RAMP potential");
+  if (!loss_host || !grad_host) return fail(GPE_ERR_ARG, "loss_host and grad_host are required");
+  if (psi_final) {
+    st = check_ptr(psi_final, "psi_final");
+    if (st != GPE_OK) return st;
+  }
+  if (nsteps < 1 || ckpt_every < 0) return fail(GPE_ERR_ARG, "nsteps must be >= 1 and ckpt_every >= 0");
+  if (!std::isfinite(t0)) return fail(GPE_ERR_ARG, "t0 must be finite");
+  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, GPE_MODE_ADJ, nsteps, ckpt_every));
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  st = make_ctx(g->prob.get(), g->prob->config, s, c);
+  if (st != GPE_OK) return st;
+  std::vector<InstParams> ps{make_params(pot, prm, t0)};
+  st = g->prob->upload(*c.cs, ps, s);
+  if (st != GPE_OK) return st;
+  if (prm->check_stability) {
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, pot->field, prm->dt)
+                           : rt_stability<float>(c, ps, pot->field, prm->dt);
+    if (st != GPE_OK) return st;
+  }
+  st = dtype == GPE_C128 ? drive_adjoint<double>(c, psi0, psi_target, pot->field, nsteps, ckpt_every, work, psi_final)
+                         : drive_adjoint<float>(c, psi0, psi_target, pot->field, nsteps, ckpt_every, work, psi_final);
+  if (st != GPE_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  return read_loss_grad(*g->prob, loss_host, grad_host, pot->n_knots);
+}
+
+// ---- batches --------------------------------------------------------------
+
+gpe_status gpe_batch_create(int32_t n, const gpe_grid* grids, int device, gpe_batch* out) {
+  if (!out) return fail(GPE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || !grids) return fail(GPE_ERR_ARG, "need at least one grid");
+  if (device < 0) return fail(GPE_ERR_ARG, "batch needs a device");
+  std::vector<const Layout*> lays;
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i]) return fail(GPE_ERR_ARG, "grid %d is NULL", i);
+    lays.push_back(&grids[i]->lay);
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return fail(GPE_ERR_DEVICE, "device %d not available", device);
+  gpe_batch b = new (std::nothrow) gpe_batch_s();
+  if (!b) return fail(GPE_ERR_ALLOC, "out of host memory");
+  b->grids.assign(grids, grids + n);
+  b->device = device;
+  b->prob.reset(new (std::nothrow) Problem());
+  if (!b->prob) {
+    delete b;
+    return fail(GPE_ERR_ALLOC, "out of host memory");
+  }
+  gpe_status st = b->prob->build(device, lays);
+  if (st != GPE_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return GPE_OK;
+}
+
+gpe_status gpe_batch_offsets(gpe_batch b, int64_t* offsets) {
+  if (!b || !offsets) return fail(GPE_ERR_ARG, "batch or offsets is NULL");
+  for (int i = 0; i <= b->prob->n_inst; ++i) offsets[i] = b->prob->inst_site[i];
+  return GPE_OK;
+}
+
+gpe_status gpe_batch_destroy(gpe_batch b) {
+  delete b;
+  return GPE_OK;
+}
+
+gpe_status gpe_batch_work_bytes(gpe_batch b, gpe_dtype dtype, int32_t mode, int64_t nsteps, int64_t ckpt_every,
+                                size_t* bytes) {
+  if (!b || !bytes) return fail(GPE_ERR_ARG, "batch or bytes is NULL");
+  gpe_status st = check_dtype(dtype);
+  if (st != GPE_OK) return st;
+  if (mode < GPE_MODE_ITP || mode > GPE_MODE_ADJ) return fail(GPE_ERR_ARG, "unknown mode");
+  if (nsteps < 0 || ckpt_every < 0) return fail(GPE_ERR_ARG, "nsteps and ckpt_every must be >= 0");
+  *bytes = work_bytes_for(b->prob->total, dtype, mode, nsteps, ckpt_every);
+  return GPE_OK;
+}
+
+static gpe_status batch_params(gpe_batch b, const gpe_ramp* ramps, const gpe_params* prms, double t0,
+                               std::vector<InstParams>& ps) {
+  if (!ramps || !prms) return fail(GPE_ERR_ARG, "ramps and params are required");
+  const int n = b->prob->n_inst;
+  ps.resize(n);
+  for (int i = 0; i < n; ++i) {
+    gpe_status st = check_params(&prms[i]);
+    if (st != GPE_OK) return st;
+    st = check_knots(ramps[i].n_knots, ramps[i].knot_t, ramps[i].knot_delta, "ramp");
+    if (st != GPE_OK) return st;
+    if (!std::isfinite(ramps[i].omega)) return fail(GPE_ERR_ARG, "ramp %d: omega must be finite", i);
+    gpe_potential pot;
+    pot.kind = GPE_POT_RF_RAMP;
+    pot.n_knots = ramps[i].n_knots;
+    pot.field = nullptr;
+    pot.omega = ramps[i].omega;
+    pot.knot_t = ramps[i].knot_t;
+    pot.knot_delta = ramps[i].knot_delta;
+    ps[i] = make_params(&pot, &prms[i], t0);
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_batch_real_time(gpe_batch b, gpe_dtype dtype, void* psi, const void* field, const gpe_ramp* ramps,
+                               const gpe_params* prms, double t0, int64_t nsteps, int32_t use_graph, void* work,
+                               size_t work_bytes, void* stream, gpe_obs* final_host) {
+  if (!b) return fail(GPE_ERR_ARG, "batch is NULL");
+  gpe_status st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi, "psi");
+  if (st == GPE_OK) st = check_ptr(field, "field");
+  if (st != GPE_OK) return st;
+  if (nsteps < 0 || !std::isfinite(t0)) return fail(GPE_ERR_ARG, "nsteps must be >= 0 and t0 finite");
+  std::vector<InstParams> ps;
+  st = batch_params(b, ramps, prms, t0, ps);
+  if (st != GPE_OK) return st;
+  st = check_work(work, work_bytes, work_bytes_for(b->prob->total, dtype, GPE_MODE_RT, nsteps, 0));
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  st = make_ctx(b->prob.get(), b->prob->config, s, c);
+  if (st != GPE_OK) return st;
+  st = b->prob->upload(*c.cs, ps, s);
+  if (st != GPE_OK) return st;
+  bool check = false;
+  double dtmax = 0.0;
+  for (auto& p : ps) dtmax = std::max(dtmax, p.dt);
+  for (int i = 0; i < b->prob->n_inst; ++i) check = check || prms[i].check_stability;
+  if (check) {
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, field, dtmax) : rt_stability<float>(c, ps, field, dtmax);
+    if (st != GPE_OK) return st;
+  }
+  if (use_graph) {
+    st = dtype == GPE_C128 ? batch_rt_graph<double>(b, c, dtype, psi, field, nsteps, work)
+                           : batch_rt_graph<float>(b, c, dtype, psi, field, nsteps, work);
+  } else {
+    st = dtype == GPE_C128 ? drive_rt<double>(c, psi, field, nsteps, work, 0, nullptr)
+                           : drive_rt<float>(c, psi, field, nsteps, work, 0, nullptr);
+  }
+  if (st != GPE_OK) return st;
+  if (final_host) {
+    // observation at the final time: the step counter now equals nsteps
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, field, false) : drive_observe<float>(c, psi, field, false);
+    if (st != GPE_OK) return st;
+    return read_obs(*b->prob, final_host, s);
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi0, const void* psi_target,
+                                   const void* field, const gpe_ramp* ramps, const gpe_params* prms, double t0,
+                                   int64_t nsteps, int64_t ckpt_every, int32_t use_graph, void* work,
+                                   size_t work_bytes, void* stream, double* loss_host, double* grad_host) {
+  (void)use_graph;
+  if (!b) return fail(GPE_ERR_ARG, "batch is NULL");
+  gpe_status st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi0, "psi0");
+  if (st == GPE_OK) st = check_ptr(psi_target, "psi_target");
+  if (st == GPE_OK) st = check_ptr(field, "field");
+  if (st != GPE_OK) return st;
+  if (!loss_host || !grad_host) return fail(GPE_ERR_ARG, "loss_host and grad_host are required");
+  if (nsteps < 1 || ckpt_every < 0 || !std::isfinite(t0)) return fail(GPE_ERR_ARG, "bad nsteps/ckpt_every/t0");
+  std::vector<InstParams> ps;
+  st = batch_params(b, ramps, prms, t0, ps);
+  if (st != GPE_OK) return st;
+  st = check_work(work, work_bytes, work_bytes_for(b->prob->total, dtype, GPE_MODE_ADJ, nsteps, ckpt_every));
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  st = make_ctx(b->prob.get(), b->prob->config, s, c);
+  if (st != GPE_OK) return st;
+  st = b->prob->upload(*c.cs, ps, s);
+  if (st != GPE_OK) return st;
+  st = dtype == GPE_C128 ? drive_adjoint<double>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr)
+                         : drive_adjoint<float>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr);
+  if (st != GPE_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  return read_loss_grad(*b->prob, loss_host, grad_host, 0);
+}
+
+// ---- launch configuration -------------------------------------------------
+
+int32_t gpe_config_count(void) { return config_count(); }
+
+gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* spt, int32_t* xcd) {
+  if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
+  LaunchConfig c = config_get(config);
+  if (block) *block = c.block;
+  if (spt) *spt = c.spt;
+  if (xcd) *xcd = c.xcd;
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_set_config(gpe_grid g, int32_t config) {
+  gpe_status st = check_grid(g);
+  if (st != GPE_OK) return st;
+  if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
+  g->prob->config = config;
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_get_config(gpe_grid g, int32_t* config) {
+  gpe_status st = check_grid(g);
+  if (st != GPE_OK) return st;
+  if (!config) return fail(GPE_ERR_ARG, "config is NULL");
+  *config = g->prob->config;
+  return GPE_OK;
+}
+
+gpe_status gpe_batch_set_config(gpe_batch b, int32_t config) {
+  if (!b) return fail(GPE_ERR_ARG, "batch is NULL");
+  if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
+  b->prob->config = config;
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
+                             int32_t reps, void* work, size_t work_bytes, void* stream, int32_t* best_config,
+                             double* times_ms) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi, "psi");
+  if (st == GPE_OK) st = check_pot(pot);
+  if (st == GPE_OK) st = check_params(prm);
+  if (st != GPE_OK) return st;
+  if (reps < 1) return fail(GPE_ERR_ARG, "reps must be >= 1");
+  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, GPE_MODE_RT, reps, 0));
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int prev = g->prob->config;
+  double best = 1e300;
+  int bi = prev;
+  for (int k = 0; k < config_count(); ++k) {
+    Ctx c;
+    st = make_ctx(g->prob.get(), k, s, c);
+    if (st != GPE_OK) break;
+    std::vector<InstParams> ps{make_params(pot, prm, 0.0)};
+    st = g->prob->upload(*c.cs, ps, s);
+    if (st != GPE_OK) break;
+    // one untimed step, then `reps` timed steps
+    st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, 1, work, 0, nullptr)
+                           : drive_rt<float>(c, psi, pot->field, 1, work, 0, nullptr);
+    if (st != GPE_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(GPE_ERR_DEVICE, "hipEventRecord"); break; }
+    st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, reps, work, 0, nullptr)
+                           : drive_rt<float>(c, psi, pot->field, reps, work, 0, nullptr);
+    if (st != GPE_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(GPE_ERR_DEVICE, "event timing failed");
+      break;
+    }
+    const double per = ms / reps;
+    if (times_ms) times_ms[k] = per;
+    if (per < best) {
+      best = per;
+      bi = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GPE_OK) {
+    g->prob->config = prev;
+    return st;
+  }
+  g->prob->config = bi;
+  if (best_config) *best_config = bi;
+  return GPE_OK;
+}
+
+// ---- timing ---------------------------------------------------------------
+
+gpe_status gpe_timing_enable(int32_t enable) {
+  g_tim.enabled = enable != 0;
+  return GPE_OK;
+}
+
+gpe_status gpe_timing_reset(void) {
+  resolve_pending(0);
+  for (int f = 0; f < FAM_COUNT; ++f) {
+    g_tim.launches[f] = 0;
+    g_tim.ms[f] = 0.0;
+  }
+  return GPE_OK;
+}
+
+int32_t gpe_timing_count(void) { return FAM_COUNT; }
+
+const char* gpe_timing_name(int32_t f) { return family_name(f); }
+
+gpe_status gpe_timing_read(int32_t f, int64_t* launches, double* total_ms) {
+  if (f < 0 || f >= FAM_COUNT) return fail(GPE_ERR_ARG, "family out of range");
+  resolve_pending(0);
+  if (launches) *launches = g_tim.launches[f];
+  if (total_ms) *total_ms = g_tim.ms[f];
+  return GPE_OK;
+}
+
+}  // extern "C"

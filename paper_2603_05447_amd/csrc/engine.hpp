@@ -1,0 +1,135 @@
+// Internal interface between the C ABI layer (abi.hip) and the kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/gpe.h"
+#include "geometry.hpp"
+
+namespace gpe {
+
+// One workgroup processes one chunk: a contiguous range of compact sites
+// of a single instance, plus the segment descriptors overlapping it.
+struct Chunk {
+  int32_t site_begin;   // global compact index of the first site
+  int32_t count;        // number of sites (<= chunk capacity)
+  int32_t seg_begin;    // global index of the segment holding site_begin
+  int32_t seg_count;    // segments overlapping the chunk
+  int32_t inst;         // instance
+  int32_t pad[3];
+};
+
+// Per-instance constants, in device memory (read by every workgroup).
+struct InstParams {
+  double g, dt, t0, dV;
+  // T~ y = cx (y[i-1] + y[i+1]) + cy (y[j-1] + y[j+1]) + cz (y[k-1] + y[k+1]) + cd y,
+  // cx = -1/(2 hx^2), ..., cd = 1/hx^2 + 1/hy^2 + 1/hz^2   (App. B, eq. (B1), hbar = m = 1)
+  double cx, cy, cz, cd;
+  double omega, norm_target;
+  int32_t pot_kind, n_knots;
+  int32_t chunk_begin, chunk_count;
+  int64_t site_begin, n_sites;
+  double knot_t[GPE_MAX_KNOTS];
+  double knot_v[GPE_MAX_KNOTS];
+};
+
+// Per-instance results written by the finalize kernels.
+struct InstOut {
+  double scale;          // renormalisation factor for the next imaginary-time step
+  double norm, energy, mu;
+  double ov_re, ov_im;   // overlap <a|b>
+  double loss;
+  double fmin, fmax;     // range of the potential field
+  double pad[7];
+};
+
+enum { NPART = 4 };       // partial sums per chunk
+
+struct Plan {
+  const SegHead* heads;   // segment heads (global, +1 sentinel)
+  const SegNb* nbs;       // segment lateral offsets
+  const Chunk* chunks;
+  const InstParams* inst;
+  double* partials;       // n_chunks * NPART
+  double* knot_acc;       // n_chunks * GPE_MAX_KNOTS
+  InstOut* out;           // n_inst
+  int64_t* step;          // device step counter
+  int32_t n_chunks;
+  int32_t n_inst;
+  int32_t xcd_map;        // 1: give each XCD a contiguous range of chunks
+  int32_t pad;
+};
+
+// Compiled launch variants (workgroup size x sites per lane, chunk capacity
+// = product) and the XCD mapping flag.
+struct LaunchConfig {
+  int block;
+  int spt;
+  int xcd;
+};
+int config_count();
+LaunchConfig config_get(int i);
+inline int chunk_capacity(const LaunchConfig& c) { return c.block * c.spt; }
+
+// Kernel families (for per-kernel timing).
+enum Family {
+  FAM_ITP1 = 0, FAM_ITP2, FAM_RK1, FAM_RK2, FAM_RK3, FAM_RK4, FAM_OBSERVE,
+  FAM_ADJ1, FAM_ADJ2, FAM_ADJ3, FAM_ADJ4, FAM_FINALIZE, FAM_POINTWISE, FAM_COUNT
+};
+const char* family_name(int f);
+
+// ---- launchers (kernels.hip) -------------------------------------------
+// All return hipSuccess or the launch error.  `cfg` selects the variant.
+// R = double (complex128) or float (complex64).
+template <typename R> hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw,
+                                               const void* prop, void* tmp, hipStream_t s);
+template <typename R> hipError_t run_itp_pass2(const Plan& p, const LaunchConfig& cfg, const void* tmp,
+                                               const void* prop, void* psi_raw, hipStream_t s);
+// stage 1..4 of the memory-optimised RK4 step; Y = stencil input, y0 = step start,
+// y2/y3 read by stage 4, out = output (stage 4: may equal y0).  obs: stage 1 also
+// writes observation partials of y0.
+template <typename R> hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool obs,
+                                              const void* Y, const void* y0, const void* y2, const void* y3,
+                                              const void* field, void* out, hipStream_t s);
+// observation partials (|psi|^2, Re psi^H T psi, V|psi|^2, |psi|^4) of scale*psi
+template <typename R> hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi,
+                                             const void* field, double t_offset_steps, bool use_scale,
+                                             hipStream_t s);
+// adjoint stage (4..1): X = stencil input (lambda for stage 4, else u_i), Y = forward
+// stage state, lam = lambda (site), lacc = running lambda, uout = next u / new lambda
+template <typename R> hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, const void* X,
+                                               const void* Y, const void* field, const void* lam, void* lacc,
+                                               void* uout, hipStream_t s);
+
+// pointwise helpers (chunk-parallel, one launch each)
+template <typename R> hipError_t run_make_prop(const Plan& p, const LaunchConfig& cfg, const void* field,
+                                               void* prop, hipStream_t s);
+template <typename R> hipError_t run_apply_scale(const Plan& p, const LaunchConfig& cfg, void* psi,
+                                                 hipStream_t s);
+template <typename R> hipError_t run_overlap(const Plan& p, const LaunchConfig& cfg, const void* a,
+                                             const void* b, hipStream_t s);
+template <typename R> hipError_t run_seed_lambda(const Plan& p, const LaunchConfig& cfg, const void* target,
+                                                 void* lam, hipStream_t s);
+template <typename R> hipError_t run_field_range(const Plan& p, const LaunchConfig& cfg, const void* field,
+                                                 hipStream_t s);
+template <typename R> hipError_t run_pack(const int64_t* run_base, const int32_t* run_start, int64_t nruns,
+                                          int64_t n_active, const void* src, void* dst, bool to_box,
+                                          hipStream_t s);
+template <typename R> hipError_t run_fill_zero(void* dst, int64_t n_complex, hipStream_t s);
+
+// finalize kinds
+enum FinalKind { FIN_NORM_SCALE = 0, FIN_OBS = 1, FIN_OVERLAP = 2, FIN_LOSS = 3, FIN_RANGE = 4 };
+hipError_t run_finalize(const Plan& p, int kind, gpe_obs* obs_dev, hipStream_t s);
+hipError_t run_knot_finalize(const Plan& p, double* grads_dev /* n_inst * GPE_MAX_KNOTS */, hipStream_t s);
+hipError_t run_zero_doubles(double* p, int64_t n, hipStream_t s);
+hipError_t run_set_scale_one(const Plan& p, hipStream_t s);
+hipError_t run_set_step(int64_t* step, int64_t value, hipStream_t s);
+hipError_t run_tick(int64_t* step, int64_t delta, hipStream_t s);
+
+// timing hooks (abi.hip): bracket a launch with events when enabled
+void timing_before(int family, hipStream_t s);
+void timing_after(int family, hipStream_t s);
+
+}  // namespace gpe

@@ -1,0 +1,823 @@
+// HIP kernels for gfx950 (MI355X): one time step of the Gross-Pitaevskii
+// equation on the compacted active sites of a masked Cartesian grid.
+//
+// Work decomposition.  The compact arrays (one entry per active site, box
+// order with z fastest) are cut into chunks of `block * spt` consecutive
+// sites; one workgroup handles one chunk.  Every pass streams its inputs
+// from HBM once per site with coalesced loads:
+//   * the chunk's own values plus one site on either side (the k-1 / k+1
+//     neighbours along the z-runs) are staged in LDS;
+//   * the heads of the segments overlapping the chunk are staged in LDS and
+//     each lane finds its segment by a fixed-length binary search;
+//   * the four lateral neighbours (i+-1, j+-1) are read from global memory
+//     at the segment's constant offset; adjacent lanes read adjacent
+//     addresses, and those planes were (or will be) streamed as some other
+//     chunk's centre, so they are served from L2.  Chunks are handed to
+//     workgroups so that each XCD (own L2) walks one contiguous eighth of the
+//     array, which keeps the i-1 / i+1 planes inside the same L2.
+// The path is bandwidth bound (a 7-point stencil plus pointwise work), so
+// no matrix cores are used.  Reductions (norm, energy, overlaps, knot
+// gradients) accumulate in FP64 per lane, are reduced across the wavefront
+// with shuffles, and written as one partial per chunk; a finalize kernel
+// sums the partials of each instance in a fixed order, so results are
+// bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+
+namespace gpe {
+
+template <typename R> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+
+template <typename R> __device__ __forceinline__ typename CT<R>::T cmk(R a, R b) {
+  typename CT<R>::T v;
+  v.x = a;
+  v.y = b;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// launch variants
+// ---------------------------------------------------------------------------
+static const LaunchConfig kConfigs[] = {
+    {256, 2, 1}, {256, 1, 1}, {256, 4, 1}, {512, 1, 1}, {512, 2, 1}, {1024, 1, 1}, {256, 2, 0}, {512, 2, 0},
+};
+int config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
+LaunchConfig config_get(int i) { return kConfigs[i]; }
+
+const char* family_name(int f) {
+  static const char* names[FAM_COUNT] = {"itp_pass1", "itp_pass2", "rk_stage1", "rk_stage2", "rk_stage3",
+                                         "rk_stage4", "observe",   "adj_stage1", "adj_stage2", "adj_stage3",
+                                         "adj_stage4", "finalize", "pointwise"};
+  return (f >= 0 && f < FAM_COUNT) ? names[f] : "?";
+}
+
+// Workgroup b runs on XCD b % 8 (round-robin dispatch).  With xcd != 0 the
+// chunk handed to it makes XCD x own chunks [base_x, base_x + cnt_x).
+__device__ __forceinline__ int chunk_index(int b, int G, int xcd) {
+  if (!xcd) return b;
+  const int q = G >> 3, r = G & 7;
+  const int x = b & 7, w = b >> 3;
+  return x * q + (x < r ? x : r) + w;
+}
+
+// piecewise-linear Delta(t), constant outside the knots
+__device__ __forceinline__ double delta_at(const InstParams& ip, double t) {
+  const int n = ip.n_knots;
+  if (n <= 1 || t <= ip.knot_t[0]) return ip.knot_v[0];
+  if (t >= ip.knot_t[n - 1]) return ip.knot_v[n - 1];
+  int k = 0;
+  while (k + 2 < n && ip.knot_t[k + 1] <= t) ++k;
+  return ip.knot_v[k] + (ip.knot_v[k + 1] - ip.knot_v[k]) * (t - ip.knot_t[k]) / (ip.knot_t[k + 1] - ip.knot_t[k]);
+}
+
+template <typename R>
+__device__ __forceinline__ R potential(int kind, R u, R delta, R omega2) {
+  if (kind == GPE_POT_RF_RAMP) {
+    const R d = u - delta;
+    return sqrt(d * d + omega2);
+  }
+  return u;
+}
+
+// dV/dDelta of the RF-dressed potential
+template <typename R>
+__device__ __forceinline__ R dpot_ddelta(int kind, R u, R delta, R omega2) {
+  if (kind == GPE_POT_RF_RAMP) {
+    const R d = u - delta;
+    return -d / sqrt(d * d + omega2);
+  }
+  return R(0);
+}
+
+// Sum NR doubles over the workgroup; thread 0 gets the result.
+template <int BLOCK, int NR>
+__device__ __forceinline__ void block_sum(double (&v)[NR], double (*red)[NR]) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[wid][r] = v[r];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double s = 0.0;
+      for (int w = 0; w < BLOCK / 64; ++w) s += red[w][r];
+      v[r] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stencil passes
+// ---------------------------------------------------------------------------
+enum PassOp {
+  OP_ITP1 = 0,   // phi = s psi P (1 - g|s psi|^2 dt/2) on load;  out = phi - dt/2 T phi
+  OP_ITP2,       // chi' = chi - dt/2 T chi;  out = chi' P (1 - g|chi'|^2 dt/2);  partial |out|^2
+  OP_RK1,        // out = y0 + dt/2 f(t, y0)             (Y = y0)
+  OP_RK1_OBS,    // same, plus observation partials of y0
+  OP_RK2,        // out = y0 + dt/2 f(t + dt/2, Y)
+  OP_RK3,        // out = y0 + dt   f(t + dt/2, Y)
+  OP_RK4,        // out = -y0/3 + y2/3 + 2 y3/3 + Y/3 + dt/6 f(t + dt, Y)
+  OP_OBS,        // observation partials of (scale) Y
+  OP_ADJ4,       // adjoint stages (see run_adj_stage)
+  OP_ADJ3,
+  OP_ADJ2,
+  OP_ADJ1,
+};
+
+template <typename R> struct PassArgs {
+  using C = typename CT<R>::T;
+  const C* Y;       // stencil input
+  const C* a;       // RK: y0; ADJ: forward stage state; ITP: unused
+  const C* b;       // RK4: y2; ADJ: lambda at the site
+  const C* c;       // RK4: y3
+  const R* field;   // V (static) or U (RF)
+  const R* prop;    // ITP: exp(-V dt/2)
+  C* out;
+  C* out2;          // ADJ: running lambda (in/out)
+  double c_stage;   // stage time offset in units of dt
+  int use_scale;    // OBS: multiply Y by the instance's scale
+};
+
+template <typename R, int BLOCK, int SPT, int OP>
+__global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
+  using C = typename CT<R>::T;
+  constexpr int CH = BLOCK * SPT;
+  constexpr bool ITP = (OP == OP_ITP1 || OP == OP_ITP2);
+  constexpr bool ADJ = (OP >= OP_ADJ4);
+  constexpr bool OBSP = (OP == OP_RK1_OBS || OP == OP_OBS);
+  constexpr int NR = OBSP ? 4 : ((OP == OP_ITP2 || ADJ) ? 1 : 0);
+  __shared__ C sy[CH + 2];
+  __shared__ SegHead sh[CH + 1];
+  __shared__ double red[BLOCK / 64][NR > 0 ? NR : 1];
+
+  const int cidx = chunk_index((int)blockIdx.x, (int)gridDim.x, pl.xcd_map);
+  const Chunk ch = pl.chunks[cidx];
+  const InstParams& ip = pl.inst[ch.inst];
+  const int64_t ib = ip.site_begin, ie = ip.site_begin + ip.n_sites;
+
+  const R g = (R)ip.g, dt = (R)ip.dt;
+  const R cx = (R)ip.cx, cy = (R)ip.cy, cz = (R)ip.cz, cd = (R)ip.cd;
+  const int kind = ip.pot_kind;
+  const R omega2 = (R)(ip.omega * ip.omega);
+  const double tstage = ip.t0 + ((double)(*pl.step) + a.c_stage) * ip.dt;
+  const R delta = (kind == GPE_POT_RF_RAMP) ? (R)delta_at(ip, tstage) : R(0);
+  R scale = R(1);
+  if (OP == OP_ITP1 || (OP == OP_OBS && a.use_scale)) scale = (R)pl.out[ch.inst].scale;
+  const R hg = g * dt * R(0.5);
+
+  // value of the stencil input at compact site s (ITP1 applies the diagonal half-step on load)
+  auto load = [&](int64_t s) -> C {
+    C v = a.Y[s];
+    if (OP == OP_ITP1) {
+      const R p = a.prop[s];
+      const R vr = v.x * scale, vi = v.y * scale;
+      const R f = p * (R(1) - hg * (vr * vr + vi * vi));
+      v = cmk<R>(vr * f, vi * f);
+    } else if (OP == OP_OBS) {
+      v = cmk<R>(v.x * scale, v.y * scale);
+    }
+    return v;
+  };
+
+  for (int t = threadIdx.x; t <= ch.seg_count; t += BLOCK) sh[t] = pl.heads[ch.seg_begin + t];
+  for (int t = threadIdx.x; t < ch.count + 2; t += BLOCK) {
+    const int64_t s = (int64_t)ch.site_begin - 1 + t;
+    sy[t] = (s >= ib && s < ie) ? load(s) : cmk<R>(R(0), R(0));
+  }
+  __syncthreads();
+
+  const int nseg = ch.seg_count;
+  const int top = nseg > 1 ? (1 << (31 - __clz(nseg - 1))) : 0;
+  double acc[NR > 0 ? NR : 1];
+#pragma unroll
+  for (int r = 0; r < (NR > 0 ? NR : 1); ++r) acc[r] = 0.0;
+
+#pragma unroll
+  for (int m = 0; m < SPT; ++m) {
+    const int l = threadIdx.x + m * BLOCK;
+    if (l < ch.count) {
+      const int s = ch.site_begin + l;
+      int j = 0;
+      for (int st = top; st > 0; st >>= 1) {
+        const int cand = j + st;
+        if (cand < nseg && sh[cand].start <= s) j = cand;
+      }
+      const SegHead hd = sh[j];
+      const int send = sh[j + 1].start;
+      const SegNb nb = pl.nbs[ch.seg_begin + j];
+      const C zero = cmk<R>(R(0), R(0));
+      const C yc = sy[l + 1];
+      const C zm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? zero : sy[l];
+      const C zp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? zero : sy[l + 2];
+      const C xm = nb.xm ? load((int64_t)s + nb.xm) : zero;
+      const C xp = nb.xp ? load((int64_t)s + nb.xp) : zero;
+      const C ym = nb.ym ? load((int64_t)s + nb.ym) : zero;
+      const C yp = nb.yp ? load((int64_t)s + nb.yp) : zero;
+      // T~ y at s
+      const R lr = cx * (xm.x + xp.x) + cy * (ym.x + yp.x) + cz * (zm.x + zp.x) + cd * yc.x;
+      const R li = cx * (xm.y + xp.y) + cy * (ym.y + yp.y) + cz * (zm.y + zp.y) + cd * yc.y;
+
+      if constexpr (OP == OP_ITP1) {
+        a.out[s] = cmk<R>(yc.x - R(0.5) * dt * lr, yc.y - R(0.5) * dt * li);
+      } else if constexpr (OP == OP_ITP2) {
+        const R qr = yc.x - R(0.5) * dt * lr, qi = yc.y - R(0.5) * dt * li;
+        const R f = a.prop[s] * (R(1) - hg * (qr * qr + qi * qi));
+        const R wr = qr * f, wi = qi * f;
+        a.out[s] = cmk<R>(wr, wi);
+        acc[0] += (double)wr * (double)wr + (double)wi * (double)wi;
+      } else if constexpr (OP == OP_OBS) {
+        const R V = potential<R>(kind, a.field[s], delta, omega2);
+        const double d = (double)yc.x * (double)yc.x + (double)yc.y * (double)yc.y;
+        acc[0] += d;
+        acc[1] += (double)yc.x * (double)lr + (double)yc.y * (double)li;
+        acc[2] += (double)V * d;
+        acc[3] += d * d;
+      } else if constexpr (OP >= OP_RK1 && OP <= OP_RK4) {
+        const R V = potential<R>(kind, a.field[s], delta, omega2);
+        const R dens = yc.x * yc.x + yc.y * yc.y;
+        const R w = V + g * dens;
+        const R hr = lr + w * yc.x, hi = li + w * yc.y;   // H y
+        const R fr = hi, fi = -hr;                         // f = -i H y
+        if constexpr (OP == OP_RK1 || OP == OP_RK1_OBS) {
+          a.out[s] = cmk<R>(yc.x + R(0.5) * dt * fr, yc.y + R(0.5) * dt * fi);
+          if constexpr (OP == OP_RK1_OBS) {
+            const double d = (double)dens;
+            acc[0] += d;
+            acc[1] += (double)yc.x * (double)lr + (double)yc.y * (double)li;
+            acc[2] += (double)V * d;
+            acc[3] += d * d;
+          }
+        } else if constexpr (OP == OP_RK2 || OP == OP_RK3) {
+          const C y0 = a.a[s];
+          const R cc = (OP == OP_RK2) ? R(0.5) * dt : dt;
+          a.out[s] = cmk<R>(y0.x + cc * fr, y0.y + cc * fi);
+        } else {
+          const C y0 = a.a[s], y2 = a.b[s], y3 = a.c[s];
+          const R third = R(1) / R(3), c6 = dt / R(6);
+          const R orr = third * (y2.x - y0.x + yc.x) + R(2) * third * y3.x + c6 * fr;
+          const R oi = third * (y2.y - y0.y + yc.y) + R(2) * third * y3.y + c6 * fi;
+          a.out[s] = cmk<R>(orr, oi);
+        }
+      } else if constexpr (ADJ) {
+        // u = f X, T u = f T X  (stage 4: X = lambda, f = b_4 = 1/6)
+        const R fx = (OP == OP_ADJ4) ? R(1) / R(6) : R(1);
+        const R ur = fx * yc.x, ui = fx * yc.y;
+        const R tur = fx * lr, tui = fx * li;
+        const C Y = a.a[s];
+        const R u0 = a.field[s];
+        const R V = potential<R>(kind, u0, delta, omega2);
+        const R dVd = dpot_ddelta<R>(kind, u0, delta, omega2);
+        const R d2 = Y.x * Y.x + Y.y * Y.y;
+        const R w = V + R(2) * g * d2;
+        // A = T u + (V + 2 g |Y|^2) u ;  B = g Y^2 conj(u)
+        const R Ar = tur + w * ur, Ai = tui + w * ui;
+        const R y2r = Y.x * Y.x - Y.y * Y.y, y2i = R(2) * Y.x * Y.y;
+        const R Br = g * (y2r * ur + y2i * ui), Bi = g * (y2i * ur - y2r * ui);
+        // theta = dt i (A - B)
+        const R thr = -dt * (Ai - Bi), thi = dt * (Ar - Br);
+        acc[0] += (double)dVd * ((double)ur * (double)Y.y - (double)ui * (double)Y.x);
+        if constexpr (OP == OP_ADJ4) {
+          // lambda = X;  u_3 = lambda/3 + theta_4;  running lambda = lambda + theta_4
+          const R third = R(1) / R(3);
+          a.out[s] = cmk<R>(third * yc.x + thr, third * yc.y + thi);
+          a.out2[s] = cmk<R>(yc.x + thr, yc.y + thi);
+        } else if constexpr (OP == OP_ADJ3 || OP == OP_ADJ2) {
+          const C lam = a.b[s];
+          const C lacc = a.out2[s];
+          const R bl = (OP == OP_ADJ3) ? R(1) / R(3) : R(1) / R(6);
+          a.out[s] = cmk<R>(bl * lam.x + R(0.5) * thr, bl * lam.y + R(0.5) * thi);
+          a.out2[s] = cmk<R>(lacc.x + thr, lacc.y + thi);
+        } else {
+          const C lacc = a.out2[s];
+          a.out[s] = cmk<R>(lacc.x + thr, lacc.y + thi);
+        }
+      }
+    }
+  }
+
+  if constexpr (NR > 0) {
+    block_sum<BLOCK, (NR > 0 ? NR : 1)>(acc, red);
+    if (threadIdx.x == 0) {
+      if constexpr (ADJ) {
+        // dL/dDelta_k += dt * phi_k(t_i) * q  (hat functions of the ramp knots)
+        if (kind == GPE_POT_RF_RAMP) {
+          const int n = ip.n_knots;
+          const double q = ip.dt * acc[0];
+          double* ka = pl.knot_acc + (size_t)cidx * GPE_MAX_KNOTS;
+          if (n <= 1 || tstage <= ip.knot_t[0]) {
+            ka[0] += q;
+          } else if (tstage >= ip.knot_t[n - 1]) {
+            ka[n - 1] += q;
+          } else {
+            int k = 0;
+            while (k + 2 < n && ip.knot_t[k + 1] <= tstage) ++k;
+            const double lam = (tstage - ip.knot_t[k]) / (ip.knot_t[k + 1] - ip.knot_t[k]);
+            ka[k] += (1.0 - lam) * q;
+            ka[k + 1] += lam * q;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pl.partials[(size_t)cidx * NPART + r] = acc[r];
+      }
+    }
+  }
+}
+
+template <int BLOCK, int SPT, typename R, int OP>
+static hipError_t launch_pass(const Plan& p, const PassArgs<R>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP>), dim3(p.n_chunks), dim3(BLOCK), 0, s, p, a);
+  return hipGetLastError();
+}
+
+template <typename R, int OP>
+static hipError_t dispatch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
+  if (p.n_chunks <= 0) return hipSuccess;
+  if (cfg.block == 256 && cfg.spt == 1) return launch_pass<256, 1, R, OP>(p, a, s);
+  if (cfg.block == 256 && cfg.spt == 2) return launch_pass<256, 2, R, OP>(p, a, s);
+  if (cfg.block == 256 && cfg.spt == 4) return launch_pass<256, 4, R, OP>(p, a, s);
+  if (cfg.block == 512 && cfg.spt == 1) return launch_pass<512, 1, R, OP>(p, a, s);
+  if (cfg.block == 512 && cfg.spt == 2) return launch_pass<512, 2, R, OP>(p, a, s);
+  if (cfg.block == 1024 && cfg.spt == 1) return launch_pass<1024, 1, R, OP>(p, a, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+static PassArgs<R> pass_args() {
+  PassArgs<R> a;
+  a.Y = a.a = a.b = a.c = nullptr;
+  a.field = a.prop = nullptr;
+  a.out = a.out2 = nullptr;
+  a.c_stage = 0.0;
+  a.use_scale = 0;
+  return a;
+}
+
+template <typename R>
+hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw, const void* prop, void* tmp,
+                         hipStream_t s) {
+  using C = typename CT<R>::T;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)psi_raw;
+  a.prop = (const R*)prop;
+  a.out = (C*)tmp;
+  timing_before(FAM_ITP1, s);
+  hipError_t e = dispatch_pass<R, OP_ITP1>(p, cfg, a, s);
+  timing_after(FAM_ITP1, s);
+  return e;
+}
+
+template <typename R>
+hipError_t run_itp_pass2(const Plan& p, const LaunchConfig& cfg, const void* tmp, const void* prop, void* psi_raw,
+                         hipStream_t s) {
+  using C = typename CT<R>::T;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)tmp;
+  a.prop = (const R*)prop;
+  a.out = (C*)psi_raw;
+  timing_before(FAM_ITP2, s);
+  hipError_t e = dispatch_pass<R, OP_ITP2>(p, cfg, a, s);
+  timing_after(FAM_ITP2, s);
+  return e;
+}
+
+template <typename R>
+hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool obs, const void* Y, const void* y0,
+                        const void* y2, const void* y3, const void* field, void* out, hipStream_t s) {
+  using C = typename CT<R>::T;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)Y;
+  a.a = (const C*)y0;
+  a.b = (const C*)y2;
+  a.c = (const C*)y3;
+  a.field = (const R*)field;
+  a.out = (C*)out;
+  static const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+  if (stage < 1 || stage > 4) return hipErrorInvalidValue;
+  a.c_stage = cst[stage - 1];
+  const int fam = FAM_RK1 + stage - 1;
+  timing_before(fam, s);
+  hipError_t e;
+  switch (stage) {
+    case 1: e = obs ? dispatch_pass<R, OP_RK1_OBS>(p, cfg, a, s) : dispatch_pass<R, OP_RK1>(p, cfg, a, s); break;
+    case 2: e = dispatch_pass<R, OP_RK2>(p, cfg, a, s); break;
+    case 3: e = dispatch_pass<R, OP_RK3>(p, cfg, a, s); break;
+    default: e = dispatch_pass<R, OP_RK4>(p, cfg, a, s); break;
+  }
+  timing_after(fam, s);
+  return e;
+}
+
+template <typename R>
+hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi, const void* field,
+                       double t_offset_steps, bool use_scale, hipStream_t s) {
+  using C = typename CT<R>::T;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)psi;
+  a.field = (const R*)field;
+  a.c_stage = t_offset_steps;
+  a.use_scale = use_scale ? 1 : 0;
+  timing_before(FAM_OBSERVE, s);
+  hipError_t e = dispatch_pass<R, OP_OBS>(p, cfg, a, s);
+  timing_after(FAM_OBSERVE, s);
+  return e;
+}
+
+template <typename R>
+hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, const void* X, const void* Y,
+                         const void* field, const void* lam, void* lacc, void* uout, hipStream_t s) {
+  using C = typename CT<R>::T;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)X;
+  a.a = (const C*)Y;
+  a.b = (const C*)lam;
+  a.field = (const R*)field;
+  a.out = (C*)uout;
+  a.out2 = (C*)lacc;
+  static const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+  if (stage < 1 || stage > 4) return hipErrorInvalidValue;
+  a.c_stage = cst[stage - 1];
+  const int fam = FAM_ADJ1 + stage - 1;
+  timing_before(fam, s);
+  hipError_t e;
+  switch (stage) {
+    case 4: e = dispatch_pass<R, OP_ADJ4>(p, cfg, a, s); break;
+    case 3: e = dispatch_pass<R, OP_ADJ3>(p, cfg, a, s); break;
+    case 2: e = dispatch_pass<R, OP_ADJ2>(p, cfg, a, s); break;
+    default: e = dispatch_pass<R, OP_ADJ1>(p, cfg, a, s); break;
+  }
+  timing_after(fam, s);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// pointwise passes (one workgroup of 256 lanes per chunk)
+// ---------------------------------------------------------------------------
+enum PointOp { PT_PROP = 0, PT_SCALE, PT_OVERLAP, PT_SEED, PT_RANGE };
+
+template <typename R> struct PointArgs {
+  using C = typename CT<R>::T;
+  const C* a;
+  const C* b;
+  const R* field;
+  C* out;
+  R* rout;
+};
+
+template <typename R, int OP>
+__global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R> a) {
+  using C = typename CT<R>::T;
+  constexpr int NR = (OP == PT_OVERLAP || OP == PT_RANGE) ? 2 : 1;
+  __shared__ double red[4][NR];
+  const int cidx = (int)blockIdx.x;
+  const Chunk ch = pl.chunks[cidx];
+  const InstParams& ip = pl.inst[ch.inst];
+  const int kind = ip.pot_kind;
+  const R omega2 = (R)(ip.omega * ip.omega);
+  const double t = ip.t0 + (double)(*pl.step) * ip.dt;
+  const R delta = (kind == GPE_POT_RF_RAMP) ? (R)delta_at(ip, t) : R(0);
+  double acc[NR];
+  if (OP == PT_RANGE) {
+    acc[0] = 1e300;
+    acc[1] = -1e300;
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  }
+  R sc = R(1);
+  double cre = 0.0, cim = 0.0;
+  if (OP == PT_SCALE) sc = (R)pl.out[ch.inst].scale;
+  if (OP == PT_SEED) {
+    cre = pl.out[ch.inst].ov_re;
+    cim = pl.out[ch.inst].ov_im;
+  }
+  for (int l = threadIdx.x; l < ch.count; l += 256) {
+    const int64_t s = (int64_t)ch.site_begin + l;
+    if constexpr (OP == PT_PROP) {
+      const R V = potential<R>(kind, a.field[s], delta, omega2);
+      a.rout[s] = exp(-V * (R)ip.dt * R(0.5));
+    } else if constexpr (OP == PT_SCALE) {
+      const C v = a.out[s];
+      a.out[s] = cmk<R>(v.x * sc, v.y * sc);
+    } else if constexpr (OP == PT_OVERLAP) {
+      const C x = a.a[s], y = a.b[s];
+      acc[0] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+      acc[1] += (double)x.x * (double)y.y - (double)x.y * (double)y.x;
+    } else if constexpr (OP == PT_SEED) {
+      // lambda_N = -2 dV c psi_target
+      const C x = a.a[s];
+      const double f = -2.0 * ip.dV;
+      a.out[s] = cmk<R>((R)(f * (cre * x.x - cim * x.y)), (R)(f * (cre * x.y + cim * x.x)));
+    } else if constexpr (OP == PT_RANGE) {
+      const double u = (double)a.field[s];
+      acc[0] = u < acc[0] ? u : acc[0];
+      acc[1] = u > acc[1] ? u : acc[1];
+    }
+  }
+  if constexpr (OP == PT_OVERLAP) {
+    block_sum<256, NR>(acc, red);
+    if (threadIdx.x == 0)
+      for (int r = 0; r < NR; ++r) pl.partials[(size_t)cidx * NPART + r] = acc[r];
+  } else if constexpr (OP == PT_RANGE) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double lo = __shfl_xor(acc[0], off, 64), hi = __shfl_xor(acc[1], off, 64);
+      acc[0] = lo < acc[0] ? lo : acc[0];
+      acc[1] = hi > acc[1] ? hi : acc[1];
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6][0] = acc[0];
+      red[threadIdx.x >> 6][1] = acc[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double lo = red[0][0], hi = red[0][1];
+      for (int w = 1; w < 4; ++w) {
+        lo = red[w][0] < lo ? red[w][0] : lo;
+        hi = red[w][1] > hi ? red[w][1] : hi;
+      }
+      pl.partials[(size_t)cidx * NPART + 0] = lo;
+      pl.partials[(size_t)cidx * NPART + 1] = hi;
+    }
+  }
+}
+
+template <typename R, int OP>
+static hipError_t launch_point(const Plan& p, const PointArgs<R>& a, hipStream_t s) {
+  if (p.n_chunks <= 0) return hipSuccess;
+  timing_before(FAM_POINTWISE, s);
+  hipLaunchKernelGGL((k_point<R, OP>), dim3(p.n_chunks), dim3(256), 0, s, p, a);
+  hipError_t e = hipGetLastError();
+  timing_after(FAM_POINTWISE, s);
+  return e;
+}
+
+template <typename R> static PointArgs<R> point_args() {
+  PointArgs<R> a;
+  a.a = a.b = nullptr;
+  a.field = nullptr;
+  a.out = nullptr;
+  a.rout = nullptr;
+  return a;
+}
+
+template <typename R>
+hipError_t run_make_prop(const Plan& p, const LaunchConfig&, const void* field, void* prop, hipStream_t s) {
+  PointArgs<R> a = point_args<R>();
+  a.field = (const R*)field;
+  a.rout = (R*)prop;
+  return launch_point<R, PT_PROP>(p, a, s);
+}
+
+template <typename R>
+hipError_t run_apply_scale(const Plan& p, const LaunchConfig&, void* psi, hipStream_t s) {
+  PointArgs<R> a = point_args<R>();
+  a.out = (typename CT<R>::T*)psi;
+  return launch_point<R, PT_SCALE>(p, a, s);
+}
+
+template <typename R>
+hipError_t run_overlap(const Plan& p, const LaunchConfig&, const void* x, const void* y, hipStream_t s) {
+  PointArgs<R> a = point_args<R>();
+  a.a = (const typename CT<R>::T*)x;
+  a.b = (const typename CT<R>::T*)y;
+  return launch_point<R, PT_OVERLAP>(p, a, s);
+}
+
+template <typename R>
+hipError_t run_seed_lambda(const Plan& p, const LaunchConfig&, const void* target, void* lam, hipStream_t s) {
+  PointArgs<R> a = point_args<R>();
+  a.a = (const typename CT<R>::T*)target;
+  a.out = (typename CT<R>::T*)lam;
+  return launch_point<R, PT_SEED>(p, a, s);
+}
+
+template <typename R>
+hipError_t run_field_range(const Plan& p, const LaunchConfig&, const void* field, hipStream_t s) {
+  PointArgs<R> a = point_args<R>();
+  a.field = (const R*)field;
+  return launch_point<R, PT_RANGE>(p, a, s);
+}
+
+// ---------------------------------------------------------------------------
+// finalize: one workgroup per instance sums its chunks' partials in order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(const Plan pl, int kind, gpe_obs* obs_dev) {
+  __shared__ double red[4][NPART];
+  const int inst = (int)blockIdx.x;
+  const InstParams& ip = pl.inst[inst];
+  double acc[NPART];
+  const bool range = (kind == FIN_RANGE);
+  if (kind == FIN_LOSS) {
+    if (threadIdx.x == 0) {
+      InstOut& o = pl.out[inst];
+      o.loss = 1.0 - (o.ov_re * o.ov_re + o.ov_im * o.ov_im);
+    }
+    return;
+  }
+  acc[0] = range ? 1e300 : 0.0;
+  acc[1] = range ? -1e300 : 0.0;
+  acc[2] = acc[3] = 0.0;
+  for (int c = ip.chunk_begin + (int)threadIdx.x; c < ip.chunk_begin + ip.chunk_count; c += 256) {
+    const double* q = pl.partials + (size_t)c * NPART;
+    if (range) {
+      acc[0] = q[0] < acc[0] ? q[0] : acc[0];
+      acc[1] = q[1] > acc[1] ? q[1] : acc[1];
+    } else {
+#pragma unroll
+      for (int r = 0; r < NPART; ++r) acc[r] += q[r];
+    }
+  }
+  if (range) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double lo = __shfl_xor(acc[0], off, 64), hi = __shfl_xor(acc[1], off, 64);
+      acc[0] = lo < acc[0] ? lo : acc[0];
+      acc[1] = hi > acc[1] ? hi : acc[1];
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6][0] = acc[0];
+      red[threadIdx.x >> 6][1] = acc[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double lo = red[0][0], hi = red[0][1];
+      for (int w = 1; w < 4; ++w) {
+        lo = red[w][0] < lo ? red[w][0] : lo;
+        hi = red[w][1] > hi ? red[w][1] : hi;
+      }
+      pl.out[inst].fmin = lo;
+      pl.out[inst].fmax = hi;
+    }
+    return;
+  }
+  block_sum<256, NPART>(acc, red);
+  if (threadIdx.x != 0) return;
+  InstOut& o = pl.out[inst];
+  const double dV = ip.dV;
+  if (kind == FIN_NORM_SCALE) {
+    const double n = dV * acc[0];
+    o.norm = n;
+    o.scale = sqrt(ip.norm_target / n);
+  } else if (kind == FIN_OBS) {
+    const double N = dV * acc[0];
+    const double E = dV * (acc[1] + acc[2] + 0.5 * ip.g * acc[3]) / N;
+    const double mu = dV * (acc[1] + acc[2] + ip.g * acc[3]) / N;
+    o.norm = N;
+    o.energy = E;
+    o.mu = mu;
+    if (obs_dev) {
+      obs_dev[inst].norm = N;
+      obs_dev[inst].energy = E;
+      obs_dev[inst].mu = mu;
+    }
+  } else if (kind == FIN_OVERLAP) {
+    o.ov_re = dV * acc[0];
+    o.ov_im = dV * acc[1];
+  }
+}
+
+hipError_t run_finalize(const Plan& p, int kind, gpe_obs* obs_dev, hipStream_t s) {
+  timing_before(FAM_FINALIZE, s);
+  hipLaunchKernelGGL(k_finalize, dim3(p.n_inst), dim3(256), 0, s, p, kind, obs_dev);
+  hipError_t e = hipGetLastError();
+  timing_after(FAM_FINALIZE, s);
+  return e;
+}
+
+__global__ __launch_bounds__(64) void k_knot_finalize(const Plan pl, double* grads) {
+  const int inst = (int)blockIdx.x;
+  const InstParams& ip = pl.inst[inst];
+  const int k = (int)threadIdx.x;
+  if (k >= GPE_MAX_KNOTS) return;
+  double s = 0.0;
+  for (int c = ip.chunk_begin; c < ip.chunk_begin + ip.chunk_count; ++c) s += pl.knot_acc[(size_t)c * GPE_MAX_KNOTS + k];
+  grads[(size_t)inst * GPE_MAX_KNOTS + k] = s;
+}
+
+hipError_t run_knot_finalize(const Plan& p, double* grads_dev, hipStream_t s) {
+  timing_before(FAM_FINALIZE, s);
+  hipLaunchKernelGGL(k_knot_finalize, dim3(p.n_inst), dim3(64), 0, s, p, grads_dev);
+  hipError_t e = hipGetLastError();
+  timing_after(FAM_FINALIZE, s);
+  return e;
+}
+
+__global__ void k_zero_doubles(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+hipError_t run_zero_doubles(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero_doubles, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+__global__ void k_set_scale_one(const Plan pl) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < pl.n_inst) pl.out[i].scale = 1.0;
+}
+
+hipError_t run_set_scale_one(const Plan& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scale_one, dim3((p.n_inst + 63) / 64), dim3(64), 0, s, p);
+  return hipGetLastError();
+}
+
+__global__ void k_set_step(int64_t* step, int64_t value) {
+  if (threadIdx.x == 0) *step = value;
+}
+__global__ void k_tick(int64_t* step, int64_t delta) {
+  if (threadIdx.x == 0) *step += delta;
+}
+
+hipError_t run_set_step(int64_t* step, int64_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, step, value);
+  return hipGetLastError();
+}
+
+hipError_t run_tick(int64_t* step, int64_t delta, hipStream_t s) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, step, delta);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// box <-> compact
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_pack(const int64_t* run_base, const int32_t* run_start, int64_t nruns, int64_t n,
+                       const typename CT<R>::T* src, typename CT<R>::T* dst, int to_box) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nruns - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (run_start[mid] <= s) lo = mid; else hi = mid - 1;
+    }
+    const int64_t box = run_base[lo] + (s - run_start[lo]);
+    if (to_box) dst[box] = src[s];
+    else dst[s] = src[box];
+  }
+}
+
+template <typename R>
+hipError_t run_pack(const int64_t* run_base, const int32_t* run_start, int64_t nruns, int64_t n_active,
+                    const void* src, void* dst, bool to_box, hipStream_t s) {
+  using C = typename CT<R>::T;
+  int64_t blocks = (n_active + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  timing_before(FAM_POINTWISE, s);
+  hipLaunchKernelGGL((k_pack<R>), dim3((unsigned)blocks), dim3(256), 0, s, run_base, run_start, nruns, n_active,
+                     (const C*)src, (C*)dst, to_box ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  timing_after(FAM_POINTWISE, s);
+  return e;
+}
+
+template <typename R>
+__global__ void k_fill_zero(typename CT<R>::T* d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = cmk<R>(R(0), R(0));
+}
+
+template <typename R>
+hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL((k_fill_zero<R>), dim3((unsigned)blocks), dim3(256), 0, s, (typename CT<R>::T*)dst, n);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+#define GPE_INST(R)                                                                                            \
+  template hipError_t run_itp_pass1<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
+                                       hipStream_t);                                                         \
+  template hipError_t run_itp_pass2<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
+                                       hipStream_t);                                                         \
+  template hipError_t run_rk_stage<R>(const Plan&, const LaunchConfig&, int, bool, const void*, const void*, \
+                                      const void*, const void*, const void*, void*, hipStream_t);            \
+  template hipError_t run_observe<R>(const Plan&, const LaunchConfig&, const void*, const void*, double, bool, \
+                                     hipStream_t);                                                           \
+  template hipError_t run_adj_stage<R>(const Plan&, const LaunchConfig&, int, const void*, const void*,      \
+                                       const void*, const void*, void*, void*, hipStream_t);                 \
+  template hipError_t run_make_prop<R>(const Plan&, const LaunchConfig&, const void*, void*, hipStream_t);   \
+  template hipError_t run_apply_scale<R>(const Plan&, const LaunchConfig&, void*, hipStream_t);              \
+  template hipError_t run_overlap<R>(const Plan&, const LaunchConfig&, const void*, const void*, hipStream_t); \
+  template hipError_t run_seed_lambda<R>(const Plan&, const LaunchConfig&, const void*, void*, hipStream_t); \
+  template hipError_t run_field_range<R>(const Plan&, const LaunchConfig&, const void*, hipStream_t);        \
+  template hipError_t run_pack<R>(const int64_t*, const int32_t*, int64_t, int64_t, const void*, void*, bool, \
+                                  hipStream_t);                                                              \
+  template hipError_t run_fill_zero<R>(void*, int64_t, hipStream_t);
+
+GPE_INST(double)
+GPE_INST(float)
+
+}  // namespace gpe

@@ -1,0 +1,51 @@
+"""Helpers shared by the GPU parity tests: put a seeded workload on the
+device through the binding, and run the oracle on the same inputs."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import operator as op
+from oracle.potential import StaticPotential, RFRamp
+from workloads import site_linear_index
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+class Case:
+    """A workload on the GPU (binding objects) and on the CPU (oracle objects)."""
+
+    def __init__(self, w, dtype="c128", config=None):
+        import torch
+        from paper_2603_05447_amd import Grid, Potential
+
+        self.w = w
+        self.dev = torch.device("cuda:0")
+        self.cdt = torch.complex128 if dtype == "c128" else torch.complex64
+        self.rdt = torch.float64 if dtype == "c128" else torch.float32
+        self.grid = Grid.from_box(w.box, runs=w.runs, device=0)
+        if config is not None:
+            self.grid.set_config(config)
+        self.field = torch.tensor(w.field, dtype=self.rdt, device=self.dev)
+        if w.kind == "rf":
+            self.pot = Potential.rf(self.field, w.omega, w.knot_t, w.knot_delta)
+            self.opot = RFRamp(w.field, w.omega, w.knot_t, w.knot_delta)
+        else:
+            self.pot = Potential.static(self.field)
+            self.opot = StaticPotential(w.field)
+        self._T = None
+
+    @property
+    def T(self):
+        if self._T is None:
+            lin = site_linear_index(self.w.box, self.w.runs)
+            self._T = op.kinetic_direct(self.w.box.n, self.w.box.h, lin)
+        return self._T
+
+    def psi(self, arr=None):
+        import torch
+        a = self.w.psi0 if arr is None else arr
+        return torch.tensor(np.asarray(a), dtype=self.cdt, device=self.dev)
