@@ -1,0 +1,343 @@
+"""Benchmark of the hot path on one MI355X.
+
+Headline workload (the configuration the metric is quoted on): the
+anisotropic RF-dressed bubble on a 1024 x 1024 x 512 bounding grid
+(h = 0.0612, U = (x^2 + y^2 + 4 z^2)/2, Delta = 60, Omega = 2, mask
+V < 27 -> 16,028,656 active sites, g = 2000, dt = 2e-4), complex128.  The
+job is imaginary time followed by RK4 real time in the ratio 5k : 10k, so
+one bench step is one imaginary-time step plus two RK4 steps; `value` counts
+site updates of both phases per second, inputs resident in HBM.
+
+Also reported: the complex64 form (FP32 stencil, FP64 reductions), the
+adjoint gradient rate on the 256^3 hollowing ramp (grads/s vs plain FP64
+forward runs), the 64-instance batched sweep (hipGraph), per-kernel timing
+(HIP events on the launch stream) with the roofline of the dominant kernel,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "active-site GPE updates/s + % HBM roofline; adjoint grads/s vs plain FP64"
+HBM_PEAK_GBPS = 8000.0
+
+# algorithmic bytes per active site per launch (each input read once from HBM,
+# each output written once), by kernel family; R = bytes of a real, C = 2R
+def algo_bytes(fam: str, R: int) -> int:
+    C = 2 * R
+    table = {
+        "itp_pass1": C + R + C,          # psi, P -> tmp
+        "itp_pass2": C + R + C,          # tmp, P -> psi
+        "rk_stage1": C + R + C,          # y0, U -> y2
+        "rk_stage2": 2 * C + R + C,      # y2, y0, U -> y3
+        "rk_stage3": 2 * C + R + C,      # y3, y0, U -> y4
+        "rk_stage4": 4 * C + R + C,      # y4, y0, y2, y3, U -> y0
+        "observe": C + R,
+        "adj_stage4": C + C + R + 2 * C,            # lam, Y4, U -> u3, lacc
+        "adj_stage3": C + C + R + C + C + 2 * C,    # u3, Y3, U, lam, lacc -> u2, lacc
+        "adj_stage2": C + C + R + C + C + 2 * C,
+        "adj_stage1": C + C + R + C + C,            # u1, Y1, U, lacc -> lam
+    }
+    return table.get(fam, 0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+# ---------------------------------------------------------------------------
+def setup_c2(dev, dtype):
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    from workloads import configs
+    t = time.time()
+    w = configs.c2()
+    log(f"[bench] C2 inputs: {w.n_active} sites, {w.runs.shape[0]} runs ({time.time() - t:.1f}s)")
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rdt = torch.float64 if dtype == "c128" else torch.float32
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    U = torch.tensor(w.field, dtype=rdt, device=dev)
+    psi = torch.tensor(w.psi0, dtype=cdt, device=dev)
+    d_itp, d_rt = w.extra["delta_itp"], w.extra["delta_rt"]
+    pot_itp = Potential.rf(U, w.omega, [0.0], [d_itp])
+    pot_rt = Potential.rf(U, w.omega, [0.0], [d_rt])
+    return w, g, U, psi, pot_itp, pot_rt
+
+
+def run_phase_timed(g, psi, pot_itp, pot_rt, w, k_itp, k_rt):
+    import torch
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(s)
+    if k_itp:
+        g.imag_time(psi, pot_itp, w.g, w.dt, k_itp, observe=False)
+    e1.record(s)
+    if k_rt:
+        g.real_time(psi, pot_rt, w.g, w.dt, k_rt, observe=False)
+    e2.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), e1.elapsed_time(e2)
+
+
+def bench_c2(args, dev, dtype, report):
+    import torch
+    from paper_2603_05447_amd import KernelTimer
+    w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, dtype)
+    n = w.n_active
+    R = 8 if dtype == "c128" else 4
+    if args.config is not None:
+        g.set_config(args.config)
+    # warmup (also builds the chunk tables)
+    run_phase_timed(g, psi, pot_itp, pot_rt, w, max(args.warmup, 1), 2 * max(args.warmup, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with KernelTimer() as kt:
+        ms_itp, ms_rt = run_phase_timed(g, psi, pot_itp, pot_rt, w, args.steps, 2 * args.steps)
+        kern = kt.read()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ms_itp + ms_rt
+    # untimed check: the state is still normalised / finite
+    obs = g.observe(psi, pot_rt, 0.0, w.g)
+    res = {
+        "n_active": n,
+        "ms_per_step": total_ms / args.steps,
+        "wall_s": wall,
+        "site_updates_per_s": n * 3 * args.steps / (total_ms * 1e-3),
+        "itp": {"ms_per_step": ms_itp / args.steps, "site_updates_per_s": n * args.steps / (ms_itp * 1e-3),
+                "eff_GBps": 2 * algo_bytes("itp_pass1", R) * n * args.steps / (ms_itp * 1e-3) / 1e9},
+        "rt_rk4": {"ms_per_step": ms_rt / (2 * args.steps),
+                   "site_updates_per_s": n * 2 * args.steps / (ms_rt * 1e-3),
+                   "eff_GBps": sum(algo_bytes(f"rk_stage{i}", R) for i in range(1, 5)) * n * 2 * args.steps
+                   / (ms_rt * 1e-3) / 1e9},
+        "final_norm": obs["norm"],
+        "config": g.get_config(),
+    }
+    kernels = {}
+    for fam, v in kern.items():
+        if v["launches"] == 0:
+            continue
+        avg_us = 1e3 * v["total_ms"] / v["launches"]
+        b = algo_bytes(fam, R) * n
+        kernels[fam] = {"launches": v["launches"], "avg_us": avg_us, "total_ms": v["total_ms"],
+                        "algo_bytes_per_launch": b, "GBps": (b / (avg_us * 1e-6) / 1e9) if b else None}
+    res["kernels"] = kernels
+    report[dtype] = res
+    del psi, U, g
+    torch.cuda.empty_cache()
+    return w
+
+
+def cpu_baseline(args):
+    """The FP64 oracle, single-threaded, on a slab of the headline workload:
+    the active sites of x-planes [448, 576) of the 1024 x 1024 x 512 grid
+    (the same shell, Dirichlet at the slab faces), one imaginary-time step
+    plus two RK4 steps per repeat."""
+    from oracle import operator as op, itp, realtime as rt
+    from oracle.potential import RFRamp
+    from workloads import configs, site_linear_index
+    w = configs.c2()
+    sel = (w.runs[:, 0] >= 448) & (w.runs[:, 0] < 576)
+    runs = w.runs[sel]
+    lens = runs[:, 3] - runs[:, 2]
+    starts = np.concatenate([[0], np.cumsum(w.runs[:, 3] - w.runs[:, 2])[:-1]])[sel]
+    idx = np.concatenate([np.arange(s, s + l) for s, l in zip(starts, lens)])
+    U = w.field[idx]
+    psi = w.psi0[idx]
+    lin = site_linear_index(w.box, runs)
+    t = time.perf_counter()
+    T = op.kinetic_direct(w.box.n, w.box.h, lin)
+    t_build = time.perf_counter() - t
+    V = np.sqrt((U - w.extra["delta_itp"]) ** 2 + w.omega ** 2)
+    P = itp.propagator(V, w.dt)
+    ramp = RFRamp(U, w.omega, [0.0], [w.extra["delta_rt"]])
+    reps, times = 0, []
+    t_all = time.perf_counter()
+    while True:
+        t = time.perf_counter()
+        psi, _ = itp.itp_step(T, psi, P, w.g, w.dt, w.box.dV)
+        psi = rt.rk4_step(T, psi, 0.0, w.dt, ramp, w.g)
+        psi = rt.rk4_step(T, psi, w.dt, w.dt, ramp, w.g)
+        times.append(time.perf_counter() - t)
+        reps += 1
+        if reps >= 3 and (time.perf_counter() - t_all > args.cpu_seconds or reps >= 50):
+            break
+    med = float(np.median(times))
+    return {"value": idx.size * 3 / med, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy/SciPy oracle, single thread, on x-planes [448,576) of the headline grid "
+                      f"({idx.size} active sites); median of {reps} repeats of 1 imaginary-time + 2 RK4 steps "
+                      f"(operator build {t_build:.1f}s not counted)",
+            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+
+
+def bench_adjoint(args, dev, report):
+    """256^3 hollowing ramp: loss + 8-knot gradient by the adjoint, vs plain
+    FP64 forward runs of the same 2000 steps."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    from workloads import configs
+    w = configs.c3(steps=args.adj_steps)
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    U = torch.tensor(w.field, dtype=torch.float64, device=dev)
+    # psi0 / target: ground states at the first and last detuning (imaginary time on the GPU)
+    psi0 = torch.tensor(w.psi0, dtype=torch.complex128, device=dev)
+    g.imag_time(psi0, Potential.rf(U, w.omega, [0.0], [w.knot_delta[0]]), w.g, 1e-3, 300, observe=False)
+    tgt = psi0.clone()
+    g.imag_time(tgt, Potential.rf(U, w.omega, [0.0], [w.knot_delta[-1]]), w.g, 1e-3, 300, observe=False)
+    pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
+    g.fidelity_grad(psi0, tgt, pot, w.g, w.dt, 20)   # warmup
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    loss, grad = g.fidelity_grad(psi0, tgt, pot, w.g, w.dt, w.steps)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t
+    p = psi0.clone()
+    g.real_time(p, pot, w.g, w.dt, 20, observe=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g.real_time(p, pot, w.g, w.dt, w.steps, observe=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    report["adjoint_c3"] = {"workload": w.name, "n_active": w.n_active, "steps": w.steps,
+                            "grads_per_s": 1.0 / t_grad, "s_per_grad": t_grad,
+                            "forward_fp64_runs_per_s": 1.0 / t_fwd, "grad_over_forward_time": t_grad / t_fwd,
+                            "loss": loss, "grad": [float(x) for x in grad]}
+    del g, U, psi0, tgt, p
+    torch.cuda.empty_cache()
+
+
+def bench_batched(args, dev, report):
+    """64 instances (96^3..192^3 boxes), complex64 storage with FP64
+    reductions, one hipGraph-captured step replayed per step."""
+    import torch
+    from paper_2603_05447_amd import Grid, Batch, GPE_C64, GPE_MODE_RT
+    from workloads import configs
+    t = time.time()
+    ws = [configs.c4_instance(i, steps=args.batch_steps) for i in range(args.batch_n)]
+    log(f"[bench] C4 inputs: {sum(w.n_active for w in ws)} sites in {len(ws)} instances ({time.time() - t:.1f}s)")
+    grids = [Grid.from_box(w.box, runs=w.runs, device=0) for w in ws]
+    b = Batch(grids, device=0)
+    psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=torch.complex64, device=dev)
+    field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=torch.float32, device=dev)
+    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    gs, dts = [w.g for w in ws], [w.dt for w in ws]
+    work = torch.empty(b.work_bytes(GPE_C64, GPE_MODE_RT, 1), dtype=torch.uint8, device=dev)
+    out = {}
+    for use_graph in (False, True):
+        b.real_time(psi, field, ramps, gs, dts, 5, use_graph=use_graph, work=work, observe=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        obs = b.real_time(psi, field, ramps, gs, dts, args.batch_steps, use_graph=use_graph, work=work)
+        el = time.perf_counter() - t
+        out["graph" if use_graph else "eager"] = {
+            "s": el, "site_updates_per_s": b.total * args.batch_steps / el,
+            "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 4) for i in range(1, 5)) * b.total * args.batch_steps / el / 1e9,
+            "norm_min": min(o["norm"] for o in obs), "norm_max": max(o["norm"] for o in obs)}
+    report["batched_c4"] = {"instances": len(ws), "total_sites": b.total, "steps": args.batch_steps, **out}
+    del b, grids, psi, field, work
+    torch.cuda.empty_cache()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=None, help="launch variant index (default: library default)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip complex64, adjoint and batched legs")
+    ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2603_05447_amd as p
+    p.load_library()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    report = {}
+    t_start = time.time()
+    bench_c2(args, dev, "c128", report)
+    log(f"[bench] c128 done: {report['c128']['site_updates_per_s']:.4g} site-updates/s")
+    if not args.no_extras:
+        bench_c2(args, dev, "c64", report)
+        log(f"[bench] c64 done: {report['c64']['site_updates_per_s']:.4g} site-updates/s")
+        bench_adjoint(args, dev, report)
+        log(f"[bench] adjoint done: {report['adjoint_c3']['grads_per_s']:.3g} grads/s")
+        bench_batched(args, dev, report)
+        log("[bench] batched done")
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args)
+        log(f"[bench] cpu baseline: {cpu['value']:.4g} site-updates/s")
+
+    main_res = report["c128"]
+    kern = main_res["kernels"]
+    dom = max((f for f in kern if kern[f]["GBps"] is not None), key=lambda f: kern[f]["total_ms"])
+    k = kern[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": None,
+                "algo_bytes_per_launch": k["algo_bytes_per_launch"], "avg_launch_us": k["avg_us"]}
+    line = {
+        "metric": METRIC,
+        "value": main_res["site_updates_per_s"],
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rf-bubble 1024x1024x512 h=0.0612, Delta=60 (ITP) / 62 (RK4), Omega=2, "
+                               "mask V<27, 16,028,656 active sites, g=2000, dt=2e-4, complex128; "
+                               "one step = 1 imaginary-time step + 2 RK4 steps",
+                   "n_active": main_res["n_active"], "launch_config": main_res["config"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases": {"c128": {k2: v for k2, v in main_res.items() if k2 != "kernels"}},
+        "kernels_c128": kern,
+        "wall_s": time.time() - t_start,
+    }
+    if "c64" in report:
+        line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
+        line["kernels_c64"] = report["c64"]["kernels"]
+    for key in ("adjoint_c3", "batched_c4"):
+        if key in report:
+            line[key] = report[key]
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

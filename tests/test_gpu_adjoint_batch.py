@@ -1,0 +1,170 @@
+"""GPU parity for the adjoint (fidelity gradient w.r.t. ramp knots) and for
+batched instances (concatenated layouts, one launch per stage, hipGraph
+replay)."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as adj, realtime as rt
+from workloads import configs
+
+from gpu_cases import Case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _target(w, seed=77):
+    rng = np.random.default_rng(seed)
+    tgt = w.psi0 * np.exp(1j * rng.uniform(0, 0.3, w.psi0.size)) + 0.05 * rng.standard_normal(w.psi0.size)
+    return tgt / np.sqrt(np.sum(np.abs(tgt) ** 2) * w.box.dV)
+
+
+@pytest.mark.parametrize("ckpt", [0, 1, 7])
+def test_fidelity_gradient_matches_oracle_adjoint(ckpt):
+    w = configs.small_rf_ramp(n=22, steps=24, g=250.0, n_knots=6)
+    c = Case(w, "c128")
+    tgt = _target(w)
+    psi0, target = c.psi(), c.psi(tgt)
+    import torch
+    fin = torch.empty_like(psi0)
+    loss, grad = c.grid.fidelity_grad(psi0, target, c.pot, w.g, w.dt, w.steps, 0.0, ckpt, psi_final=fin)
+    oloss, ograd, oy = adj.fidelity_grad(c.T, c.opot, w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV, ckpt)
+    _print(f"adjoint ckpt={ckpt}: loss {loss:.15f} vs {oloss:.15f}; grad rel err "
+           f"{np.max(np.abs(grad - ograd)) / np.max(np.abs(ograd)):.3e}")
+    assert rel_l2(fin.cpu().numpy(), oy) <= 1e-10
+    assert abs(loss - oloss) <= 1e-10 * max(abs(oloss), 1e-3)
+    assert np.max(np.abs(grad - ograd)) <= 1e-9 * np.max(np.abs(ograd))
+
+
+def test_fidelity_gradient_matches_central_differences_on_gpu():
+    """Central differences (h = 1e-5) of the GPU forward loss agree with the
+    GPU adjoint gradient to ~1e-6 (truncation O(h^2) + rounding O(eps/h))."""
+    w = configs.small_rf_ramp(n=20, steps=16, g=250.0, n_knots=5)
+    c = Case(w, "c128")
+    tgt = _target(w, 5)
+    psi0, target = c.psi(), c.psi(tgt)
+    loss, grad = c.grid.fidelity_grad(psi0, target, c.pot, w.g, w.dt, w.steps)
+    h = 1e-5
+    for k in range(len(w.knot_delta)):
+        kp = w.knot_delta.copy(); kp[k] += h
+        km = w.knot_delta.copy(); km[k] -= h
+        lp, _ = c.grid.fidelity_grad(psi0, target, c.pot.with_knots(kp), w.g, w.dt, w.steps)
+        lm, _ = c.grid.fidelity_grad(psi0, target, c.pot.with_knots(km), w.g, w.dt, w.steps)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grad[k]) <= 1e-6 * np.max(np.abs(grad)) + 1e-11, (k, fd, grad[k])
+
+
+def test_autograd_function():
+    import torch
+    from paper_2603_05447_amd import FidelityGrad
+    w = configs.small_rf_ramp(n=20, steps=12, g=200.0, n_knots=5)
+    c = Case(w, "c128")
+    tgt = _target(w, 9)
+    knots = torch.tensor(w.knot_delta, dtype=torch.float64, requires_grad=True)
+    loss = FidelityGrad.apply(knots, c.grid, c.psi(), c.psi(tgt), c.field, w.omega, w.knot_t, w.g, w.dt, w.steps, 0)
+    (2.0 * loss).backward()
+    oloss, ograd, _ = adj.fidelity_grad(c.T, c.opot, w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV)
+    assert abs(loss.item() - oloss) <= 1e-10
+    assert np.max(np.abs(knots.grad.numpy() - 2.0 * ograd)) <= 1e-9 * np.max(np.abs(ograd))
+
+
+def test_fidelity_gradient_fp32():
+    w = configs.small_rf_ramp(n=20, steps=12, g=200.0, n_knots=5)
+    c = Case(w, "c64")
+    tgt = _target(w, 3)
+    loss, grad = c.grid.fidelity_grad(c.psi(), c.psi(tgt), c.pot, w.g, w.dt, w.steps)
+    oloss, ograd, _ = adj.fidelity_grad(c.T, c.opot, w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV)
+    err = np.max(np.abs(grad - ograd)) / np.max(np.abs(ograd))
+    _print(f"fp32 adjoint: loss err {abs(loss - oloss):.2e}, grad rel err {err:.2e}")
+    assert abs(loss - oloss) <= 1e-5
+    assert err <= 1e-3
+
+
+def _instances(k=5, steps=10):
+    ws = [configs.c4_instance(i, n_lo=14, n_hi=26, steps=steps) for i in range(k)]
+    return ws
+
+
+def _batch(ws, dtype):
+    import torch
+    from paper_2603_05447_amd import Grid, Batch
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rdt = torch.float64 if dtype == "c128" else torch.float32
+    grids = [Grid.from_box(w.box, runs=w.runs, device=0) for w in ws]
+    b = Batch(grids, device=0)
+    psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=cdt, device="cuda:0")
+    field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=rdt, device="cuda:0")
+    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    return b, psi, field, ramps
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_matches_single_instances(use_graph, dtype):
+    ws = _instances()
+    b, psi, field, ramps = _batch(ws, dtype)
+    steps = 10
+    obs = b.real_time(psi, field, ramps, [w.g for w in ws], [w.dt for w in ws], steps, use_graph=use_graph)
+    out = psi.cpu().numpy()
+    tol = 1e-13 if dtype == "c128" else 1e-6
+    for i, w in enumerate(ws):
+        c = Case(w, dtype)
+        p = c.psi()
+        o1 = c.grid.real_time(p, c.pot, w.g, w.dt, steps)
+        mine = out[b.offsets[i]:b.offsets[i + 1]]
+        assert rel_l2(mine, p.cpu().numpy()) <= tol, i
+        assert abs(obs[i]["norm"] - o1["norm"]) <= tol * 10
+        if dtype == "c128":
+            ref = rt.real_time(c.T, w.psi0, c.opot, w.g, w.dt, 0.0, steps)
+            assert rel_l2(mine, ref) <= 1e-10
+
+
+def test_graph_replay_equals_eager_repeatedly():
+    """Replays of the captured step, with eager work and syncs in between,
+    match the eager launches every time."""
+    import torch
+    ws = _instances(4, 6)
+    b, psi, field, ramps = _batch(ws, "c128")
+    gs, dts = [w.g for w in ws], [w.dt for w in ws]
+    ref = psi.clone()
+    for rep in range(3):
+        b.real_time(psi, field, ramps, gs, dts, 6, use_graph=True, observe=False)
+        b.real_time(ref, field, ramps, gs, dts, 6, use_graph=False, observe=False)
+        torch.cuda.synchronize()
+        x = torch.randn(1000, device="cuda:0").sum().item()   # unrelated eager work
+        assert torch.equal(psi, ref), rep
+
+
+def test_batch_fidelity_grad_matches_single():
+    ws = _instances(3, 8)
+    b, psi, field, ramps = _batch(ws, "c128")
+    import torch
+    tg = [_target(w, 10 + i) for i, w in enumerate(ws)]
+    target = torch.tensor(np.concatenate(tg), dtype=torch.complex128, device="cuda:0")
+    loss, grads = b.fidelity_grad(psi, target, field, ramps, [w.g for w in ws], [w.dt for w in ws], 8)
+    for i, w in enumerate(ws):
+        c = Case(w, "c128")
+        l1, g1 = c.grid.fidelity_grad(c.psi(), c.psi(tg[i]), c.pot, w.g, w.dt, 8)
+        assert abs(loss[i] - l1) <= 1e-13
+        assert np.max(np.abs(grads[i] - g1)) <= 1e-12 * np.max(np.abs(g1))
+
+
+def test_autotune_selects_a_valid_config():
+    from paper_2603_05447_amd import config_count
+    w = configs.small_rf_ramp(n=28)
+    c = Case(w, "c128")
+    best, times = c.grid.autotune(c.psi(), c.pot, w.g, w.dt, reps=3)
+    assert 0 <= best < config_count()
+    assert c.grid.get_config() == best
+    assert all(t > 0 for t in times)
+    assert times[best] == min(times)

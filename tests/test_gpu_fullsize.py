@@ -1,0 +1,110 @@
+"""Full-size parity on the headline workload (1024 x 1024 x 512 RF bubble,
+16,028,656 active sites) in the launch configuration the benchmark uses.
+
+The oracle cannot run the whole grid in a test, so it is evaluated on local
+patches: one RK4 step moves information at most 4 sites (4 stencil stages)
+and one imaginary-time step 2 sites, so the oracle on the active sites of a
+13^3 box around a sampled site reproduces that site's value exactly (the
+truncated patch boundary is 6 sites away).  The imaginary-time result is
+checked up to its global renormalisation factor (a single positive scale).
+Properties that hold at any size (norm after renormalisation, RK4 norm
+conservation) are checked on the whole array."""
+import numpy as np
+import pytest
+
+from oracle import operator as op, itp, realtime as rt
+from oracle.potential import RFRamp
+from workloads import configs, site_ijk
+
+pytestmark = pytest.mark.gpu
+R_PATCH = 6
+
+
+@pytest.fixture(scope="module")
+def c2():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = configs.c2()
+    i, j, k = site_ijk(w.runs)
+    return w, (i, j, k)
+
+
+def _patch(w, ijk, s, R=R_PATCH):
+    i, j, k = ijk
+    ci, cj, ck = i[s], j[s], k[s]
+    sel = (np.abs(i - ci) <= R) & (np.abs(j - cj) <= R) & (np.abs(k - ck) <= R)
+    idx = np.nonzero(sel)[0]
+    lin = (i[idx] * w.box.n[1] + j[idx]) * w.box.n[2] + k[idx]
+    T = op.kinetic_direct(w.box.n, w.box.h, lin)
+    centre = int(np.searchsorted(idx, s))
+    return idx, T, centre
+
+
+def _samples(w, ijk, count=40, seed=0):
+    rng = np.random.default_rng(seed)
+    n = w.n_active
+    lens = w.runs[:, 3] - w.runs[:, 2]
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    s = list(rng.integers(0, n, count))
+    s += [0, n - 1, int(starts[len(starts) // 2]), int(starts[len(starts) // 3] + lens[len(starts) // 3] - 1)]
+    return sorted(set(int(x) for x in s))
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-5)])
+def test_c2_rk4_step_sampled(c2, dtype, tol):
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    w, ijk = c2
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rdt = torch.float64 if dtype == "c128" else torch.float32
+    print(f"C2 full size RK4 sampled parity {dtype}: {w.n_active} sites", flush=True)
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    U = torch.tensor(w.field, dtype=rdt, device="cuda:0")
+    psi = torch.tensor(w.psi0, dtype=cdt, device="cuda:0")
+    d = w.extra["delta_rt"]
+    pot = Potential.rf(U, w.omega, [0.0], [d])
+    g.real_time(psi, pot, w.g, w.dt, 1, observe=False)
+    out = psi.cpu().numpy()
+    got, ref = [], []
+    for s in _samples(w, ijk):
+        idx, T, c = _patch(w, ijk, s)
+        ramp = RFRamp(w.field[idx], w.omega, [0.0], [d])
+        y = rt.rk4_step(T, w.psi0[idx], 0.0, w.dt, ramp, w.g)
+        got.append(out[s])
+        ref.append(y[c])
+    got, ref = np.array(got), np.array(ref)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  sampled rel L2 = {err:.3e}", flush=True)
+    assert err <= tol
+    # any size: RK4 conserves the norm to O(dt^4) per unit time
+    n0 = float(np.sum(np.abs(w.psi0) ** 2)) * w.box.dV
+    g.real_time(psi, pot, w.g, w.dt, 19, observe=False)
+    o = g.observe(psi, pot, 0.0, w.g)
+    assert abs(o["norm"] - n0) <= (1e-9 if dtype == "c128" else 1e-5)
+
+
+def test_c2_imag_time_step_sampled(c2):
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    w, ijk = c2
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    U = torch.tensor(w.field, dtype=torch.float64, device="cuda:0")
+    psi = torch.tensor(w.psi0, dtype=torch.complex128, device="cuda:0")
+    d = w.extra["delta_itp"]
+    obs = g.imag_time(psi, Potential.rf(U, w.omega, [0.0], [d]), w.g, w.dt, 1)
+    assert abs(obs["norm"] - 1.0) < 1e-12
+    out = psi.cpu().numpy()
+    got, ref = [], []
+    for s in _samples(w, ijk, seed=1):
+        idx, T, c = _patch(w, ijk, s)
+        V = np.sqrt((w.field[idx] - d) ** 2 + w.omega ** 2)
+        y, nrm = itp.itp_step(T, w.psi0[idx], itp.propagator(V, w.dt), w.g, w.dt, w.box.dV)
+        ref.append(y[c] * np.sqrt(nrm))      # undo the patch's own renormalisation
+        got.append(out[s])
+    got, ref = np.array(got), np.array(ref)
+    scale = np.real(np.vdot(ref, got)) / np.real(np.vdot(ref, ref))   # the global 1/sqrt(norm)
+    assert scale > 0
+    err = np.linalg.norm(got - scale * ref) / np.linalg.norm(scale * ref)
+    print(f"C2 ITP sampled rel L2 (up to the global scale) = {err:.3e}", flush=True)
+    assert err <= 1e-10
