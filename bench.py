@@ -260,6 +260,45 @@ def bench_batched(args, dev, report):
     torch.cuda.empty_cache()
 
 
+def bench_c5(args, dev, report):
+    """Large thin shell (2048 x 2048 x 1024, ~60M active sites): RK4 in
+    complex64 (FP32 stencil, FP64 reductions) against complex128 from the
+    same start; relative L2 difference and norm drift of each."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    from workloads import configs
+    t = time.time()
+    w = configs.c5()
+    log(f"[bench] C5 inputs: {w.n_active} sites ({time.time() - t:.1f}s)")
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    out = {"workload": w.name, "n_active": w.n_active, "steps": args.c5}
+    n0 = float(np.sum(np.abs(w.psi0) ** 2)) * w.box.dV
+    res = {}
+    for dtype, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
+        U = torch.tensor(w.field, dtype=rdt, device=dev)
+        psi = torch.tensor(w.psi0, dtype=cdt, device=dev)
+        pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
+        g.real_time(psi, pot, w.g, w.dt, 2, observe=False)
+        psi.copy_(torch.tensor(w.psi0, dtype=cdt, device=dev))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        obs = g.real_time(psi, pot, w.g, w.dt, args.c5)
+        el = time.perf_counter() - t
+        res[dtype] = psi.to(torch.complex128).cpu().numpy()
+        out[dtype] = {"s": el, "site_updates_per_s": w.n_active * args.c5 / el,
+                      "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 8 if dtype == "c128" else 4) for i in range(1, 5))
+                      * w.n_active * args.c5 / el / 1e9,
+                      "norm_drift": obs["norm"] - n0, "energy": obs["energy"]}
+        del U, psi
+        g.release_work()
+        torch.cuda.empty_cache()
+    a, b = res["c64"], res["c128"]
+    out["c64_vs_c128_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    ov = np.vdot(b, a)
+    out["c64_vs_c128_phase_aligned"] = float(1.0 - abs(ov) / (np.linalg.norm(a) * np.linalg.norm(b)))
+    report["precision_c5"] = out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +311,7 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=2000)
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--c5", type=int, default=0, help="run the 60M-site FP32-vs-FP64 study for this many steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -295,6 +335,9 @@ def main():
         log(f"[bench] adjoint done: {report['adjoint_c3']['grads_per_s']:.3g} grads/s")
         bench_batched(args, dev, report)
         log("[bench] batched done")
+    if args.c5 > 0:
+        bench_c5(args, dev, report)
+        log("[bench] C5 precision study done")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args)
@@ -333,7 +376,7 @@ def main():
     if "c64" in report:
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
-    for key in ("adjoint_c3", "batched_c4"):
+    for key in ("adjoint_c3", "batched_c4", "precision_c5"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)

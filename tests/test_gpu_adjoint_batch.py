@@ -91,7 +91,12 @@ def test_fidelity_gradient_fp32():
 
 
 def _instances(k=5, steps=10):
+    """Small C4-style instances.  Their boxes are tiny, so a unit norm gives a
+    large density; g is lowered so that dt * (T + V + g|psi|^2) stays inside
+    the RK4 stability region, with a distinct g per instance."""
     ws = [configs.c4_instance(i, n_lo=14, n_hi=26, steps=steps) for i in range(k)]
+    for i, w in enumerate(ws):
+        w.g = 10.0 + 7.0 * i
     return ws
 
 
