@@ -109,6 +109,15 @@ def bench_c2(args, dev, dtype, report):
     R = 8 if dtype == "c128" else 4
     if args.config is not None:
         g.set_config(args.config)
+    tune = None
+    if args.autotune:
+        from paper_2603_05447_amd import config_describe
+        scratch = psi.clone()
+        best, times = g.autotune(scratch, pot_rt, w.g, w.dt, reps=5)
+        del scratch
+        tune = {"best": best, "rk4_ms_per_step": {str(k): times[k] for k in range(len(times))},
+                "variants": {str(k): config_describe(k) for k in range(len(times))}}
+        log(f"[bench] autotune {dtype}: best variant {best}, ms/step {['%.3f' % t for t in times]}")
     # warmup (also builds the chunk tables)
     run_phase_timed(g, psi, pot_itp, pot_rt, w, max(args.warmup, 1), 2 * max(args.warmup, 1))
     torch.cuda.synchronize()
@@ -134,6 +143,7 @@ def bench_c2(args, dev, dtype, report):
                    / (ms_rt * 1e-3) / 1e9},
         "final_norm": obs["norm"],
         "config": g.get_config(),
+        "autotune": tune,
     }
     kernels = {}
     for fam, v in kern.items():
@@ -305,6 +315,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=None, help="launch variant index (default: library default)")
+    ap.add_argument("--autotune", action="store_true", help="time every launch variant and use the fastest")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip complex64, adjoint and batched legs")
@@ -312,6 +323,8 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--c5", type=int, default=0, help="run the 60M-site FP32-vs-FP64 study for this many steps")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -326,6 +339,14 @@ def main():
     dev = torch.device("cuda:0")
     report = {}
     t_start = time.time()
+    if args.calib_copy_mb > 0:
+        x = torch.ones(args.calib_copy_mb * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)      # reads and writes calib_copy_mb MiB each
+        torch.cuda.synchronize()
+        del x, y
+        torch.cuda.empty_cache()
     bench_c2(args, dev, "c128", report)
     log(f"[bench] c128 done: {report['c128']['site_updates_per_s']:.4g} site-updates/s")
     if not args.no_extras:

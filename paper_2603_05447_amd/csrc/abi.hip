@@ -331,7 +331,7 @@ struct Problem {
     p.n_chunks = cs.n_chunks;
     p.n_inst = n_inst;
     p.xcd_map = cfg.xcd;
-    p.pad = 0;
+    p.pstride = (int32_t)max_chunks;
     return p;
   }
 
@@ -530,15 +530,17 @@ gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
     if (_e != hipSuccess) return hip_fail(_e, #expr);       \
   } while (0)
 
+// One RK4 step n (step < 0: the step index is read from the device counter,
+// which is then advanced; used for captured graphs).
 template <typename R>
 gpe_status rk_step(const Ctx& c, const void* y0, const void* field, void* y2, void* y3, void* y4, void* out,
-                   bool obs, gpe_obs* obs_dev) {
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, obs, y0, y0, nullptr, nullptr, field, y2, c.s));
+                   bool obs, gpe_obs* obs_dev, int64_t step) {
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, obs, y0, y0, nullptr, nullptr, field, y2, step, c.s));
   if (obs) LTRY(run_finalize(c.pl, FIN_OBS, obs_dev, c.s));
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, y0, nullptr, nullptr, field, y3, c.s));
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, y0, nullptr, nullptr, field, y4, c.s));
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 4, false, y4, y0, y2, y3, field, out, c.s));
-  LTRY(run_tick(c.pl.step, 1, c.s));
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, y0, nullptr, nullptr, field, y3, step, c.s));
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, y0, nullptr, nullptr, field, y4, step, c.s));
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 4, false, y4, y0, y2, y3, field, out, step, c.s));
+  if (step < 0) LTRY(run_tick(c.pl.step, 1, c.s));
   return GPE_OK;
 }
 
@@ -554,7 +556,7 @@ gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps,
   int64_t k = 0;
   for (int64_t n = 0; n < nsteps; ++n) {
     if (hist && obs_every > 0 && n % obs_every == 0) {
-      LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, true, c.s));
+      LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, true, 0, c.s));
       LTRY(run_finalize(c.pl, FIN_OBS, hist + k * c.P->n_inst, c.s));
       ++k;
     }
@@ -574,11 +576,10 @@ gpe_status drive_rt(const Ctx& c, void* psi, const void* field, int64_t nsteps, 
   void* y2 = cv.take(st);
   void* y3 = cv.take(st);
   void* y4 = cv.take(st);
-  LTRY(run_set_step(c.pl.step, 0, c.s));
   int64_t k = 0;
   for (int64_t n = 0; n < nsteps; ++n) {
     const bool obs = hist && obs_every > 0 && n % obs_every == 0;
-    gpe_status r = rk_step<R>(c, psi, field, y2, y3, y4, psi, obs, obs ? hist + k * c.P->n_inst : nullptr);
+    gpe_status r = rk_step<R>(c, psi, field, y2, y3, y4, psi, obs, obs ? hist + k * c.P->n_inst : nullptr, n);
     if (r != GPE_OK) return r;
     if (obs) ++k;
   }
@@ -586,8 +587,8 @@ gpe_status drive_rt(const Ctx& c, void* psi, const void* field, int64_t nsteps, 
 }
 
 template <typename R>
-gpe_status drive_observe(const Ctx& c, const void* psi, const void* field, bool use_scale) {
-  LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, use_scale, c.s));
+gpe_status drive_observe(const Ctx& c, const void* psi, const void* field, bool use_scale, int64_t step) {
+  LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, use_scale, step, c.s));
   LTRY(run_finalize(c.pl, FIN_OBS, nullptr, c.s));
   return GPE_OK;
 }
@@ -628,10 +629,9 @@ gpe_status drive_adjoint(const Ctx& c, const void* psi0, const void* target, con
   void* cur = cv.take(st);
 
   LTRY(hipMemcpyAsync(cur, psi0, st, hipMemcpyDeviceToDevice, c.s));
-  LTRY(run_set_step(c.pl.step, 0, c.s));
   for (int64_t n = 0; n < nsteps; ++n) {
     if (n % K == 0) LTRY(hipMemcpyAsync(ck[n / K], cur, st, hipMemcpyDeviceToDevice, c.s));
-    gpe_status r = rk_step<R>(c, cur, field, y2, y3, y4, cur, false, nullptr);
+    gpe_status r = rk_step<R>(c, cur, field, y2, y3, y4, cur, false, nullptr, n);
     if (r != GPE_OK) return r;
   }
   if (psi_final) LTRY(hipMemcpyAsync(psi_final, cur, st, hipMemcpyDeviceToDevice, c.s));
@@ -643,21 +643,19 @@ gpe_status drive_adjoint(const Ctx& c, const void* psi0, const void* target, con
   for (int64_t m = nck - 1; m >= 0; --m) {
     const int64_t n0 = m * K, n1 = std::min(n0 + K, nsteps);
     seg[0] = ck[m];
-    LTRY(run_set_step(c.pl.step, n0, c.s));
     for (int64_t r = 0; r + 1 < n1 - n0; ++r) {
-      gpe_status q = rk_step<R>(c, seg[r], field, y2, y3, y4, seg[r + 1], false, nullptr);
+      gpe_status q = rk_step<R>(c, seg[r], field, y2, y3, y4, seg[r + 1], false, nullptr, n0 + r);
       if (q != GPE_OK) return q;
     }
     for (int64_t n = n1 - 1; n >= n0; --n) {
       void* Y1 = seg[n - n0];
-      LTRY(run_set_step(c.pl.step, n, c.s));
-      LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, false, Y1, Y1, nullptr, nullptr, field, y2, c.s));
-      LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, Y1, nullptr, nullptr, field, y3, c.s));
-      LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, Y1, nullptr, nullptr, field, y4, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 4, lam, y4, field, nullptr, lacc, uA, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 3, uA, y3, field, lam, lacc, uB, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 2, uB, y2, field, lam, lacc, uA, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 1, uA, Y1, field, nullptr, lacc, lam, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, false, Y1, Y1, nullptr, nullptr, field, y2, n, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, Y1, nullptr, nullptr, field, y3, n, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, Y1, nullptr, nullptr, field, y4, n, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 4, lam, y4, field, nullptr, lacc, uA, n, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 3, uA, y3, field, lam, lacc, uB, n, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 2, uB, y2, field, lam, lacc, uA, n, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 1, uA, Y1, field, nullptr, lacc, lam, n, c.s));
     }
   }
   LTRY(run_knot_finalize(c.pl, c.P->d_grads, c.s));
@@ -746,7 +744,7 @@ static gpe_status batch_rt_graph(gpe_batch b, const Ctx& c, int dtype, void* psi
     if (e == hipSuccess) {
       Ctx cc = c;
       cc.s = cap;
-      r = rk_step<R>(cc, psi, field, y2, y3, y4, psi, false, nullptr);
+      r = rk_step<R>(cc, psi, field, y2, y3, y4, psi, false, nullptr, -1);
       hipError_t e2 = hipStreamEndCapture(cap, &graph);
       if (r == GPE_OK && e2 != hipSuccess) r = hip_fail(e2, "hipStreamEndCapture");
     } else {
@@ -987,8 +985,8 @@ gpe_status gpe_imag_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_poten
                          : drive_itp<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev);
   if (st != GPE_OK) return st;
   if (final_host) {
-    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false)
-                           : drive_observe<float>(c, psi, pot->field, false);
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false, 0)
+                           : drive_observe<float>(c, psi, pot->field, false, 0);
     if (st != GPE_OK) return st;
     return read_obs(*g->prob, final_host, s);
   }
@@ -1026,8 +1024,9 @@ gpe_status gpe_real_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_poten
                          : drive_rt<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev);
   if (st != GPE_OK) return st;
   if (final_host) {
-    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false)
-                           : drive_observe<float>(c, psi, pot->field, false);
+    // observation at the final time t0 + nsteps dt
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false, nsteps)
+                           : drive_observe<float>(c, psi, pot->field, false, nsteps);
     if (st != GPE_OK) return st;
     return read_obs(*g->prob, final_host, s);
   }
@@ -1055,9 +1054,8 @@ gpe_status gpe_observe(gpe_grid g, gpe_dtype dtype, const void* psi, const gpe_p
   std::vector<InstParams> ps{make_params(pot, &prm, t)};
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
-  if (run_set_step(c.pl.step, 0, s) != hipSuccess) return fail(GPE_ERR_DEVICE, "set_step launch failed");
-  st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false)
-                         : drive_observe<float>(c, psi, pot->field, false);
+  st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false, 0)
+                         : drive_observe<float>(c, psi, pot->field, false, 0);
   if (st != GPE_OK) return st;
   return read_obs(*g->prob, out_host, s);
 }
@@ -1244,8 +1242,9 @@ gpe_status gpe_batch_real_time(gpe_batch b, gpe_dtype dtype, void* psi, const vo
   }
   if (st != GPE_OK) return st;
   if (final_host) {
-    // observation at the final time: the step counter now equals nsteps
-    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, field, false) : drive_observe<float>(c, psi, field, false);
+    // observation at the final time t0 + nsteps dt
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, field, false, nsteps)
+                           : drive_observe<float>(c, psi, field, false, nsteps);
     if (st != GPE_OK) return st;
     return read_obs(*b->prob, final_host, s);
   }

@@ -52,14 +52,14 @@ struct Plan {
   const SegNb* nbs;       // segment lateral offsets
   const Chunk* chunks;
   const InstParams* inst;
-  double* partials;       // n_chunks * NPART
+  double* partials;       // NPART x pstride, component-major: partials[r * pstride + chunk]
   double* knot_acc;       // n_chunks * GPE_MAX_KNOTS
   InstOut* out;           // n_inst
   int64_t* step;          // device step counter
   int32_t n_chunks;
   int32_t n_inst;
   int32_t xcd_map;        // 1: give each XCD a contiguous range of chunks
-  int32_t pad;
+  int32_t pstride;        // stride between partial-sum components (>= n_chunks)
 };
 
 // Compiled launch variants (workgroup size x sites per lane, chunk capacity
@@ -89,19 +89,20 @@ template <typename R> hipError_t run_itp_pass2(const Plan& p, const LaunchConfig
                                                const void* prop, void* psi_raw, hipStream_t s);
 // stage 1..4 of the memory-optimised RK4 step; Y = stencil input, y0 = step start,
 // y2/y3 read by stage 4, out = output (stage 4: may equal y0).  obs: stage 1 also
-// writes observation partials of y0.
+// writes observation partials of y0.  `step` is the step index n (stage time
+// t0 + (n + c_i) dt); step < 0 reads the device step counter instead.
 template <typename R> hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool obs,
                                               const void* Y, const void* y0, const void* y2, const void* y3,
-                                              const void* field, void* out, hipStream_t s);
+                                              const void* field, void* out, int64_t step, hipStream_t s);
 // observation partials (|psi|^2, Re psi^H T psi, V|psi|^2, |psi|^4) of scale*psi
 template <typename R> hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi,
                                              const void* field, double t_offset_steps, bool use_scale,
-                                             hipStream_t s);
+                                             int64_t step, hipStream_t s);
 // adjoint stage (4..1): X = stencil input (lambda for stage 4, else u_i), Y = forward
 // stage state, lam = lambda (site), lacc = running lambda, uout = next u / new lambda
 template <typename R> hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, const void* X,
                                                const void* Y, const void* field, const void* lam, void* lacc,
-                                               void* uout, hipStream_t s);
+                                               void* uout, int64_t step, hipStream_t s);
 
 // pointwise helpers (chunk-parallel, one launch each)
 template <typename R> hipError_t run_make_prop(const Plan& p, const LaunchConfig& cfg, const void* field,

@@ -143,6 +143,7 @@ template <typename R> struct PassArgs {
   C* out;
   C* out2;          // ADJ: running lambda (in/out)
   double c_stage;   // stage time offset in units of dt
+  int64_t step;     // step index; < 0: read the device step counter (graph replay)
   int use_scale;    // OBS: multiply Y by the instance's scale
 };
 
@@ -150,12 +151,21 @@ template <typename R, int BLOCK, int SPT, int OP>
 __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
   using C = typename CT<R>::T;
   constexpr int CH = BLOCK * SPT;
-  constexpr bool ITP = (OP == OP_ITP1 || OP == OP_ITP2);
+  constexpr int NB_CAP = CH / 4;   // lateral-offset descriptors kept in LDS (rest read from global)
   constexpr bool ADJ = (OP >= OP_ADJ4);
+  constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4);
   constexpr bool OBSP = (OP == OP_RK1_OBS || OP == OP_OBS);
   constexpr int NR = OBSP ? 4 : ((OP == OP_ITP2 || ADJ) ? 1 : 0);
+  // per-site streams read at the lane's own site
+  constexpr bool NEED_A = (OP == OP_RK2 || OP == OP_RK3 || OP == OP_RK4 || ADJ);
+  constexpr bool NEED_B = (OP == OP_RK4 || OP == OP_ADJ3 || OP == OP_ADJ2);
+  constexpr bool NEED_C = (OP == OP_RK4);
+  constexpr bool NEED_L = (OP == OP_ADJ3 || OP == OP_ADJ2 || OP == OP_ADJ1);
+  constexpr bool NEED_F = (RK || OP == OP_OBS || ADJ);
+  constexpr bool NEED_P = (OP == OP_ITP2);
   __shared__ C sy[CH + 2];
   __shared__ SegHead sh[CH + 1];
+  __shared__ SegNb snb[NB_CAP];
   __shared__ double red[BLOCK / 64][NR > 0 ? NR : 1];
 
   const int cidx = chunk_index((int)blockIdx.x, (int)gridDim.x, pl.xcd_map);
@@ -167,11 +177,13 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const R cx = (R)ip.cx, cy = (R)ip.cy, cz = (R)ip.cz, cd = (R)ip.cd;
   const int kind = ip.pot_kind;
   const R omega2 = (R)(ip.omega * ip.omega);
-  const double tstage = ip.t0 + ((double)(*pl.step) + a.c_stage) * ip.dt;
+  const int64_t step = a.step >= 0 ? a.step : *pl.step;
+  const double tstage = ip.t0 + ((double)step + a.c_stage) * ip.dt;
   const R delta = (kind == GPE_POT_RF_RAMP) ? (R)delta_at(ip, tstage) : R(0);
   R scale = R(1);
   if (OP == OP_ITP1 || (OP == OP_OBS && a.use_scale)) scale = (R)pl.out[ch.inst].scale;
   const R hg = g * dt * R(0.5);
+  const C zero = cmk<R>(R(0), R(0));
 
   // value of the stencil input at compact site s (ITP1 applies the diagonal half-step on load)
   auto load = [&](int64_t s) -> C {
@@ -187,15 +199,61 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     return v;
   };
 
-  for (int t = threadIdx.x; t <= ch.seg_count; t += BLOCK) sh[t] = pl.heads[ch.seg_begin + t];
+  // ---- phase A: every load that does not depend on the segment search ----
+  C ra[SPT], rb[SPT], rc[SPT], rl[SPT];
+  R rf[SPT], rp[SPT];
+#pragma unroll
+  for (int m = 0; m < SPT; ++m) {
+    const int l = threadIdx.x + m * BLOCK;
+    ra[m] = rb[m] = rc[m] = rl[m] = zero;
+    rf[m] = rp[m] = R(0);
+    if (l < ch.count) {
+      const int64_t s = (int64_t)ch.site_begin + l;
+      if constexpr (NEED_A) ra[m] = a.a[s];
+      if constexpr (NEED_B) rb[m] = a.b[s];
+      if constexpr (NEED_C) rc[m] = a.c[s];
+      if constexpr (NEED_L) rl[m] = a.out2[s];
+      if constexpr (NEED_F) rf[m] = a.field[s];
+      if constexpr (NEED_P) rp[m] = a.prop[s];
+    }
+  }
+  for (int t = threadIdx.x; t <= ch.seg_count; t += BLOCK) {
+    sh[t] = pl.heads[ch.seg_begin + t];
+    if (t < ch.seg_count && t < NB_CAP) snb[t] = pl.nbs[ch.seg_begin + t];
+  }
   for (int t = threadIdx.x; t < ch.count + 2; t += BLOCK) {
     const int64_t s = (int64_t)ch.site_begin - 1 + t;
-    sy[t] = (s >= ib && s < ie) ? load(s) : cmk<R>(R(0), R(0));
+    sy[t] = (s >= ib && s < ie) ? load(s) : zero;
   }
   __syncthreads();
 
+  // ---- phase B1: segment search and the lateral loads of all of the lane's sites ----
   const int nseg = ch.seg_count;
   const int top = nseg > 1 ? (1 << (31 - __clz(nseg - 1))) : 0;
+  int js[SPT];
+  C xm[SPT], xp[SPT], ym[SPT], yp[SPT];
+#pragma unroll
+  for (int m = 0; m < SPT; ++m) {
+    const int l = threadIdx.x + m * BLOCK;
+    js[m] = 0;
+    xm[m] = xp[m] = ym[m] = yp[m] = zero;
+    if (l < ch.count) {
+      const int s = ch.site_begin + l;
+      int j = 0;
+      for (int st = top; st > 0; st >>= 1) {
+        const int cand = j + st;
+        if (cand < nseg && sh[cand].start <= s) j = cand;
+      }
+      js[m] = j;
+      const SegNb nb = (j < NB_CAP) ? snb[j] : pl.nbs[ch.seg_begin + j];
+      if (nb.xm) xm[m] = load((int64_t)s + nb.xm);
+      if (nb.xp) xp[m] = load((int64_t)s + nb.xp);
+      if (nb.ym) ym[m] = load((int64_t)s + nb.ym);
+      if (nb.yp) yp[m] = load((int64_t)s + nb.yp);
+    }
+  }
+
+  // ---- phase B2: arithmetic and stores ----
   double acc[NR > 0 ? NR : 1];
 #pragma unroll
   for (int r = 0; r < (NR > 0 ? NR : 1); ++r) acc[r] = 0.0;
@@ -205,43 +263,32 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     const int l = threadIdx.x + m * BLOCK;
     if (l < ch.count) {
       const int s = ch.site_begin + l;
-      int j = 0;
-      for (int st = top; st > 0; st >>= 1) {
-        const int cand = j + st;
-        if (cand < nseg && sh[cand].start <= s) j = cand;
-      }
-      const SegHead hd = sh[j];
-      const int send = sh[j + 1].start;
-      const SegNb nb = pl.nbs[ch.seg_begin + j];
-      const C zero = cmk<R>(R(0), R(0));
+      const SegHead hd = sh[js[m]];
+      const int send = sh[js[m] + 1].start;
       const C yc = sy[l + 1];
       const C zm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? zero : sy[l];
       const C zp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? zero : sy[l + 2];
-      const C xm = nb.xm ? load((int64_t)s + nb.xm) : zero;
-      const C xp = nb.xp ? load((int64_t)s + nb.xp) : zero;
-      const C ym = nb.ym ? load((int64_t)s + nb.ym) : zero;
-      const C yp = nb.yp ? load((int64_t)s + nb.yp) : zero;
       // T~ y at s
-      const R lr = cx * (xm.x + xp.x) + cy * (ym.x + yp.x) + cz * (zm.x + zp.x) + cd * yc.x;
-      const R li = cx * (xm.y + xp.y) + cy * (ym.y + yp.y) + cz * (zm.y + zp.y) + cd * yc.y;
+      const R lr = cx * (xm[m].x + xp[m].x) + cy * (ym[m].x + yp[m].x) + cz * (zm.x + zp.x) + cd * yc.x;
+      const R li = cx * (xm[m].y + xp[m].y) + cy * (ym[m].y + yp[m].y) + cz * (zm.y + zp.y) + cd * yc.y;
 
       if constexpr (OP == OP_ITP1) {
         a.out[s] = cmk<R>(yc.x - R(0.5) * dt * lr, yc.y - R(0.5) * dt * li);
       } else if constexpr (OP == OP_ITP2) {
         const R qr = yc.x - R(0.5) * dt * lr, qi = yc.y - R(0.5) * dt * li;
-        const R f = a.prop[s] * (R(1) - hg * (qr * qr + qi * qi));
+        const R f = rp[m] * (R(1) - hg * (qr * qr + qi * qi));
         const R wr = qr * f, wi = qi * f;
         a.out[s] = cmk<R>(wr, wi);
         acc[0] += (double)wr * (double)wr + (double)wi * (double)wi;
       } else if constexpr (OP == OP_OBS) {
-        const R V = potential<R>(kind, a.field[s], delta, omega2);
+        const R V = potential<R>(kind, rf[m], delta, omega2);
         const double d = (double)yc.x * (double)yc.x + (double)yc.y * (double)yc.y;
         acc[0] += d;
         acc[1] += (double)yc.x * (double)lr + (double)yc.y * (double)li;
         acc[2] += (double)V * d;
         acc[3] += d * d;
-      } else if constexpr (OP >= OP_RK1 && OP <= OP_RK4) {
-        const R V = potential<R>(kind, a.field[s], delta, omega2);
+      } else if constexpr (RK) {
+        const R V = potential<R>(kind, rf[m], delta, omega2);
         const R dens = yc.x * yc.x + yc.y * yc.y;
         const R w = V + g * dens;
         const R hr = lr + w * yc.x, hi = li + w * yc.y;   // H y
@@ -256,11 +303,11 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
             acc[3] += d * d;
           }
         } else if constexpr (OP == OP_RK2 || OP == OP_RK3) {
-          const C y0 = a.a[s];
+          const C y0 = ra[m];
           const R cc = (OP == OP_RK2) ? R(0.5) * dt : dt;
           a.out[s] = cmk<R>(y0.x + cc * fr, y0.y + cc * fi);
         } else {
-          const C y0 = a.a[s], y2 = a.b[s], y3 = a.c[s];
+          const C y0 = ra[m], y2 = rb[m], y3 = rc[m];
           const R third = R(1) / R(3), c6 = dt / R(6);
           const R orr = third * (y2.x - y0.x + yc.x) + R(2) * third * y3.x + c6 * fr;
           const R oi = third * (y2.y - y0.y + yc.y) + R(2) * third * y3.y + c6 * fi;
@@ -271,8 +318,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         const R fx = (OP == OP_ADJ4) ? R(1) / R(6) : R(1);
         const R ur = fx * yc.x, ui = fx * yc.y;
         const R tur = fx * lr, tui = fx * li;
-        const C Y = a.a[s];
-        const R u0 = a.field[s];
+        const C Y = ra[m];
+        const R u0 = rf[m];
         const R V = potential<R>(kind, u0, delta, omega2);
         const R dVd = dpot_ddelta<R>(kind, u0, delta, omega2);
         const R d2 = Y.x * Y.x + Y.y * Y.y;
@@ -290,13 +337,13 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
           a.out[s] = cmk<R>(third * yc.x + thr, third * yc.y + thi);
           a.out2[s] = cmk<R>(yc.x + thr, yc.y + thi);
         } else if constexpr (OP == OP_ADJ3 || OP == OP_ADJ2) {
-          const C lam = a.b[s];
-          const C lacc = a.out2[s];
+          const C lam = rb[m];
+          const C lacc = rl[m];
           const R bl = (OP == OP_ADJ3) ? R(1) / R(3) : R(1) / R(6);
           a.out[s] = cmk<R>(bl * lam.x + R(0.5) * thr, bl * lam.y + R(0.5) * thi);
           a.out2[s] = cmk<R>(lacc.x + thr, lacc.y + thi);
         } else {
-          const C lacc = a.out2[s];
+          const C lacc = rl[m];
           a.out[s] = cmk<R>(lacc.x + thr, lacc.y + thi);
         }
       }
@@ -326,7 +373,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) pl.partials[(size_t)cidx * NPART + r] = acc[r];
+        for (int r = 0; r < NR; ++r) pl.partials[(size_t)r * pl.pstride + cidx] = acc[r];
       }
     }
   }
@@ -357,6 +404,7 @@ static PassArgs<R> pass_args() {
   a.field = a.prop = nullptr;
   a.out = a.out2 = nullptr;
   a.c_stage = 0.0;
+  a.step = -1;
   a.use_scale = 0;
   return a;
 }
@@ -391,7 +439,7 @@ hipError_t run_itp_pass2(const Plan& p, const LaunchConfig& cfg, const void* tmp
 
 template <typename R>
 hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool obs, const void* Y, const void* y0,
-                        const void* y2, const void* y3, const void* field, void* out, hipStream_t s) {
+                        const void* y2, const void* y3, const void* field, void* out, int64_t step, hipStream_t s) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
   a.Y = (const C*)Y;
@@ -403,6 +451,7 @@ hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool 
   static const double cst[4] = {0.0, 0.5, 0.5, 1.0};
   if (stage < 1 || stage > 4) return hipErrorInvalidValue;
   a.c_stage = cst[stage - 1];
+  a.step = step;
   const int fam = FAM_RK1 + stage - 1;
   timing_before(fam, s);
   hipError_t e;
@@ -418,12 +467,13 @@ hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool 
 
 template <typename R>
 hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi, const void* field,
-                       double t_offset_steps, bool use_scale, hipStream_t s) {
+                       double t_offset_steps, bool use_scale, int64_t step, hipStream_t s) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
   a.Y = (const C*)psi;
   a.field = (const R*)field;
   a.c_stage = t_offset_steps;
+  a.step = step;
   a.use_scale = use_scale ? 1 : 0;
   timing_before(FAM_OBSERVE, s);
   hipError_t e = dispatch_pass<R, OP_OBS>(p, cfg, a, s);
@@ -433,7 +483,7 @@ hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi, 
 
 template <typename R>
 hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, const void* X, const void* Y,
-                         const void* field, const void* lam, void* lacc, void* uout, hipStream_t s) {
+                         const void* field, const void* lam, void* lacc, void* uout, int64_t step, hipStream_t s) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
   a.Y = (const C*)X;
@@ -445,6 +495,7 @@ hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, cons
   static const double cst[4] = {0.0, 0.5, 0.5, 1.0};
   if (stage < 1 || stage > 4) return hipErrorInvalidValue;
   a.c_stage = cst[stage - 1];
+  a.step = step;
   const int fam = FAM_ADJ1 + stage - 1;
   timing_before(fam, s);
   hipError_t e;
@@ -525,7 +576,7 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   if constexpr (OP == PT_OVERLAP) {
     block_sum<256, NR>(acc, red);
     if (threadIdx.x == 0)
-      for (int r = 0; r < NR; ++r) pl.partials[(size_t)cidx * NPART + r] = acc[r];
+      for (int r = 0; r < NR; ++r) pl.partials[(size_t)r * pl.pstride + cidx] = acc[r];
   } else if constexpr (OP == PT_RANGE) {
     for (int off = 32; off > 0; off >>= 1) {
       const double lo = __shfl_xor(acc[0], off, 64), hi = __shfl_xor(acc[1], off, 64);
@@ -543,8 +594,8 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
         lo = red[w][0] < lo ? red[w][0] : lo;
         hi = red[w][1] > hi ? red[w][1] : hi;
       }
-      pl.partials[(size_t)cidx * NPART + 0] = lo;
-      pl.partials[(size_t)cidx * NPART + 1] = hi;
+      pl.partials[cidx] = lo;
+      pl.partials[(size_t)pl.pstride + cidx] = hi;
     }
   }
 }
@@ -609,12 +660,12 @@ hipError_t run_field_range(const Plan& p, const LaunchConfig&, const void* field
 // ---------------------------------------------------------------------------
 // finalize: one workgroup per instance sums its chunks' partials in order
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(const Plan pl, int kind, gpe_obs* obs_dev) {
-  __shared__ double red[4][NPART];
+constexpr int FIN_BLOCK = 1024;
+
+__global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const Plan pl, int kind, gpe_obs* obs_dev) {
+  __shared__ double red[FIN_BLOCK / 64][NPART];
   const int inst = (int)blockIdx.x;
   const InstParams& ip = pl.inst[inst];
-  double acc[NPART];
-  const bool range = (kind == FIN_RANGE);
   if (kind == FIN_LOSS) {
     if (threadIdx.x == 0) {
       InstOut& o = pl.out[inst];
@@ -622,17 +673,30 @@ __global__ __launch_bounds__(256) void k_finalize(const Plan pl, int kind, gpe_o
     }
     return;
   }
+  const int c0 = ip.chunk_begin, c1 = ip.chunk_begin + ip.chunk_count;
+  const size_t ps = (size_t)pl.pstride;
+  const bool range = (kind == FIN_RANGE);
+  const int nr = (kind == FIN_OBS) ? 4 : ((kind == FIN_NORM_SCALE) ? 1 : 2);
+  double acc[NPART];
   acc[0] = range ? 1e300 : 0.0;
   acc[1] = range ? -1e300 : 0.0;
   acc[2] = acc[3] = 0.0;
-  for (int c = ip.chunk_begin + (int)threadIdx.x; c < ip.chunk_begin + ip.chunk_count; c += 256) {
-    const double* q = pl.partials + (size_t)c * NPART;
-    if (range) {
-      acc[0] = q[0] < acc[0] ? q[0] : acc[0];
-      acc[1] = q[1] > acc[1] ? q[1] : acc[1];
-    } else {
+  // component-major partials: each pass of the loop is a coalesced read; 8
+  // independent loads are issued before they are added in a fixed order
+  constexpr int U = 8;
+  for (int base = c0; base < c1; base += FIN_BLOCK * U) {
+    for (int r = 0; r < nr; ++r) {
+      double v[U];
 #pragma unroll
-      for (int r = 0; r < NPART; ++r) acc[r] += q[r];
+      for (int u = 0; u < U; ++u) {
+        const int c = base + (int)threadIdx.x + u * FIN_BLOCK;
+        v[u] = (c < c1) ? pl.partials[r * ps + c] : (range ? (r == 0 ? 1e300 : -1e300) : 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (range) acc[r] = (r == 0) ? (v[u] < acc[r] ? v[u] : acc[r]) : (v[u] > acc[r] ? v[u] : acc[r]);
+        else acc[r] += v[u];
+      }
     }
   }
   if (range) {
@@ -648,7 +712,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Plan pl, int kind, gpe_o
     __syncthreads();
     if (threadIdx.x == 0) {
       double lo = red[0][0], hi = red[0][1];
-      for (int w = 1; w < 4; ++w) {
+      for (int w = 1; w < FIN_BLOCK / 64; ++w) {
         lo = red[w][0] < lo ? red[w][0] : lo;
         hi = red[w][1] > hi ? red[w][1] : hi;
       }
@@ -657,7 +721,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Plan pl, int kind, gpe_o
     }
     return;
   }
-  block_sum<256, NPART>(acc, red);
+  block_sum<FIN_BLOCK, NPART>(acc, red);
   if (threadIdx.x != 0) return;
   InstOut& o = pl.out[inst];
   const double dV = ip.dV;
@@ -685,7 +749,7 @@ __global__ __launch_bounds__(256) void k_finalize(const Plan pl, int kind, gpe_o
 
 hipError_t run_finalize(const Plan& p, int kind, gpe_obs* obs_dev, hipStream_t s) {
   timing_before(FAM_FINALIZE, s);
-  hipLaunchKernelGGL(k_finalize, dim3(p.n_inst), dim3(256), 0, s, p, kind, obs_dev);
+  hipLaunchKernelGGL(k_finalize, dim3(p.n_inst), dim3(FIN_BLOCK), 0, s, p, kind, obs_dev);
   hipError_t e = hipGetLastError();
   timing_after(FAM_FINALIZE, s);
   return e;
@@ -803,11 +867,11 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
   template hipError_t run_itp_pass2<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
                                        hipStream_t);                                                         \
   template hipError_t run_rk_stage<R>(const Plan&, const LaunchConfig&, int, bool, const void*, const void*, \
-                                      const void*, const void*, const void*, void*, hipStream_t);            \
+                                      const void*, const void*, const void*, void*, int64_t, hipStream_t);   \
   template hipError_t run_observe<R>(const Plan&, const LaunchConfig&, const void*, const void*, double, bool, \
-                                     hipStream_t);                                                           \
+                                     int64_t, hipStream_t);                                                  \
   template hipError_t run_adj_stage<R>(const Plan&, const LaunchConfig&, int, const void*, const void*,      \
-                                       const void*, const void*, void*, void*, hipStream_t);                 \
+                                       const void*, const void*, void*, void*, int64_t, hipStream_t);        \
   template hipError_t run_make_prop<R>(const Plan&, const LaunchConfig&, const void*, void*, hipStream_t);   \
   template hipError_t run_apply_scale<R>(const Plan&, const LaunchConfig&, void*, hipStream_t);              \
   template hipError_t run_overlap<R>(const Plan&, const LaunchConfig&, const void*, const void*, hipStream_t); \
