@@ -228,7 +228,10 @@ gpe_status gpe_batch_real_time(gpe_batch batch, gpe_dtype dtype, void* psi, cons
                                gpe_obs* final_host);
 
 /* Batched gpe_fidelity_grad: loss_host[n], grad_host[n x GPE_MAX_KNOTS]
- * (instance i's gradient at grad_host + i*GPE_MAX_KNOTS, n_knots entries). */
+ * (instance i's gradient at grad_host + i*GPE_MAX_KNOTS, n_knots entries).
+ * use_graph != 0: the forward sweep replays the captured step graph of
+ * gpe_batch_real_time (checkpoint copies are enqueued between replays); the
+ * reverse sweep is launched eagerly. */
 gpe_status gpe_batch_fidelity_grad(gpe_batch batch, gpe_dtype dtype, const void* psi0, const void* psi_target,
                                    const void* field, const gpe_ramp* ramps, const gpe_params* params,
                                    double t0, int64_t nsteps, int64_t ckpt_every, int32_t use_graph,

@@ -334,7 +334,7 @@ class Batch:
         return [_obs_dict(o) for o in obs] if observe else None
 
     def fidelity_grad(self, psi0: torch.Tensor, target: torch.Tensor, field: torch.Tensor, ramps, gs, dts,
-                      steps: int, t0: float = 0.0, ckpt_every: int = 0, stream=None):
+                      steps: int, t0: float = 0.0, ckpt_every: int = 0, use_graph: bool = False, stream=None):
         dt_ = _dtype_of(psi0)
         ra, keep = self._ramps(ramps)
         pa = self._params(gs, dts)
@@ -344,7 +344,8 @@ class Batch:
         loss = (C.c_double * n)()
         grad = (C.c_double * (n * L.GPE_MAX_KNOTS))()
         check(L.load().gpe_batch_fidelity_grad(self._h, dt_, psi0.data_ptr(), target.data_ptr(), field.data_ptr(),
-                                               ra, pa, float(t0), int(steps), int(ckpt_every), 0, w.data_ptr(),
+                                               ra, pa, float(t0), int(steps), int(ckpt_every),
+                                               1 if use_graph else 0, w.data_ptr(),
                                                w.numel(), _stream(stream), loss, grad))
         g = np.array(grad[:], dtype=np.float64).reshape(n, L.GPE_MAX_KNOTS)
         return np.array(loss[:]), [g[i, :len(ramps[i][1])] for i in range(n)]

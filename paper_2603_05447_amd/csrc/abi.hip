@@ -609,9 +609,50 @@ gpe_status read_obs(Problem& P, gpe_obs* out_host, hipStream_t s) {
 }
 
 // adjoint: loss and knot gradients, fully on the device
+// Captured graph of one in-place RK4 step of psi (scratch y2, y3, y4); the
+// step index comes from the device counter, so one graph serves every step.
+template <typename R>
+static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* field, void* y2, void* y3, void* y4,
+                             hipGraphExec_t* out) {
+  Problem& P = *c.P;
+  Problem::GraphKey key{psi, field, y2, dtype, P.config};
+  auto it = P.graphs.find(key);
+  if (it != P.graphs.end()) {
+    *out = it->second;
+    return GPE_OK;
+  }
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  gpe_status r = GPE_OK;
+  if (e == hipSuccess) {
+    Ctx cc = c;
+    cc.s = cap;
+    r = rk_step<R>(cc, psi, field, y2, y3, y4, psi, false, nullptr, -1);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (r == GPE_OK && e2 != hipSuccess) r = hip_fail(e2, "hipStreamEndCapture");
+  } else {
+    r = hip_fail(e, "hipStreamBeginCapture");
+  }
+  if (r == GPE_OK) {
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) r = hip_fail(e, "hipGraphInstantiate");
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  if (r != GPE_OK) return r;
+  P.graphs[key] = exec;
+  *out = exec;
+  return GPE_OK;
+}
+
+// use_graph: the first forward sweep replays a captured step graph (the
+// checkpoint copies run eagerly between replays); the reverse sweep is eager.
 template <typename R>
 gpe_status drive_adjoint(const Ctx& c, const void* psi0, const void* target, const void* field, int64_t nsteps,
-                         int64_t ckpt_every, void* work, void* psi_final) {
+                         int64_t ckpt_every, void* work, void* psi_final, bool use_graph = false) {
   const int64_t K = ckpt_interval(nsteps, ckpt_every);
   const int64_t nck = (std::max<int64_t>(nsteps, 1) + K - 1) / K;
   const size_t st = (size_t)c.P->total * 2 * sizeof(R);
@@ -629,10 +670,20 @@ gpe_status drive_adjoint(const Ctx& c, const void* psi0, const void* target, con
   void* cur = cv.take(st);
 
   LTRY(hipMemcpyAsync(cur, psi0, st, hipMemcpyDeviceToDevice, c.s));
+  hipGraphExec_t fwd = nullptr;
+  if (use_graph) {
+    gpe_status r = step_graph<R>(c, sizeof(R) == 8 ? GPE_C128 : GPE_C64, cur, field, y2, y3, y4, &fwd);
+    if (r != GPE_OK) return r;
+    LTRY(run_set_step(c.pl.step, 0, c.s));
+  }
   for (int64_t n = 0; n < nsteps; ++n) {
     if (n % K == 0) LTRY(hipMemcpyAsync(ck[n / K], cur, st, hipMemcpyDeviceToDevice, c.s));
-    gpe_status r = rk_step<R>(c, cur, field, y2, y3, y4, cur, false, nullptr, n);
-    if (r != GPE_OK) return r;
+    if (fwd) {
+      LTRY(hipGraphLaunch(fwd, c.s));
+    } else {
+      gpe_status r = rk_step<R>(c, cur, field, y2, y3, y4, cur, false, nullptr, n);
+      if (r != GPE_OK) return r;
+    }
   }
   if (psi_final) LTRY(hipMemcpyAsync(psi_final, cur, st, hipMemcpyDeviceToDevice, c.s));
   LTRY(run_overlap<R>(c.pl, c.cfg, target, cur, c.s));
@@ -722,43 +773,15 @@ static gpe_status rt_stability(const Ctx& c, const std::vector<InstParams>& ps, 
 }
 
 template <typename R>
-static gpe_status batch_rt_graph(gpe_batch b, const Ctx& c, int dtype, void* psi, const void* field, int64_t nsteps,
-                                 void* work) {
-  Problem& P = *b->prob;
-  Problem::GraphKey key{psi, field, work, dtype, P.config};
+static gpe_status batch_rt_graph(const Ctx& c, int dtype, void* psi, const void* field, int64_t nsteps, void* work) {
+  Carver cv(work);
+  const size_t st = (size_t)c.P->total * 2 * sizeof(R);
+  void* y2 = cv.take(st);
+  void* y3 = cv.take(st);
+  void* y4 = cv.take(st);
   hipGraphExec_t exec = nullptr;
-  auto it = P.graphs.find(key);
-  if (it != P.graphs.end()) {
-    exec = it->second;
-  } else {
-    Carver cv(work);
-    const size_t st = (size_t)P.total * 2 * sizeof(R);
-    void* y2 = cv.take(st);
-    void* y3 = cv.take(st);
-    void* y4 = cv.take(st);
-    hipStream_t cap = nullptr;
-    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    gpe_status r = GPE_OK;
-    if (e == hipSuccess) {
-      Ctx cc = c;
-      cc.s = cap;
-      r = rk_step<R>(cc, psi, field, y2, y3, y4, psi, false, nullptr, -1);
-      hipError_t e2 = hipStreamEndCapture(cap, &graph);
-      if (r == GPE_OK && e2 != hipSuccess) r = hip_fail(e2, "hipStreamEndCapture");
-    } else {
-      r = hip_fail(e, "hipStreamBeginCapture");
-    }
-    if (r == GPE_OK) {
-      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) r = hip_fail(e, "hipGraphInstantiate");
-    }
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cap);
-    if (r != GPE_OK) return r;
-    P.graphs[key] = exec;
-  }
+  gpe_status r = step_graph<R>(c, dtype, psi, field, y2, y3, y4, &exec);
+  if (r != GPE_OK) return r;
   HIP_TRY(run_set_step(c.pl.step, 0, c.s));
   for (int64_t n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(exec, c.s));
   return GPE_OK;
@@ -1234,8 +1257,8 @@ gpe_status gpe_batch_real_time(gpe_batch b, gpe_dtype dtype, void* psi, const vo
     if (st != GPE_OK) return st;
   }
   if (use_graph) {
-    st = dtype == GPE_C128 ? batch_rt_graph<double>(b, c, dtype, psi, field, nsteps, work)
-                           : batch_rt_graph<float>(b, c, dtype, psi, field, nsteps, work);
+    st = dtype == GPE_C128 ? batch_rt_graph<double>(c, dtype, psi, field, nsteps, work)
+                           : batch_rt_graph<float>(c, dtype, psi, field, nsteps, work);
   } else {
     st = dtype == GPE_C128 ? drive_rt<double>(c, psi, field, nsteps, work, 0, nullptr)
                            : drive_rt<float>(c, psi, field, nsteps, work, 0, nullptr);
@@ -1255,7 +1278,6 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi
                                    const void* field, const gpe_ramp* ramps, const gpe_params* prms, double t0,
                                    int64_t nsteps, int64_t ckpt_every, int32_t use_graph, void* work,
                                    size_t work_bytes, void* stream, double* loss_host, double* grad_host) {
-  (void)use_graph;
   if (!b) return fail(GPE_ERR_ARG, "batch is NULL");
   gpe_status st = check_dtype(dtype);
   if (st == GPE_OK) st = check_ptr(psi0, "psi0");
@@ -1276,8 +1298,9 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi
   if (st != GPE_OK) return st;
   st = b->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
-  st = dtype == GPE_C128 ? drive_adjoint<double>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr)
-                         : drive_adjoint<float>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr);
+  st = dtype == GPE_C128
+           ? drive_adjoint<double>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr, use_graph != 0)
+           : drive_adjoint<float>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr, use_graph != 0);
   if (st != GPE_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));
   return read_loss_grad(*b->prob, loss_host, grad_host, 0);

@@ -150,13 +150,15 @@ def test_graph_replay_equals_eager_repeatedly():
         assert torch.equal(psi, ref), rep
 
 
-def test_batch_fidelity_grad_matches_single():
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_fidelity_grad_matches_single(use_graph):
     ws = _instances(3, 8)
     b, psi, field, ramps = _batch(ws, "c128")
     import torch
     tg = [_target(w, 10 + i) for i, w in enumerate(ws)]
     target = torch.tensor(np.concatenate(tg), dtype=torch.complex128, device="cuda:0")
-    loss, grads = b.fidelity_grad(psi, target, field, ramps, [w.g for w in ws], [w.dt for w in ws], 8)
+    loss, grads = b.fidelity_grad(psi, target, field, ramps, [w.g for w in ws], [w.dt for w in ws], 8,
+                                  use_graph=use_graph)
     for i, w in enumerate(ws):
         c = Case(w, "c128")
         l1, g1 = c.grid.fidelity_grad(c.psi(), c.psi(tg[i]), c.pot, w.g, w.dt, 8)
