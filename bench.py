@@ -33,8 +33,12 @@ HBM_PEAK_GBPS = 8000.0
 
 # algorithmic bytes per active site per launch (each input read once from HBM,
 # each output written once), by kernel family; R = bytes of a real, C = 2R
-def algo_bytes(fam: str, R: int) -> int:
+def algo_bytes(fam: str, R: int, scheme: int = 0) -> int:
     C = 2 * R
+    if scheme == 1 and fam == "rk_stage2":
+        return 2 * C + R + 2 * C         # y2, y0, U -> y3, A
+    if scheme == 1 and fam == "rk_stage4":
+        return 2 * C + R + C             # y4, A, U -> y0
     table = {
         "itp_pass1": C + R + C,          # psi, P -> tmp
         "itp_pass2": C + R + C,          # tmp, P -> psi
@@ -104,6 +108,7 @@ def run_phase_timed(g, psi, pot_itp, pot_rt, w, k_itp, k_rt):
 def bench_c2(args, dev, dtype, report):
     import torch
     from paper_2603_05447_amd import KernelTimer
+    from paper_2603_05447_amd import config_describe
     w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, dtype)
     n = w.n_active
     R = 8 if dtype == "c128" else 4
@@ -116,10 +121,11 @@ def bench_c2(args, dev, dtype, report):
         best, times = g.autotune(scratch, pot_rt, w.g, w.dt, reps=5)
         del scratch
         tune = {"best": best, "rk4_ms_per_step": {str(k): times[k] for k in range(len(times))},
-                "variants": {str(k): config_describe(k) for k in range(len(times))}}
+                        "variants": {str(k): config_describe(k) for k in range(len(times))}}
         log(f"[bench] autotune {dtype}: best variant {best}, ms/step {['%.3f' % t for t in times]}")
     # warmup (also builds the chunk tables)
     run_phase_timed(g, psi, pot_itp, pot_rt, w, max(args.warmup, 1), 2 * max(args.warmup, 1))
+    scheme = config_describe(g.get_config())["rk_scheme"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with KernelTimer() as kt:
@@ -139,8 +145,10 @@ def bench_c2(args, dev, dtype, report):
                 "eff_GBps": 2 * algo_bytes("itp_pass1", R) * n * args.steps / (ms_itp * 1e-3) / 1e9},
         "rt_rk4": {"ms_per_step": ms_rt / (2 * args.steps),
                    "site_updates_per_s": n * 2 * args.steps / (ms_rt * 1e-3),
-                   "eff_GBps": sum(algo_bytes(f"rk_stage{i}", R) for i in range(1, 5)) * n * 2 * args.steps
-                   / (ms_rt * 1e-3) / 1e9},
+                   "eff_GBps": sum(algo_bytes(f"rk_stage{i}", R, scheme) for i in range(1, 5)) * n * 2 * args.steps
+                   / (ms_rt * 1e-3) / 1e9,
+                   "algo_bytes_per_site_step": sum(algo_bytes(f"rk_stage{i}", R, scheme) for i in range(1, 5)),
+                   "rk_scheme": scheme},
         "final_norm": obs["norm"],
         "config": g.get_config(),
         "autotune": tune,
@@ -150,7 +158,7 @@ def bench_c2(args, dev, dtype, report):
         if v["launches"] == 0:
             continue
         avg_us = 1e3 * v["total_ms"] / v["launches"]
-        b = algo_bytes(fam, R) * n
+        b = algo_bytes(fam, R, scheme) * n
         kernels[fam] = {"launches": v["launches"], "avg_us": avg_us, "total_ms": v["total_ms"],
                         "algo_bytes_per_launch": b, "GBps": (b / (avg_us * 1e-6) / 1e9) if b else None}
     res["kernels"] = kernels
@@ -254,6 +262,8 @@ def bench_batched(args, dev, report):
     ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
     gs, dts = [w.g for w in ws], [w.dt for w in ws]
     work = torch.empty(b.work_bytes(GPE_C64, GPE_MODE_RT, 1), dtype=torch.uint8, device=dev)
+    from paper_2603_05447_amd import config_describe
+    scheme = config_describe(0)["rk_scheme"]     # batches use launch variant 0 unless set
     out = {}
     for use_graph in (False, True):
         b.real_time(psi, field, ramps, gs, dts, 5, use_graph=use_graph, work=work, observe=False)
@@ -263,7 +273,8 @@ def bench_batched(args, dev, report):
         el = time.perf_counter() - t
         out["graph" if use_graph else "eager"] = {
             "s": el, "site_updates_per_s": b.total * args.batch_steps / el,
-            "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 4) for i in range(1, 5)) * b.total * args.batch_steps / el / 1e9,
+            "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 4, scheme) for i in range(1, 5)) * b.total * args.batch_steps
+            / el / 1e9,
             "norm_min": min(o["norm"] for o in obs), "norm_max": max(o["norm"] for o in obs)}
     report["batched_c4"] = {"instances": len(ws), "total_sites": b.total, "steps": args.batch_steps, **out}
     del b, grids, psi, field, work
@@ -275,7 +286,7 @@ def bench_c5(args, dev, report):
     complex64 (FP32 stencil, FP64 reductions) against complex128 from the
     same start; relative L2 difference and norm drift of each."""
     import torch
-    from paper_2603_05447_amd import Grid, Potential
+    from paper_2603_05447_amd import Grid, Potential, config_describe
     from workloads import configs
     t = time.time()
     w = configs.c5()
@@ -296,7 +307,8 @@ def bench_c5(args, dev, report):
         el = time.perf_counter() - t
         res[dtype] = psi.to(torch.complex128).cpu().numpy()
         out[dtype] = {"s": el, "site_updates_per_s": w.n_active * args.c5 / el,
-                      "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 8 if dtype == "c128" else 4) for i in range(1, 5))
+                      "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 8 if dtype == "c128" else 4,
+                                                 config_describe(g.get_config())["rk_scheme"]) for i in range(1, 5))
                       * w.n_active * args.c5 / el / 1e9,
                       "norm_drift": obs["norm"] - n0, "energy": obs["energy"]}
         del U, psi

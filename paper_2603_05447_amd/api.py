@@ -376,9 +376,9 @@ def config_count() -> int:
 
 
 def config_describe(i: int):
-    b, s, x = C.c_int32(), C.c_int32(), C.c_int32()
-    check(L.load().gpe_config_describe(int(i), C.byref(b), C.byref(s), C.byref(x)))
-    return {"block": b.value, "sites_per_lane": s.value, "xcd_map": x.value}
+    b, s, x, r = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    check(L.load().gpe_config_describe(int(i), C.byref(b), C.byref(s), C.byref(x), C.byref(r)))
+    return {"block": b.value, "sites_per_lane": s.value, "xcd_map": x.value, "rk_scheme": r.value}
 
 
 class KernelTimer:

@@ -532,14 +532,23 @@ gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
 
 // One RK4 step n (step < 0: the step index is read from the device counter,
 // which is then advanced; used for captured graphs).
+// Scratch buffers b1, b2, b3 (each one state vector).  Scheme 0 keeps y2, y3,
+// y4 in b1, b2, b3; scheme 1 keeps y2 in b1, y3 in b2, A in b3 and writes y4
+// over y2 (b1) once stage 2 has folded y2 into A.
 template <typename R>
-gpe_status rk_step(const Ctx& c, const void* y0, const void* field, void* y2, void* y3, void* y4, void* out,
+gpe_status rk_step(const Ctx& c, const void* y0, const void* field, void* b1, void* b2, void* b3, void* out,
                    bool obs, gpe_obs* obs_dev, int64_t step) {
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, obs, y0, y0, nullptr, nullptr, field, y2, step, c.s));
+  LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, obs, y0, y0, nullptr, nullptr, field, b1, step, c.s));
   if (obs) LTRY(run_finalize(c.pl, FIN_OBS, obs_dev, c.s));
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, y0, nullptr, nullptr, field, y3, step, c.s));
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, y0, nullptr, nullptr, field, y4, step, c.s));
-  LTRY(run_rk_stage<R>(c.pl, c.cfg, 4, false, y4, y0, y2, y3, field, out, step, c.s));
+  if (c.cfg.scheme == 1) {
+    LTRY(run_rk_stage2_fold<R>(c.pl, c.cfg, b1, y0, field, b2, b3, step, c.s));
+    LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, b2, y0, nullptr, nullptr, field, b1, step, c.s));
+    LTRY(run_rk_stage4_fold<R>(c.pl, c.cfg, b1, b3, field, out, step, c.s));
+  } else {
+    LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, b1, y0, nullptr, nullptr, field, b2, step, c.s));
+    LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, b2, y0, nullptr, nullptr, field, b3, step, c.s));
+    LTRY(run_rk_stage<R>(c.pl, c.cfg, 4, false, b3, y0, b1, b2, field, out, step, c.s));
+  }
   if (step < 0) LTRY(run_tick(c.pl.step, 1, c.s));
   return GPE_OK;
 }
@@ -1310,12 +1319,13 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi
 
 int32_t gpe_config_count(void) { return config_count(); }
 
-gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* spt, int32_t* xcd) {
+gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* spt, int32_t* xcd, int32_t* rk_scheme) {
   if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
   LaunchConfig c = config_get(config);
   if (block) *block = c.block;
   if (spt) *spt = c.spt;
   if (xcd) *xcd = c.xcd;
+  if (rk_scheme) *rk_scheme = c.scheme;
   return GPE_OK;
 }
 

@@ -63,11 +63,16 @@ struct Plan {
 };
 
 // Compiled launch variants (workgroup size x sites per lane, chunk capacity
-// = product) and the XCD mapping flag.
+// = product), the XCD mapping flag, and the RK4 storage scheme:
+//   scheme 0: App. A form; stage 4 reads y0, y2, y3 and forms
+//             -y0/3 + y2/3 + 2 y3/3 + y4/3 + dt/6 k4          (240 B/site/step in complex128)
+//   scheme 1: stage 2 also writes A = (-y0 + y2 + 2 y3)/3, stage 4 reads A only
+//             and forms A + y4/3 + dt/6 k4; y4 reuses y2's buffer (224 B/site/step)
 struct LaunchConfig {
   int block;
   int spt;
   int xcd;
+  int scheme;
 };
 int config_count();
 LaunchConfig config_get(int i);
@@ -94,6 +99,14 @@ template <typename R> hipError_t run_itp_pass2(const Plan& p, const LaunchConfig
 template <typename R> hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool obs,
                                               const void* Y, const void* y0, const void* y2, const void* y3,
                                               const void* field, void* out, int64_t step, hipStream_t s);
+// scheme-1 stages: stage 2 writes y3 = y0 + dt/2 f(Y) and A = (-y0 + Y + 2 y3)/3;
+// stage 4 writes A + Y/3 + dt/6 f(Y)
+template <typename R> hipError_t run_rk_stage2_fold(const Plan& p, const LaunchConfig& cfg, const void* Y,
+                                                    const void* y0, const void* field, void* y3, void* A,
+                                                    int64_t step, hipStream_t s);
+template <typename R> hipError_t run_rk_stage4_fold(const Plan& p, const LaunchConfig& cfg, const void* Y,
+                                                    const void* A, const void* field, void* out, int64_t step,
+                                                    hipStream_t s);
 // observation partials (|psi|^2, Re psi^H T psi, V|psi|^2, |psi|^4) of scale*psi
 template <typename R> hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi,
                                              const void* field, double t_offset_steps, bool use_scale,

@@ -42,7 +42,8 @@ template <typename R> __device__ __forceinline__ typename CT<R>::T cmk(R a, R b)
 // launch variants
 // ---------------------------------------------------------------------------
 static const LaunchConfig kConfigs[] = {
-    {256, 2, 1}, {256, 1, 1}, {256, 4, 1}, {512, 1, 1}, {512, 2, 1}, {1024, 1, 1}, {256, 2, 0}, {512, 2, 0},
+    {256, 2, 1, 1}, {256, 1, 1, 1}, {256, 4, 1, 1}, {512, 1, 1, 1}, {512, 2, 1, 1}, {1024, 1, 1, 1},
+    {256, 2, 0, 1}, {512, 2, 0, 1}, {256, 2, 1, 0}, {512, 1, 1, 0},
 };
 int config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
 LaunchConfig config_get(int i) { return kConfigs[i]; }
@@ -130,6 +131,8 @@ enum PassOp {
   OP_ADJ3,
   OP_ADJ2,
   OP_ADJ1,
+  OP_RK2F,       // as OP_RK2, and out2 = (-y0 + Y + 2 out)/3
+  OP_RK4F,       // out = A + Y/3 + dt/6 f(t + dt, Y)    (A read through `a`)
 };
 
 template <typename R> struct PassArgs {
@@ -152,12 +155,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   using C = typename CT<R>::T;
   constexpr int CH = BLOCK * SPT;
   constexpr int NB_CAP = CH / 4;   // lateral-offset descriptors kept in LDS (rest read from global)
-  constexpr bool ADJ = (OP >= OP_ADJ4);
-  constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4);
+  constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
+  constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4) || OP == OP_RK2F || OP == OP_RK4F;
   constexpr bool OBSP = (OP == OP_RK1_OBS || OP == OP_OBS);
   constexpr int NR = OBSP ? 4 : ((OP == OP_ITP2 || ADJ) ? 1 : 0);
   // per-site streams read at the lane's own site
-  constexpr bool NEED_A = (OP == OP_RK2 || OP == OP_RK3 || OP == OP_RK4 || ADJ);
+  constexpr bool NEED_A = (OP == OP_RK2 || OP == OP_RK3 || OP == OP_RK4 || ADJ || OP == OP_RK2F || OP == OP_RK4F);
   constexpr bool NEED_B = (OP == OP_RK4 || OP == OP_ADJ3 || OP == OP_ADJ2);
   constexpr bool NEED_C = (OP == OP_RK4);
   constexpr bool NEED_L = (OP == OP_ADJ3 || OP == OP_ADJ2 || OP == OP_ADJ1);
@@ -306,6 +309,16 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
           const C y0 = ra[m];
           const R cc = (OP == OP_RK2) ? R(0.5) * dt : dt;
           a.out[s] = cmk<R>(y0.x + cc * fr, y0.y + cc * fi);
+        } else if constexpr (OP == OP_RK2F) {
+          const C y0 = ra[m];
+          const R y3r = y0.x + R(0.5) * dt * fr, y3i = y0.y + R(0.5) * dt * fi;
+          const R third = R(1) / R(3);
+          a.out[s] = cmk<R>(y3r, y3i);
+          a.out2[s] = cmk<R>(third * (yc.x - y0.x) + R(2) * third * y3r, third * (yc.y - y0.y) + R(2) * third * y3i);
+        } else if constexpr (OP == OP_RK4F) {
+          const C A = ra[m];
+          const R third = R(1) / R(3), c6 = dt / R(6);
+          a.out[s] = cmk<R>(A.x + third * yc.x + c6 * fr, A.y + third * yc.y + c6 * fi);
         } else {
           const C y0 = ra[m], y2 = rb[m], y3 = rc[m];
           const R third = R(1) / R(3), c6 = dt / R(6);
@@ -462,6 +475,41 @@ hipError_t run_rk_stage(const Plan& p, const LaunchConfig& cfg, int stage, bool 
     default: e = dispatch_pass<R, OP_RK4>(p, cfg, a, s); break;
   }
   timing_after(fam, s);
+  return e;
+}
+
+template <typename R>
+hipError_t run_rk_stage2_fold(const Plan& p, const LaunchConfig& cfg, const void* Y, const void* y0, const void* field,
+                              void* y3, void* A, int64_t step, hipStream_t s) {
+  using C = typename CT<R>::T;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)Y;
+  a.a = (const C*)y0;
+  a.field = (const R*)field;
+  a.out = (C*)y3;
+  a.out2 = (C*)A;
+  a.c_stage = 0.5;
+  a.step = step;
+  timing_before(FAM_RK2, s);
+  hipError_t e = dispatch_pass<R, OP_RK2F>(p, cfg, a, s);
+  timing_after(FAM_RK2, s);
+  return e;
+}
+
+template <typename R>
+hipError_t run_rk_stage4_fold(const Plan& p, const LaunchConfig& cfg, const void* Y, const void* A, const void* field,
+                              void* out, int64_t step, hipStream_t s) {
+  using C = typename CT<R>::T;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)Y;
+  a.a = (const C*)A;
+  a.field = (const R*)field;
+  a.out = (C*)out;
+  a.c_stage = 1.0;
+  a.step = step;
+  timing_before(FAM_RK4, s);
+  hipError_t e = dispatch_pass<R, OP_RK4F>(p, cfg, a, s);
+  timing_after(FAM_RK4, s);
   return e;
 }
 
@@ -868,6 +916,10 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
                                        hipStream_t);                                                         \
   template hipError_t run_rk_stage<R>(const Plan&, const LaunchConfig&, int, bool, const void*, const void*, \
                                       const void*, const void*, const void*, void*, int64_t, hipStream_t);   \
+  template hipError_t run_rk_stage2_fold<R>(const Plan&, const LaunchConfig&, const void*, const void*,       \
+                                            const void*, void*, void*, int64_t, hipStream_t);                \
+  template hipError_t run_rk_stage4_fold<R>(const Plan&, const LaunchConfig&, const void*, const void*,       \
+                                            const void*, void*, int64_t, hipStream_t);                       \
   template hipError_t run_observe<R>(const Plan&, const LaunchConfig&, const void*, const void*, double, bool, \
                                      int64_t, hipStream_t);                                                  \
   template hipError_t run_adj_stage<R>(const Plan&, const LaunchConfig&, int, const void*, const void*,      \
