@@ -146,6 +146,7 @@ hipError_t dalloc(T** p, size_t count) {
 struct ChunkSet {
   int capacity = 0;
   int n_chunks = 0;
+  int max_seg = 1;
   Chunk* d_chunks = nullptr;
   std::vector<int> inst_begin, inst_count;
 };
@@ -300,6 +301,7 @@ struct Problem {
         c.seg_count = (int32_t)(last - seg + 1);
         c.inst = i;
         c.pad[0] = c.pad[1] = c.pad[2] = 0;
+        cs.max_seg = std::max(cs.max_seg, c.seg_count);
         tab.push_back(c);
       }
       cs.inst_count[i] = (int)tab.size() - cs.inst_begin[i];
@@ -332,6 +334,9 @@ struct Problem {
     p.n_inst = n_inst;
     p.xcd_map = cfg.xcd;
     p.pstride = (int32_t)max_chunks;
+    // complex128 is the widest per-site element (16 bytes)
+    p.off32 = ((uint64_t)total * 16u < (uint64_t(1) << 32)) ? 1 : 0;
+    p.max_seg = cs.max_seg;
     return p;
   }
 

@@ -60,6 +60,8 @@ struct Plan {
   int32_t n_inst;
   int32_t xcd_map;        // 1: give each XCD a contiguous range of chunks
   int32_t pstride;        // stride between partial-sum components (>= n_chunks)
+  int32_t off32;          // 1: every per-site array is below 4 GiB (32-bit byte offsets)
+  int32_t max_seg;        // largest seg_count of any chunk (sizes the dynamic LDS)
 };
 
 // Compiled launch variants (workgroup size x sites per lane, chunk capacity

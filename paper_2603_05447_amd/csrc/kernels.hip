@@ -23,6 +23,8 @@
 // bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "engine.hpp"
 
 namespace gpe {
@@ -150,11 +152,10 @@ template <typename R> struct PassArgs {
   int use_scale;    // OBS: multiply Y by the instance's scale
 };
 
-template <typename R, int BLOCK, int SPT, int OP>
+template <typename R, int BLOCK, int SPT, int OP, bool OFF32>
 __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
   using C = typename CT<R>::T;
   constexpr int CH = BLOCK * SPT;
-  constexpr int NB_CAP = CH / 4;   // lateral-offset descriptors kept in LDS (rest read from global)
   constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
   constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4) || OP == OP_RK2F || OP == OP_RK4F;
   constexpr bool OBSP = (OP == OP_RK1_OBS || OP == OP_OBS);
@@ -167,14 +168,16 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   constexpr bool NEED_F = (RK || OP == OP_OBS || ADJ);
   constexpr bool NEED_P = (OP == OP_ITP2);
   __shared__ C sy[CH + 2];
-  __shared__ SegHead sh[CH + 1];
-  __shared__ SegNb snb[NB_CAP];
   __shared__ double red[BLOCK / 64][NR > 0 ? NR : 1];
+  // dynamic LDS: lateral offsets (max_seg) then segment heads (max_seg + 1)
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  SegNb* snb = reinterpret_cast<SegNb*>(dyn_lds);
+  SegHead* sh = reinterpret_cast<SegHead*>(dyn_lds + (size_t)pl.max_seg * sizeof(SegNb));
 
   const int cidx = chunk_index((int)blockIdx.x, (int)gridDim.x, pl.xcd_map);
   const Chunk ch = pl.chunks[cidx];
   const InstParams& ip = pl.inst[ch.inst];
-  const int64_t ib = ip.site_begin, ie = ip.site_begin + ip.n_sites;
+  const int ib = (int)ip.site_begin, ie = (int)(ip.site_begin + ip.n_sites);
 
   const R g = (R)ip.g, dt = (R)ip.dt;
   const R cx = (R)ip.cx, cy = (R)ip.cy, cz = (R)ip.cz, cd = (R)ip.cd;
@@ -188,11 +191,22 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const R hg = g * dt * R(0.5);
   const C zero = cmk<R>(R(0), R(0));
 
+  // element i of a per-site array; with OFF32 the byte offset is formed in
+  // 32 bits (every array is below 4 GiB), giving base-register + offset loads
+  auto at = [&](auto* base, int i) -> decltype(*base) {
+    using T = typename std::remove_reference<decltype(*base)>::type;
+    if constexpr (OFF32)
+      return *reinterpret_cast<T*>(reinterpret_cast<typename std::conditional<std::is_const<T>::value, const char*,
+                                                                                char*>::type>(base) +
+                                   (uint32_t)i * (uint32_t)sizeof(T));
+    else
+      return base[i];
+  };
   // value of the stencil input at compact site s (ITP1 applies the diagonal half-step on load)
-  auto load = [&](int64_t s) -> C {
-    C v = a.Y[s];
+  auto load = [&](int s) -> C {
+    C v = at(a.Y, s);
     if (OP == OP_ITP1) {
-      const R p = a.prop[s];
+      const R p = at(a.prop, s);
       const R vr = v.x * scale, vi = v.y * scale;
       const R f = p * (R(1) - hg * (vr * vr + vi * vi));
       v = cmk<R>(vr * f, vi * f);
@@ -203,57 +217,57 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   };
 
   // ---- phase A: every load that does not depend on the segment search ----
+  // Lanes past the end of the chunk load its last site (always valid) and
+  // skip their stores.
+  const int last = ch.site_begin + ch.count - 1;
   C ra[SPT], rb[SPT], rc[SPT], rl[SPT];
   R rf[SPT], rp[SPT];
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
-    const int l = threadIdx.x + m * BLOCK;
-    ra[m] = rb[m] = rc[m] = rl[m] = zero;
-    rf[m] = rp[m] = R(0);
-    if (l < ch.count) {
-      const int64_t s = (int64_t)ch.site_begin + l;
-      if constexpr (NEED_A) ra[m] = a.a[s];
-      if constexpr (NEED_B) rb[m] = a.b[s];
-      if constexpr (NEED_C) rc[m] = a.c[s];
-      if constexpr (NEED_L) rl[m] = a.out2[s];
-      if constexpr (NEED_F) rf[m] = a.field[s];
-      if constexpr (NEED_P) rp[m] = a.prop[s];
-    }
+    const int sc = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
+    if constexpr (NEED_A) ra[m] = at(a.a, sc);
+    if constexpr (NEED_B) rb[m] = at(a.b, sc);
+    if constexpr (NEED_C) rc[m] = at(a.c, sc);
+    if constexpr (NEED_L) rl[m] = at(a.out2, sc);
+    if constexpr (NEED_F) rf[m] = at(a.field, sc);
+    if constexpr (NEED_P) rp[m] = at(a.prop, sc);
   }
   for (int t = threadIdx.x; t <= ch.seg_count; t += BLOCK) {
     sh[t] = pl.heads[ch.seg_begin + t];
-    if (t < ch.seg_count && t < NB_CAP) snb[t] = pl.nbs[ch.seg_begin + t];
+    if (t < ch.seg_count) snb[t] = pl.nbs[ch.seg_begin + t];
   }
   for (int t = threadIdx.x; t < ch.count + 2; t += BLOCK) {
-    const int64_t s = (int64_t)ch.site_begin - 1 + t;
+    const int s = ch.site_begin - 1 + t;
     sy[t] = (s >= ib && s < ie) ? load(s) : zero;
   }
   __syncthreads();
 
   // ---- phase B1: segment search and the lateral loads of all of the lane's sites ----
+  // An absent lateral neighbour (offset 0) loads the site itself and gets
+  // stencil weight 0, so every lane issues the same four loads.
   const int nseg = ch.seg_count;
   const int top = nseg > 1 ? (1 << (31 - __clz(nseg - 1))) : 0;
   int js[SPT];
   C xm[SPT], xp[SPT], ym[SPT], yp[SPT];
+  R wxm[SPT], wxp[SPT], wym[SPT], wyp[SPT];
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
-    const int l = threadIdx.x + m * BLOCK;
-    js[m] = 0;
-    xm[m] = xp[m] = ym[m] = yp[m] = zero;
-    if (l < ch.count) {
-      const int s = ch.site_begin + l;
-      int j = 0;
-      for (int st = top; st > 0; st >>= 1) {
-        const int cand = j + st;
-        if (cand < nseg && sh[cand].start <= s) j = cand;
-      }
-      js[m] = j;
-      const SegNb nb = (j < NB_CAP) ? snb[j] : pl.nbs[ch.seg_begin + j];
-      if (nb.xm) xm[m] = load((int64_t)s + nb.xm);
-      if (nb.xp) xp[m] = load((int64_t)s + nb.xp);
-      if (nb.ym) ym[m] = load((int64_t)s + nb.ym);
-      if (nb.yp) yp[m] = load((int64_t)s + nb.yp);
+    const int s = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
+    int j = 0;
+    for (int st = top; st > 0; st >>= 1) {
+      const int cand = j + st;
+      if (cand < nseg && sh[cand].start <= s) j = cand;
     }
+    js[m] = j;
+    const SegNb nb = snb[j];
+    xm[m] = load(s + nb.xm);
+    xp[m] = load(s + nb.xp);
+    ym[m] = load(s + nb.ym);
+    yp[m] = load(s + nb.yp);
+    wxm[m] = nb.xm ? cx : R(0);
+    wxp[m] = nb.xp ? cx : R(0);
+    wym[m] = nb.ym ? cy : R(0);
+    wyp[m] = nb.yp ? cy : R(0);
   }
 
   // ---- phase B2: arithmetic and stores ----
@@ -269,11 +283,14 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       const SegHead hd = sh[js[m]];
       const int send = sh[js[m] + 1].start;
       const C yc = sy[l + 1];
-      const C zm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? zero : sy[l];
-      const C zp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? zero : sy[l + 2];
+      const C zm = sy[l], zp = sy[l + 2];
+      const R wzm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? R(0) : cz;
+      const R wzp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? R(0) : cz;
       // T~ y at s
-      const R lr = cx * (xm[m].x + xp[m].x) + cy * (ym[m].x + yp[m].x) + cz * (zm.x + zp.x) + cd * yc.x;
-      const R li = cx * (xm[m].y + xp[m].y) + cy * (ym[m].y + yp[m].y) + cz * (zm.y + zp.y) + cd * yc.y;
+      const R lr = wxm[m] * xm[m].x + wxp[m] * xp[m].x + wym[m] * ym[m].x + wyp[m] * yp[m].x + wzm * zm.x +
+                   wzp * zp.x + cd * yc.x;
+      const R li = wxm[m] * xm[m].y + wxp[m] * xp[m].y + wym[m] * ym[m].y + wyp[m] * yp[m].y + wzm * zm.y +
+                   wzp * zp.y + cd * yc.y;
 
       if constexpr (OP == OP_ITP1) {
         a.out[s] = cmk<R>(yc.x - R(0.5) * dt * lr, yc.y - R(0.5) * dt * li);
@@ -394,7 +411,11 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 
 template <int BLOCK, int SPT, typename R, int OP>
 static hipError_t launch_pass(const Plan& p, const PassArgs<R>& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP>), dim3(p.n_chunks), dim3(BLOCK), 0, s, p, a);
+  const size_t dyn = (size_t)p.max_seg * sizeof(SegNb) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
+  if (p.off32)
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+  else
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
   return hipGetLastError();
 }
 
