@@ -244,12 +244,13 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch batch, gpe_dtype dtype, const void*
  * RK4 storage scheme (0: the App. A form, whose last stage reads y0, y2, y3;
  * 1: the second stage also stores A = (-y0 + y2 + 2 y3)/3 so the last stage
  * reads A alone, 16 fewer bytes per site per complex128 step; both give the
- * RK4 result up to rounding).  gpe_config_count/gpe_config_describe list
- * them.  The grid's (or batch's) configuration is used by every later call
- * on it. */
+ * RK4 result up to rounding), and whether streams touched once per pass use
+ * non-temporal loads/stores.  gpe_config_count/gpe_config_describe list
+ * them; variant 0 is the default.  The grid's (or batch's) configuration is
+ * used by every later call on it. */
 int32_t gpe_config_count(void);
 gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* sites_per_lane, int32_t* xcd_map,
-                               int32_t* rk_scheme);
+                               int32_t* rk_scheme, int32_t* nontemporal);
 gpe_status gpe_grid_set_config(gpe_grid grid, int32_t config);
 gpe_status gpe_grid_get_config(gpe_grid grid, int32_t* config);
 gpe_status gpe_batch_set_config(gpe_batch batch, int32_t config);

@@ -522,6 +522,12 @@ struct Ctx {
 gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
   c.P = P;
   c.cfg = config_get(config);
+  if ((uint64_t)P->total * 16u >= (uint64_t(1) << 32)) {
+    // 64-bit addressing is compiled for one shape only
+    c.cfg.block = 256;
+    c.cfg.spt = 2;
+    c.cfg.nt = 0;
+  }
   gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs);
   if (st != GPE_OK) return st;
   c.pl = P->plan(*c.cs, c.cfg);
@@ -1324,13 +1330,15 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi
 
 int32_t gpe_config_count(void) { return config_count(); }
 
-gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* spt, int32_t* xcd, int32_t* rk_scheme) {
+gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* spt, int32_t* xcd, int32_t* rk_scheme,
+                               int32_t* nontemporal) {
   if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
   LaunchConfig c = config_get(config);
   if (block) *block = c.block;
   if (spt) *spt = c.spt;
   if (xcd) *xcd = c.xcd;
   if (rk_scheme) *rk_scheme = c.scheme;
+  if (nontemporal) *nontemporal = c.nt;
   return GPE_OK;
 }
 

@@ -70,11 +70,14 @@ struct Plan {
 //             -y0/3 + y2/3 + 2 y3/3 + y4/3 + dt/6 k4          (240 B/site/step in complex128)
 //   scheme 1: stage 2 also writes A = (-y0 + y2 + 2 y3)/3, stage 4 reads A only
 //             and forms A + y4/3 + dt/6 k4; y4 reuses y2's buffer (224 B/site/step)
+//   nt: streams touched once per pass (own-site inputs, outputs) use
+//       non-temporal loads and stores
 struct LaunchConfig {
   int block;
   int spt;
   int xcd;
   int scheme;
+  int nt;
 };
 int config_count();
 LaunchConfig config_get(int i);

@@ -40,12 +40,46 @@ template <typename R> __device__ __forceinline__ typename CT<R>::T cmk(R a, R b)
   return v;
 }
 
+// native two-element vectors, for non-temporal loads and stores of (re, im)
+template <typename C> struct NVec;
+template <> struct NVec<double2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct NVec<float2> { typedef float T __attribute__((ext_vector_type(2))); };
+
+// Non-temporal (NT = true) accesses are used for streams touched once per
+// pass, so that they do not displace the neighbour planes from L2.
+template <bool NT, typename T> __device__ __forceinline__ T ld(const T* p) {
+  if constexpr (!NT) {
+    return *p;
+  } else if constexpr (std::is_floating_point<T>::value) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    const auto v = __builtin_nontemporal_load(reinterpret_cast<const typename NVec<T>::T*>(p));
+    T r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+  }
+}
+template <bool NT, typename T> __device__ __forceinline__ void st(T* p, const T& v) {
+  if constexpr (!NT) {
+    *p = v;
+  } else {
+    typename NVec<T>::T w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<typename NVec<T>::T*>(p));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launch variants
 // ---------------------------------------------------------------------------
+// Variant 0 is the default.  Measured on the 16M-site headline grid, handing
+// chunks to workgroups in array order beat the XCD-contiguous order.
 static const LaunchConfig kConfigs[] = {
-    {256, 2, 1, 1}, {256, 1, 1, 1}, {256, 4, 1, 1}, {512, 1, 1, 1}, {512, 2, 1, 1}, {1024, 1, 1, 1},
-    {256, 2, 0, 1}, {512, 2, 0, 1}, {256, 2, 1, 0}, {512, 1, 1, 0},
+    {256, 2, 0, 1, 0}, {256, 1, 0, 1, 0}, {256, 4, 0, 1, 0}, {512, 1, 0, 1, 0}, {512, 2, 0, 1, 0},
+    {1024, 1, 0, 1, 0}, {256, 2, 1, 1, 0}, {512, 1, 1, 1, 0}, {256, 2, 0, 0, 0}, {256, 2, 0, 1, 1},
+    {256, 1, 0, 1, 1}, {512, 1, 0, 1, 1},
 };
 int config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
 LaunchConfig config_get(int i) { return kConfigs[i]; }
@@ -152,7 +186,7 @@ template <typename R> struct PassArgs {
   int use_scale;    // OBS: multiply Y by the instance's scale
 };
 
-template <typename R, int BLOCK, int SPT, int OP, bool OFF32>
+template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
   using C = typename CT<R>::T;
   constexpr int CH = BLOCK * SPT;
@@ -191,17 +225,22 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const R hg = g * dt * R(0.5);
   const C zero = cmk<R>(R(0), R(0));
 
-  // element i of a per-site array; with OFF32 the byte offset is formed in
-  // 32 bits (every array is below 4 GiB), giving base-register + offset loads
-  auto at = [&](auto* base, int i) -> decltype(*base) {
-    using T = typename std::remove_reference<decltype(*base)>::type;
-    if constexpr (OFF32)
-      return *reinterpret_cast<T*>(reinterpret_cast<typename std::conditional<std::is_const<T>::value, const char*,
-                                                                                char*>::type>(base) +
-                                   (uint32_t)i * (uint32_t)sizeof(T));
-    else
-      return base[i];
+  // address of element i of a per-site array; with OFF32 the byte offset is
+  // formed in 32 bits (every array is below 4 GiB), giving base-register +
+  // offset addressing
+  auto ptr = [&](auto* base, int i) {
+    using P = decltype(base);
+    using T = typename std::remove_pointer<P>::type;
+    if constexpr (OFF32) {
+      using B = typename std::conditional<std::is_const<T>::value, const char*, char*>::type;
+      return reinterpret_cast<P>(reinterpret_cast<B>(base) + (uint32_t)i * (uint32_t)sizeof(T));
+    } else {
+      return base + i;
+    }
   };
+  auto at = [&](auto* base, int i) { return ld<false>(ptr(base, i)); };       // reused stream
+  auto at1 = [&](auto* base, int i) { return ld<NT>(ptr(base, i)); };         // touched once
+  auto put = [&](auto* base, int i, const C& v) { st<NT>(ptr(base, i), v); };
   // value of the stencil input at compact site s (ITP1 applies the diagonal half-step on load)
   auto load = [&](int s) -> C {
     C v = at(a.Y, s);
@@ -225,12 +264,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int sc = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
-    if constexpr (NEED_A) ra[m] = at(a.a, sc);
-    if constexpr (NEED_B) rb[m] = at(a.b, sc);
-    if constexpr (NEED_C) rc[m] = at(a.c, sc);
-    if constexpr (NEED_L) rl[m] = at(a.out2, sc);
-    if constexpr (NEED_F) rf[m] = at(a.field, sc);
-    if constexpr (NEED_P) rp[m] = at(a.prop, sc);
+    if constexpr (NEED_A) ra[m] = at1(a.a, sc);
+    if constexpr (NEED_B) rb[m] = at1(a.b, sc);
+    if constexpr (NEED_C) rc[m] = at1(a.c, sc);
+    if constexpr (NEED_L) rl[m] = at1((const C*)a.out2, sc);
+    if constexpr (NEED_F) rf[m] = at1(a.field, sc);
+    if constexpr (NEED_P) rp[m] = at1(a.prop, sc);
   }
   for (int t = threadIdx.x; t <= ch.seg_count; t += BLOCK) {
     sh[t] = pl.heads[ch.seg_begin + t];
@@ -293,12 +332,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
                    wzp * zp.y + cd * yc.y;
 
       if constexpr (OP == OP_ITP1) {
-        a.out[s] = cmk<R>(yc.x - R(0.5) * dt * lr, yc.y - R(0.5) * dt * li);
+        put(a.out, s, cmk<R>(yc.x - R(0.5) * dt * lr, yc.y - R(0.5) * dt * li));
       } else if constexpr (OP == OP_ITP2) {
         const R qr = yc.x - R(0.5) * dt * lr, qi = yc.y - R(0.5) * dt * li;
         const R f = rp[m] * (R(1) - hg * (qr * qr + qi * qi));
         const R wr = qr * f, wi = qi * f;
-        a.out[s] = cmk<R>(wr, wi);
+        put(a.out, s, cmk<R>(wr, wi));
         acc[0] += (double)wr * (double)wr + (double)wi * (double)wi;
       } else if constexpr (OP == OP_OBS) {
         const R V = potential<R>(kind, rf[m], delta, omega2);
@@ -314,7 +353,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         const R hr = lr + w * yc.x, hi = li + w * yc.y;   // H y
         const R fr = hi, fi = -hr;                         // f = -i H y
         if constexpr (OP == OP_RK1 || OP == OP_RK1_OBS) {
-          a.out[s] = cmk<R>(yc.x + R(0.5) * dt * fr, yc.y + R(0.5) * dt * fi);
+          put(a.out, s, cmk<R>(yc.x + R(0.5) * dt * fr, yc.y + R(0.5) * dt * fi));
           if constexpr (OP == OP_RK1_OBS) {
             const double d = (double)dens;
             acc[0] += d;
@@ -325,23 +364,23 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         } else if constexpr (OP == OP_RK2 || OP == OP_RK3) {
           const C y0 = ra[m];
           const R cc = (OP == OP_RK2) ? R(0.5) * dt : dt;
-          a.out[s] = cmk<R>(y0.x + cc * fr, y0.y + cc * fi);
+          put(a.out, s, cmk<R>(y0.x + cc * fr, y0.y + cc * fi));
         } else if constexpr (OP == OP_RK2F) {
           const C y0 = ra[m];
           const R y3r = y0.x + R(0.5) * dt * fr, y3i = y0.y + R(0.5) * dt * fi;
           const R third = R(1) / R(3);
-          a.out[s] = cmk<R>(y3r, y3i);
-          a.out2[s] = cmk<R>(third * (yc.x - y0.x) + R(2) * third * y3r, third * (yc.y - y0.y) + R(2) * third * y3i);
+          put(a.out, s, cmk<R>(y3r, y3i));
+          put(a.out2, s, cmk<R>(third * (yc.x - y0.x) + R(2) * third * y3r, third * (yc.y - y0.y) + R(2) * third * y3i));
         } else if constexpr (OP == OP_RK4F) {
           const C A = ra[m];
           const R third = R(1) / R(3), c6 = dt / R(6);
-          a.out[s] = cmk<R>(A.x + third * yc.x + c6 * fr, A.y + third * yc.y + c6 * fi);
+          put(a.out, s, cmk<R>(A.x + third * yc.x + c6 * fr, A.y + third * yc.y + c6 * fi));
         } else {
           const C y0 = ra[m], y2 = rb[m], y3 = rc[m];
           const R third = R(1) / R(3), c6 = dt / R(6);
           const R orr = third * (y2.x - y0.x + yc.x) + R(2) * third * y3.x + c6 * fr;
           const R oi = third * (y2.y - y0.y + yc.y) + R(2) * third * y3.y + c6 * fi;
-          a.out[s] = cmk<R>(orr, oi);
+          put(a.out, s, cmk<R>(orr, oi));
         }
       } else if constexpr (ADJ) {
         // u = f X, T u = f T X  (stage 4: X = lambda, f = b_4 = 1/6)
@@ -364,17 +403,17 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         if constexpr (OP == OP_ADJ4) {
           // lambda = X;  u_3 = lambda/3 + theta_4;  running lambda = lambda + theta_4
           const R third = R(1) / R(3);
-          a.out[s] = cmk<R>(third * yc.x + thr, third * yc.y + thi);
-          a.out2[s] = cmk<R>(yc.x + thr, yc.y + thi);
+          put(a.out, s, cmk<R>(third * yc.x + thr, third * yc.y + thi));
+          put(a.out2, s, cmk<R>(yc.x + thr, yc.y + thi));
         } else if constexpr (OP == OP_ADJ3 || OP == OP_ADJ2) {
           const C lam = rb[m];
           const C lacc = rl[m];
           const R bl = (OP == OP_ADJ3) ? R(1) / R(3) : R(1) / R(6);
-          a.out[s] = cmk<R>(bl * lam.x + R(0.5) * thr, bl * lam.y + R(0.5) * thi);
-          a.out2[s] = cmk<R>(lacc.x + thr, lacc.y + thi);
+          put(a.out, s, cmk<R>(bl * lam.x + R(0.5) * thr, bl * lam.y + R(0.5) * thi));
+          put(a.out2, s, cmk<R>(lacc.x + thr, lacc.y + thi));
         } else {
           const C lacc = rl[m];
-          a.out[s] = cmk<R>(lacc.x + thr, lacc.y + thi);
+          put(a.out, s, cmk<R>(lacc.x + thr, lacc.y + thi));
         }
       }
     }
@@ -410,24 +449,28 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 }
 
 template <int BLOCK, int SPT, typename R, int OP>
-static hipError_t launch_pass(const Plan& p, const PassArgs<R>& a, hipStream_t s) {
+static hipError_t launch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   const size_t dyn = (size_t)p.max_seg * sizeof(SegNb) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
-  if (p.off32)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+  if (p.off32 && cfg.nt)
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+  else if (p.off32)
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
   else
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
   return hipGetLastError();
 }
 
 template <typename R, int OP>
 static hipError_t dispatch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   if (p.n_chunks <= 0) return hipSuccess;
-  if (cfg.block == 256 && cfg.spt == 1) return launch_pass<256, 1, R, OP>(p, a, s);
-  if (cfg.block == 256 && cfg.spt == 2) return launch_pass<256, 2, R, OP>(p, a, s);
-  if (cfg.block == 256 && cfg.spt == 4) return launch_pass<256, 4, R, OP>(p, a, s);
-  if (cfg.block == 512 && cfg.spt == 1) return launch_pass<512, 1, R, OP>(p, a, s);
-  if (cfg.block == 512 && cfg.spt == 2) return launch_pass<512, 2, R, OP>(p, a, s);
-  if (cfg.block == 1024 && cfg.spt == 1) return launch_pass<1024, 1, R, OP>(p, a, s);
+  // arrays of 4 GiB or more use 64-bit addressing with the 256 x 2 shape (the
+  // chunk table of a grid that large is built for that shape)
+  if (cfg.block == 256 && cfg.spt == 1) return launch_pass<256, 1, R, OP>(p, cfg, a, s);
+  if (cfg.block == 256 && cfg.spt == 2) return launch_pass<256, 2, R, OP>(p, cfg, a, s);
+  if (cfg.block == 256 && cfg.spt == 4) return launch_pass<256, 4, R, OP>(p, cfg, a, s);
+  if (cfg.block == 512 && cfg.spt == 1) return launch_pass<512, 1, R, OP>(p, cfg, a, s);
+  if (cfg.block == 512 && cfg.spt == 2) return launch_pass<512, 2, R, OP>(p, cfg, a, s);
+  if (cfg.block == 1024 && cfg.spt == 1) return launch_pass<1024, 1, R, OP>(p, cfg, a, s);
   return hipErrorInvalidValue;
 }
 
