@@ -241,8 +241,11 @@ struct Problem {
     heads[n_segs] = {(int32_t)total, 0};
     DeviceGuard g(device);
     if (!g.ok) return fail(GPE_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+    // chunks of >= 256 sites each, plus at most one extra chunk per
+    // MAX_CHUNK_SEGS segments where a fragmented mask cuts chunks short
     max_chunks = 0;
-    for (int i = 0; i < n_inst; ++i) max_chunks += (lays[i]->n_active + 255) / 256;
+    for (int i = 0; i < n_inst; ++i)
+      max_chunks += (lays[i]->n_active + 255) / 256 + lays[i]->n_segments() / MAX_CHUNK_SEGS + 1;
     if (dalloc(&d_heads, n_segs + 1) != hipSuccess || dalloc(&d_nbs, n_segs) != hipSuccess ||
         dalloc(&d_inst, n_inst) != hipSuccess || dalloc(&d_out, n_inst) != hipSuccess ||
         dalloc(&d_step, 1) != hipSuccess || dalloc(&d_partials, max_chunks * NPART) != hipSuccess ||
@@ -289,11 +292,16 @@ struct Problem {
     for (int i = 0; i < n_inst; ++i) {
       cs.inst_begin[i] = (int)tab.size();
       int64_t seg = inst_seg[i];
-      for (int64_t b = inst_site[i]; b < inst_site[i + 1]; b += capacity) {
-        const int64_t e = std::min<int64_t>(b + capacity, inst_site[i + 1]);
+      for (int64_t b = inst_site[i]; b < inst_site[i + 1];) {
+        int64_t e = std::min<int64_t>(b + capacity, inst_site[i + 1]);
         while (heads[seg + 1].start <= b) ++seg;
         int64_t last = seg;
         while (heads[last + 1].start <= e - 1) ++last;
+        if (last - seg + 1 > MAX_CHUNK_SEGS) {
+          // end the chunk where its (MAX_CHUNK_SEGS + 1)-th segment begins
+          last = seg + MAX_CHUNK_SEGS - 1;
+          e = heads[last + 1].start;
+        }
         Chunk c;
         c.site_begin = (int32_t)b;
         c.count = (int32_t)(e - b);
@@ -303,6 +311,7 @@ struct Problem {
         c.pad[0] = c.pad[1] = c.pad[2] = 0;
         cs.max_seg = std::max(cs.max_seg, c.seg_count);
         tab.push_back(c);
+        b = e;
       }
       cs.inst_count[i] = (int)tab.size() - cs.inst_begin[i];
     }

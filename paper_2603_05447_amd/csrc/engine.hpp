@@ -11,7 +11,11 @@
 namespace gpe {
 
 // One workgroup processes one chunk: a contiguous range of compact sites
-// of a single instance, plus the segment descriptors overlapping it.
+// of a single instance, plus the segment descriptors overlapping it.  A chunk
+// holds at most `block * spt` sites and at most MAX_CHUNK_SEGS segments (a
+// chunk is cut short where a mask fragments into many short segments), so
+// one lane per segment stages the chunk's segment table.
+constexpr int MAX_CHUNK_SEGS = 255;
 struct Chunk {
   int32_t site_begin;   // global compact index of the first site
   int32_t count;        // number of sites (<= chunk capacity)

@@ -255,7 +255,27 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     return v;
   };
 
-  // ---- phase A: every load that does not depend on the segment search ----
+  // Load schedule.  Global loads return in issue order, and the barriers
+  // below wait for LDS traffic only, so the large streams stay in flight
+  // while the workgroup exchanges the small segment tables:
+  //   1. segment heads / lateral offsets (small)          -> LDS
+  //   2. own-site streams (y0, y2, y3, A, lambda, U, P)   -> registers
+  //   3. the chunk's stencil input plus one site each side -> registers
+  //   barrier (LDS only): segment search, 4. lateral neighbour loads
+  //   registers of 3 -> LDS (waits for 2 and 3 only), barrier (LDS only),
+  //   arithmetic.
+  constexpr int NSTG = SPT + 1;    // staging slots per lane: ceil((CH + 2) / BLOCK)
+  // Segment-table slots past the end re-load the last entry (same value to
+  // the same LDS slot), so these loads are unconditional and issue first.
+  const SegHead* hsrc = pl.heads + ch.seg_begin;
+  const SegNb* nsrc = pl.nbs + ch.seg_begin;
+  const int t0 = threadIdx.x;
+  // a chunk holds at most MAX_CHUNK_SEGS (< 256 <= BLOCK) segments, so one
+  // slot per lane covers its table
+  sh[min(t0, ch.seg_count)] = hsrc[min(t0, ch.seg_count)];
+  snb[min(t0, ch.seg_count - 1)] = nsrc[min(t0, ch.seg_count - 1)];
+  __builtin_amdgcn_sched_barrier(0);
+
   // Lanes past the end of the chunk load its last site (always valid) and
   // skip their stores.
   const int last = ch.site_begin + ch.count - 1;
@@ -271,17 +291,23 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     if constexpr (NEED_F) rf[m] = at1(a.field, sc);
     if constexpr (NEED_P) rp[m] = at1(a.prop, sc);
   }
-  for (int t = threadIdx.x; t <= ch.seg_count; t += BLOCK) {
-    sh[t] = pl.heads[ch.seg_begin + t];
-    if (t < ch.seg_count) snb[t] = pl.nbs[ch.seg_begin + t];
+  __builtin_amdgcn_sched_barrier(0);
+  C stg[NSTG];
+#pragma unroll
+  for (int q = 0; q < NSTG; ++q) {
+    const int t = threadIdx.x + q * BLOCK;
+    const int sidx = ch.site_begin - 1 + t;
+    const bool in = (t < ch.count + 2) && sidx >= ib && sidx < ie;
+    stg[q] = load(in ? sidx : last);
+    if (!in) stg[q] = zero;
   }
-  for (int t = threadIdx.x; t < ch.count + 2; t += BLOCK) {
-    const int s = ch.site_begin - 1 + t;
-    sy[t] = (s >= ib && s < ie) ? load(s) : zero;
-  }
-  __syncthreads();
+  __builtin_amdgcn_sched_barrier(0);
 
-  // ---- phase B1: segment search and the lateral loads of all of the lane's sites ----
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+
+  // ---- segment search and the lateral loads of all of the lane's sites ----
   // An absent lateral neighbour (offset 0) loads the site itself and gets
   // stencil weight 0, so every lane issues the same four loads.
   const int nseg = ch.seg_count;
@@ -308,6 +334,17 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     wym[m] = nb.ym ? cy : R(0);
     wyp[m] = nb.yp ? cy : R(0);
   }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // the staged stencil input becomes visible to the neighbouring lanes
+#pragma unroll
+  for (int q = 0; q < NSTG; ++q) {
+    const int t = threadIdx.x + q * BLOCK;
+    if (t < CH + 2) sy[t] = stg[q];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 
   // ---- phase B2: arithmetic and stores ----
   double acc[NR > 0 ? NR : 1];
