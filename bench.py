@@ -59,6 +59,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(family: str):
+    """Calibrated HBM bytes per launch of `family` from the committed
+    rocprofv3 summary (profiles/*.txt, FETCH_SIZE + WRITE_SIZE scaled by a
+    copy kernel of known size), or None when no summary was taken on the
+    current kernel source."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2603_05447_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        for line in open(f):
+            if not line.startswith("TRAFFIC "):
+                continue
+            kv = dict(item.split("=", 1) for item in line.split()[1:])
+            if kv.get("family") == family and kv.get("sha256") == sha:
+                return int(kv["fetch_bytes"]) + int(kv["write_bytes"]), os.path.basename(f)
+    return None, None
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -380,9 +399,11 @@ def main():
     kern = main_res["kernels"]
     dom = max((f for f in kern if kern[f]["GBps"] is not None), key=lambda f: kern[f]["total_ms"])
     k = kern[dom]
+    traffic, tsrc = profiled_traffic(dom) if main_res["config"] == 0 else (None, None)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": None,
-                "algo_bytes_per_launch": k["algo_bytes_per_launch"], "avg_launch_us": k["avg_us"]}
+                "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": traffic, "traffic_unit": "bytes/launch",
+                "traffic_source": tsrc, "algo_bytes_per_launch": k["algo_bytes_per_launch"],
+                "avg_launch_us": k["avg_us"], "launches": k["launches"]}
     line = {
         "metric": METRIC,
         "value": main_res["site_updates_per_s"],
