@@ -62,14 +62,14 @@ struct Plan {
   int64_t* step;          // device step counter
   int32_t n_chunks;
   int32_t n_inst;
-  int32_t xcd_map;        // 1: give each XCD a contiguous range of chunks
+  int32_t xcd_map;        // chunk order mode (see chunk_index in kernels.hip)
   int32_t pstride;        // stride between partial-sum components (>= n_chunks)
   int32_t off32;          // 1: every per-site array is below 4 GiB (32-bit byte offsets)
   int32_t max_seg;        // largest seg_count of any chunk (sizes the dynamic LDS)
 };
 
 // Compiled launch variants (workgroup size x sites per lane, chunk capacity
-// = product), the XCD mapping flag, and the RK4 storage scheme:
+// = product), the chunk-to-XCD order mode, and the RK4 storage scheme:
 //   scheme 0: App. A form; stage 4 reads y0, y2, y3 and forms
 //             -y0/3 + y2/3 + 2 y3/3 + y4/3 + dt/6 k4          (240 B/site/step in complex128)
 //   scheme 1: stage 2 also writes A = (-y0 + y2 + 2 y3)/3, stage 4 reads A only

@@ -80,6 +80,7 @@ template <bool NT, typename T> __device__ __forceinline__ void st(T* p, const T&
 static const LaunchConfig kConfigs[] = {
     {256, 2, 0, 1, 1}, {512, 1, 0, 1, 1}, {256, 1, 0, 1, 1}, {256, 4, 0, 1, 1}, {512, 2, 0, 1, 1},
     {1024, 1, 0, 1, 1}, {256, 2, 0, 1, 0}, {512, 1, 0, 1, 0}, {256, 2, 1, 1, 1}, {256, 2, 0, 0, 1},
+    {256, 2, 2, 1, 1}, {256, 2, 3, 1, 1}, {512, 1, 2, 1, 1},
 };
 int config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
 LaunchConfig config_get(int i) { return kConfigs[i]; }
@@ -91,13 +92,24 @@ const char* family_name(int f) {
   return (f >= 0 && f < FAM_COUNT) ? names[f] : "?";
 }
 
-// Workgroup b runs on XCD b % 8 (round-robin dispatch).  With xcd != 0 the
-// chunk handed to it makes XCD x own chunks [base_x, base_x + cnt_x).
-__device__ __forceinline__ int chunk_index(int b, int G, int xcd) {
-  if (!xcd) return b;
-  const int q = G >> 3, r = G & 7;
+// Workgroup b runs on XCD b % 8 (round-robin dispatch); each XCD has its own
+// L2.  Chunk order modes:
+//   0: chunk b (array order; neighbouring chunks land on different XCDs)
+//   1: XCD x owns the contiguous eighth [base_x, base_x + cnt_x)
+//   2, 3: blocks of 64 / 256 consecutive chunks go to one XCD, blocks dealt
+//         round-robin, so neighbouring columns and planes mostly share an L2
+//         while all XCDs stream from one compact region
+__device__ __forceinline__ int chunk_index(int b, int G, int mode) {
+  if (mode == 0) return b;
   const int x = b & 7, w = b >> 3;
-  return x * q + (x < r ? x : r) + w;
+  if (mode == 1) {
+    const int q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + w;
+  }
+  const int B = (mode == 2) ? 64 : 256;
+  const int R = G / (8 * B);          // full rounds of 8 blocks
+  if (w < R * B) return (w / B) * 8 * B + x * B + (w % B);
+  return b;                           // the tail keeps array order
 }
 
 // piecewise-linear Delta(t), constant outside the knots
