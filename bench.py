@@ -137,7 +137,7 @@ def bench_c2(args, dev, dtype, report):
     if args.autotune:
         from paper_2603_05447_amd import config_describe
         scratch = psi.clone()
-        best, times = g.autotune(scratch, pot_rt, w.g, w.dt, reps=5)
+        best, times = g.autotune(scratch, pot_rt, w.g, w.dt, reps=10)
         del scratch
         tune = {"best": best, "rk4_ms_per_step": {str(k): times[k] for k in range(len(times))},
                         "variants": {str(k): config_describe(k) for k in range(len(times))}}

@@ -258,9 +258,9 @@ gpe_status gpe_grid_get_config(gpe_grid grid, int32_t* config);
 gpe_status gpe_batch_set_config(gpe_batch batch, int32_t config);
 
 /* Time every configuration on `reps` real-time RK4 steps of psi (contents
- * are advanced; pass a scratch copy), select the fastest and store it on the
- * grid.  times_ms_host: optional gpe_config_count() doubles (mean ms per
- * step, or -1 for variants that could not run). */
+ * are advanced; pass a scratch copy), in three interleaved rounds keeping
+ * each variant's fastest, select the fastest and store it on the grid.
+ * times_ms_host: optional gpe_config_count() doubles (ms per step). */
 gpe_status gpe_grid_autotune(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
                              const gpe_params* params, int32_t reps, void* work, size_t work_bytes,
                              void* stream, int32_t* best_config, double* times_ms_host);
