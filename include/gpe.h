@@ -188,8 +188,10 @@ gpe_status gpe_overlap(gpe_grid grid, gpe_dtype dtype, const void* a, const void
  * psi0 at t0 under an RF_RAMP potential, and dL/dDelta_k for every knot, by
  * the discrete adjoint of the RK4 map (the paper optimises the ramp without
  * gradients, Sec. V; this is the gradient of the same forward scheme).
- * Forward states are checkpointed every ckpt_every steps (0 = ceil(sqrt(nsteps)))
- * and recomputed per segment in the reverse sweep.
+ * Forward states are checkpointed every ckpt_every steps (0 = ceil(sqrt(nsteps)));
+ * the reverse sweep recomputes one segment at a time from its checkpoint,
+ * keeping the segment's stage states, so the work buffer holds
+ * ceil(nsteps/K) + 4K + 8 state vectors (K = the checkpoint interval).
  *   psi_final: optional device output of psi(T) (may be NULL).
  *   grad_host: n_knots doubles. */
 gpe_status gpe_fidelity_grad(gpe_grid grid, gpe_dtype dtype, const void* psi0, const void* psi_target,

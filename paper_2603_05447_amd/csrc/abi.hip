@@ -176,9 +176,10 @@ struct Problem {
   // captured forward-step graphs, keyed by buffer pointers
   struct GraphKey {
     const void *psi, *field, *work;
-    int dtype, config;
+    int dtype, config, scheme;
     bool operator<(const GraphKey& o) const {
-      return std::tie(psi, field, work, dtype, config) < std::tie(o.psi, o.field, o.work, o.dtype, o.config);
+      return std::tie(psi, field, work, dtype, config, scheme) <
+             std::tie(o.psi, o.field, o.work, o.dtype, o.config, o.scheme);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -402,9 +403,10 @@ size_t work_bytes_for(int64_t n, int dtype, int mode, int64_t nsteps, int64_t ck
   } else if (mode == GPE_MODE_RT) {
     for (int i = 0; i < 3; ++i) c.take(st);
   } else {
+    // checkpoints + per segment step: state, Y2, Y3, Y4 + 8 vectors
     const int64_t K = ckpt_interval(nsteps, ckpt_every);
     const int64_t nck = (std::max<int64_t>(nsteps, 1) + K - 1) / K;
-    for (int64_t i = 0; i < nck + K + 8; ++i) c.take(st);
+    for (int64_t i = 0; i < nck + 4 * K + 8; ++i) c.take(st);
   }
   return c.off;
 }
@@ -644,7 +646,7 @@ template <typename R>
 static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* field, void* y2, void* y3, void* y4,
                              hipGraphExec_t* out) {
   Problem& P = *c.P;
-  Problem::GraphKey key{psi, field, y2, dtype, P.config};
+  Problem::GraphKey key{psi, field, y2, dtype, P.config, c.cfg.scheme};
   auto it = P.graphs.find(key);
   if (it != P.graphs.end()) {
     *out = it->second;
@@ -677,18 +679,31 @@ static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* fie
   return GPE_OK;
 }
 
-// use_graph: the first forward sweep replays a captured step graph (the
-// checkpoint copies run eagerly between replays); the reverse sweep is eager.
+// Discrete adjoint of the RK4 map with checkpointing: the forward sweep keeps
+// every K-th state (K = ceil(sqrt(nsteps)) by default); the reverse sweep
+// recomputes each segment of K steps from its checkpoint, keeping the stage
+// states Y2, Y3, Y4 of every step of the segment, then runs the four adjoint
+// stages of each step in reverse.  The whole driver uses the App. A storage
+// scheme (distinct y2, y3, y4), so recomputed states equal the forward
+// sweep's bit for bit.  use_graph: the forward sweep replays a captured step
+// graph (the checkpoint copies run eagerly between replays).
 template <typename R>
-gpe_status drive_adjoint(const Ctx& c, const void* psi0, const void* target, const void* field, int64_t nsteps,
+gpe_status drive_adjoint(const Ctx& c_in, const void* psi0, const void* target, const void* field, int64_t nsteps,
                          int64_t ckpt_every, void* work, void* psi_final, bool use_graph = false) {
+  Ctx c = c_in;
+  c.cfg.scheme = 0;
   const int64_t K = ckpt_interval(nsteps, ckpt_every);
   const int64_t nck = (std::max<int64_t>(nsteps, 1) + K - 1) / K;
   const size_t st = (size_t)c.P->total * 2 * sizeof(R);
   Carver cv(work);
-  std::vector<void*> ck(nck), seg(K);
+  std::vector<void*> ck(nck), seg(K), s2(K), s3(K), s4(K);
   for (auto& p : ck) p = cv.take(st);
-  for (auto& p : seg) p = cv.take(st);
+  for (int64_t r = 0; r < K; ++r) {
+    seg[r] = cv.take(st);
+    s2[r] = cv.take(st);
+    s3[r] = cv.take(st);
+    s4[r] = cv.take(st);
+  }
   void* y2 = cv.take(st);
   void* y3 = cv.take(st);
   void* y4 = cv.take(st);
@@ -721,21 +736,25 @@ gpe_status drive_adjoint(const Ctx& c, const void* psi0, const void* target, con
   LTRY(run_seed_lambda<R>(c.pl, c.cfg, target, lam, c.s));
   LTRY(run_zero_doubles(c.pl.knot_acc, (int64_t)c.cs->n_chunks * GPE_MAX_KNOTS, c.s));
   for (int64_t m = nck - 1; m >= 0; --m) {
-    const int64_t n0 = m * K, n1 = std::min(n0 + K, nsteps);
-    seg[0] = ck[m];
-    for (int64_t r = 0; r + 1 < n1 - n0; ++r) {
-      gpe_status q = rk_step<R>(c, seg[r], field, y2, y3, y4, seg[r + 1], false, nullptr, n0 + r);
-      if (q != GPE_OK) return q;
+    const int64_t n0 = m * K, L = std::min(K, nsteps - n0);
+    void* Y1 = ck[m];
+    for (int64_t r = 0; r < L; ++r) {
+      const int64_t n = n0 + r;
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, false, Y1, Y1, nullptr, nullptr, field, s2[r], n, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, s2[r], Y1, nullptr, nullptr, field, s3[r], n, c.s));
+      LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, s3[r], Y1, nullptr, nullptr, field, s4[r], n, c.s));
+      if (r + 1 < L) {
+        LTRY(run_rk_stage<R>(c.pl, c.cfg, 4, false, s4[r], Y1, s2[r], s3[r], field, seg[r + 1], n, c.s));
+        Y1 = seg[r + 1];
+      }
     }
-    for (int64_t n = n1 - 1; n >= n0; --n) {
-      void* Y1 = seg[n - n0];
-      LTRY(run_rk_stage<R>(c.pl, c.cfg, 1, false, Y1, Y1, nullptr, nullptr, field, y2, n, c.s));
-      LTRY(run_rk_stage<R>(c.pl, c.cfg, 2, false, y2, Y1, nullptr, nullptr, field, y3, n, c.s));
-      LTRY(run_rk_stage<R>(c.pl, c.cfg, 3, false, y3, Y1, nullptr, nullptr, field, y4, n, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 4, lam, y4, field, nullptr, lacc, uA, n, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 3, uA, y3, field, lam, lacc, uB, n, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 2, uB, y2, field, lam, lacc, uA, n, c.s));
-      LTRY(run_adj_stage<R>(c.pl, c.cfg, 1, uA, Y1, field, nullptr, lacc, lam, n, c.s));
+    for (int64_t r = L - 1; r >= 0; --r) {
+      const int64_t n = n0 + r;
+      void* Yr = r == 0 ? ck[m] : seg[r];
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 4, lam, s4[r], field, nullptr, lacc, uA, n, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 3, uA, s3[r], field, lam, lacc, uB, n, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 2, uB, s2[r], field, lam, lacc, uA, n, c.s));
+      LTRY(run_adj_stage<R>(c.pl, c.cfg, 1, uA, Yr, field, nullptr, lacc, lam, n, c.s));
     }
   }
   LTRY(run_knot_finalize(c.pl, c.P->d_grads, c.s));
