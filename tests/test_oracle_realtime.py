@@ -1,5 +1,6 @@
 """Pins for the oracle's real-time RK4 (Sec. II.A, eqs. (8)-(9); App. A)."""
 import numpy as np
+import pytest
 
 from oracle import operator as op
 from oracle import realtime as rt, observables as ob, dense, tableau
@@ -101,3 +102,71 @@ def test_memory_optimised_form_equals_classic():
             y1 = sum(float(b_star[j]) * Y[j] for j in range(4)) + dt * float(b[3]) * k
     ref = rt.rk4_step(T, y0, t, dt, ramp, w.g)
     assert np.linalg.norm(y1 - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+METHODS = [("RKHE3", tableau.heun3, 3), ("RK4", tableau.rk4, 4), ("RKCK", tableau.cash_karp5, 5)]
+
+
+@pytest.mark.parametrize("name,fn,order", METHODS)
+def test_tableau_method_linear_case_equals_stability_function(name, fn, order):
+    """g = 0, static V: one step of an explicit method is y -> R(-i H dt) y with
+    the stability function R(z) = 1 + z b^T (I - z A)^-1 e."""
+    A, b = fn()
+    Af = np.array([[float(v) for v in r] for r in A])
+    bf = np.array([float(v) for v in b])
+    w = configs.random_mask_problem(n=(5, 6, 5), density=0.6, seed=15)
+    lin, T = _setup(w)
+    H = T.toarray() + np.diag(w.field)
+    lam, W = np.linalg.eigh(H)
+    dt, n = 0.01, 40
+    e = np.ones(len(bf))
+    R = np.array([1 + z * bf @ np.linalg.solve(np.eye(len(bf)) - z * Af, e) for z in -1j * lam * dt])
+    exact = W @ (R ** n * (W.T @ w.psi0))
+    got = rt.real_time_tableau(T, w.psi0, StaticPotential(w.field), 0.0, dt, 0.0, n, A, b)
+    assert np.linalg.norm(got - exact) <= 1e-12 * np.linalg.norm(exact)
+    # R agrees with exp(z) to the method's order
+    z = 1e-2j
+    Rz = 1 + z * bf @ np.linalg.solve(np.eye(len(bf)) - z * Af, e)
+    assert abs(Rz - np.exp(z)) < 10 * abs(z) ** (order + 1)
+
+
+@pytest.mark.parametrize("name,fn,order", METHODS)
+def test_tableau_method_convergence_order(name, fn, order):
+    w, T, ramp = _ramp_problem()
+    A, b = fn()
+    Tend = 0.04
+    ramp = RFRamp(w.field, w.omega, [0.0, Tend], [-5.0, 15.0])
+    ref = rt.real_time_tableau(T, w.psi0, ramp, w.g, Tend / 256, 0.0, 256, *tableau.cash_karp5())
+    errs = []
+    for m in (8, 16, 32):
+        y = rt.real_time_tableau(T, w.psi0, ramp, w.g, Tend / m, 0.0, m, A, b)
+        errs.append(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    r = errs[1] / errs[2]
+    assert 0.75 * 2 ** order < r < 1.3 * 2 ** order, (errs, r)
+
+
+def test_rk4_tableau_equals_rk4_step():
+    w, T, ramp = _ramp_problem()
+    a = rt.rk4_step(T, w.psi0, 0.01, 2e-3, ramp, w.g)
+    b_ = rt.rk_step_tableau(T, w.psi0, 0.01, 2e-3, ramp, w.g, *tableau.rk4())
+    assert np.linalg.norm(a - b_) <= 1e-15 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("name,fn,order", METHODS)
+def test_memory_optimised_form_of_each_method(name, fn, order):
+    """App. A form with the derived (a*, b*) reproduces the k-form step."""
+    w, T, ramp = _ramp_problem()
+    A, b = fn()
+    a_star, b_star = tableau.modified_tableau(A, b)
+    c = [float(sum(r)) for r in A]
+    y0, t, dt = w.psi0, 0.013, 2e-3
+    Y = [y0]
+    s = len(b)
+    for i in range(s):
+        k = rt.rhs(T, ramp(t + c[i] * dt), w.g, Y[i])
+        if i < s - 1:
+            Y.append(sum(float(a_star[i][j]) * Y[j] for j in range(i + 1)) + dt * float(A[i + 1][i]) * k)
+        else:
+            y1 = sum(float(b_star[j]) * Y[j] for j in range(s)) + dt * float(b[s - 1]) * k
+    ref = rt.rk_step_tableau(T, y0, t, dt, ramp, w.g, A, b)
+    assert np.linalg.norm(y1 - ref) <= 1e-13 * np.linalg.norm(ref)
