@@ -55,6 +55,19 @@ def algo_bytes(fam: str, R: int, scheme: int = 0) -> int:
     return table.get(fam, 0)
 
 
+# stored stage states each stage of the memory-optimised forms (App. A)
+# reads at the site besides its stencil input: the non-zero entries of the
+# a* rows (and of b* for the last stage) other than the input's own
+RK_HIST = {"rkhe3": [0, 1, 2], "rkck": [0, 1, 2, 3, 4, 5]}
+
+
+def rk_generic_bytes(integrator: str, R: int) -> int:
+    """Algorithmic HBM bytes per site per step: every stage reads its input
+    state, the stored states it combines and the field, and writes one state."""
+    C = 2 * R
+    return sum((1 + h) * C + R + C for h in RK_HIST[integrator])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -187,6 +200,39 @@ def bench_c2(args, dev, dtype, report):
     return w
 
 
+def bench_integrators(args, dev, report):
+    """Real time at the headline size with each explicit integrator (Sec.
+    II.A): ms per step and effective bandwidth of the memory-optimised forms."""
+    import torch
+    from paper_2603_05447_amd import config_describe
+    w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, "c128")
+    n, R = w.n_active, 8
+    steps = max(args.int_steps, 1)
+    out = {"workload": "rf-bubble 1024x1024x512, 16,028,656 active sites, complex128", "steps": steps}
+    scheme = config_describe(g.get_config())["rk_scheme"]
+    for integ in ("rk4", "rkhe3", "rkck"):
+        g.real_time(psi, pot_rt, w.g, w.dt, 2, observe=False, integrator=integ)     # warm-up
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        g.real_time(psi, pot_rt, w.g, w.dt, steps, observe=False, integrator=integ)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        b = (sum(algo_bytes(f"rk_stage{i}", R, scheme) for i in range(1, 5)) if integ == "rk4"
+             else rk_generic_bytes(integ, R))
+        out[integ] = {"ms_per_step": ms, "site_updates_per_s": n / (ms * 1e-3),
+                      "algo_bytes_per_site_step": b, "eff_GBps": b * n / (ms * 1e-3) / 1e9,
+                      "stages": {"rk4": 4, "rkhe3": 3, "rkck": 6}[integ]}
+        log(f"[bench] {integ}: {ms:.3f} ms/step, {b} B/site/step, {out[integ]['eff_GBps']:.0f} GB/s")
+    obs = g.observe(psi, pot_rt, 0.0, w.g)
+    out["final_norm"] = obs["norm"]
+    report["integrators_c2"] = out
+    del psi, U, g
+    torch.cuda.empty_cache()
+
+
 def cpu_baseline(args):
     """The FP64 oracle, single-threaded, on a slab of the headline workload:
     the active sites of x-planes [448, 576) of the 1024 x 1024 x 512 grid
@@ -244,6 +290,8 @@ def bench_adjoint(args, dev, report):
     tgt = psi0.clone()
     g.imag_time(tgt, Potential.rf(U, w.omega, [0.0], [w.knot_delta[-1]]), w.g, 1e-3, 300, observe=False)
     pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
+    # the ramp lasts 2 time units whatever the step count: refuse a dt above RK4's bound
+    g.real_time(psi0.clone(), pot, w.g, w.dt, 1, observe=False, check_stability=True)
     g.fidelity_grad(psi0, tgt, pot, w.g, w.dt, 20)   # warmup
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -350,9 +398,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip complex64, adjoint and batched legs")
-    ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--adj-steps", type=int, default=2000,
+                    help="steps of the 2-time-unit adjoint ramp (dt = 2/steps; RK4 needs steps >= 1100)")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--int-steps", type=int, default=100, help="steps per integrator in the RKHE3/RK4/RKCK leg")
     ap.add_argument("--c5", type=int, default=0, help="run the 60M-site FP32-vs-FP64 study for this many steps")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reference for HBM byte counters)")
@@ -387,6 +437,8 @@ def main():
         log(f"[bench] adjoint done: {report['adjoint_c3']['grads_per_s']:.3g} grads/s")
         bench_batched(args, dev, report)
         log("[bench] batched done")
+        bench_integrators(args, dev, report)
+        log("[bench] integrators done")
     if args.c5 > 0:
         bench_c5(args, dev, report)
         log("[bench] C5 precision study done")
@@ -430,7 +482,7 @@ def main():
     if "c64" in report:
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
-    for key in ("adjoint_c3", "batched_c4", "precision_c5"):
+    for key in ("adjoint_c3", "batched_c4", "integrators_c2", "precision_c5"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)

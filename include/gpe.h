@@ -58,7 +58,18 @@ typedef enum {
 
 typedef enum { GPE_C128 = 0, GPE_C64 = 1 } gpe_dtype;
 
-typedef enum { GPE_MODE_ITP = 0, GPE_MODE_RT = 1, GPE_MODE_ADJ = 2 } gpe_mode;
+typedef enum {
+  GPE_MODE_ITP = 0,       /* gpe_imag_time */
+  GPE_MODE_RT = 1,        /* gpe_real_time with GPE_RK4 */
+  GPE_MODE_ADJ = 2,       /* gpe_fidelity_grad */
+  GPE_MODE_RT_RKHE3 = 3,  /* gpe_real_time with GPE_RKHE3 */
+  GPE_MODE_RT_RKCK = 4    /* gpe_real_time with GPE_RKCK */
+} gpe_mode;
+
+/* Explicit integrators for real time (Sec. II.A; App. A gives each one's
+ * memory-optimised form): the classic fourth-order method, Heun's
+ * third-order method and the fifth-order Cash-Karp weights. */
+typedef enum { GPE_RK4 = 0, GPE_RKHE3 = 1, GPE_RKCK = 2 } gpe_integrator;
 
 typedef struct {
   int64_t n[3];   /* points per axis, each >= 1 */
@@ -95,7 +106,7 @@ typedef struct {
   double norm_target;     /* N of eq. (3) for imaginary time; <= 0 means 1 */
   int64_t obs_every;      /* > 0: record an observation every obs_every steps */
   int32_t check_stability;/* nonzero: fail with GPE_ERR_UNSTABLE above the bound */
-  int32_t reserved;       /* must be 0 */
+  int32_t integrator;     /* gpe_integrator for real time (0 = GPE_RK4); other calls need 0 */
 } gpe_params;
 
 typedef struct { double norm, energy, mu; } gpe_obs;
@@ -139,7 +150,8 @@ gpe_status gpe_grid_runs(gpe_grid grid, int64_t* out_host);
 gpe_status gpe_grid_destroy(gpe_grid grid);
 
 /* Size in bytes of the device work buffer a call needs.
- *   mode GPE_MODE_ITP: gpe_imag_time; GPE_MODE_RT: gpe_real_time;
+ *   mode GPE_MODE_ITP: gpe_imag_time; GPE_MODE_RT / _RT_RKHE3 / _RT_RKCK:
+ *   gpe_real_time with that integrator (3, 2 and 5 state vectors);
  *   GPE_MODE_ADJ: gpe_fidelity_grad with nsteps and ckpt_every as given. */
 gpe_status gpe_work_bytes(gpe_grid grid, gpe_dtype dtype, int32_t mode, int64_t nsteps, int64_t ckpt_every,
                           size_t* bytes);
@@ -166,11 +178,19 @@ gpe_status gpe_imag_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_po
                          const gpe_params* params, int64_t nsteps, void* work, size_t work_bytes,
                          void* stream, gpe_obs* final_host, gpe_obs* history_dev);
 
-/* Real-time evolution with RK4 (Sec. II.A eq. (8)), in the memory-optimised
- * form of App. A (stored stage states y2, y3, y4; final combination
- * b* = (-1/3, 1/3, 2/3, 1/3) plus dt/6 k4).  Step n starts at t0 + n dt;
- * stage times t + (0, 1/2, 1/2, 1) dt.
- * check_stability: dt * (lambda_max(T) + max V) <= 2 sqrt(2). */
+/* Real-time evolution (Sec. II.A eq. (8)) with params->integrator, in the
+ * memory-optimised form of App. A, eqs. (A6)-(A7): each stage reads one
+ * stage state through the stencil plus the earlier stored stage states at
+ * the same site, and writes the next stage state; the last stage overwrites
+ * psi.
+ *   GPE_RK4  : stored y2, y3, y4; final b* = (-1/3, 1/3, 2/3, 1/3) plus
+ *              dt/6 k4; stage times t + (0, 1/2, 1/2, 1) dt.
+ *   GPE_RKHE3: stored y2, y3; stage times t + (0, 1/3, 2/3) dt.
+ *   GPE_RKCK : stored y2..y6; stage times t + (0, 1/5, 3/10, 3/5, 1, 7/8) dt.
+ * Step n starts at t0 + n dt.  work: gpe_work_bytes of the matching mode.
+ * check_stability: dt * (lambda_max(T) + max V) <= 2 sqrt(2) (RK4), sqrt(3)
+ * (RKHE3) or 1 (RKCK, whose stability function exceeds 1 in modulus on the
+ * whole imaginary axis; at 1 the growth per step is below 2.3e-4). */
 gpe_status gpe_real_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
                          const gpe_params* params, double t0, int64_t nsteps, void* work, size_t work_bytes,
                          void* stream, gpe_obs* final_host, gpe_obs* history_dev);
@@ -184,7 +204,8 @@ gpe_status gpe_observe(gpe_grid grid, gpe_dtype dtype, const void* psi, const gp
 gpe_status gpe_overlap(gpe_grid grid, gpe_dtype dtype, const void* a, const void* b, void* stream,
                        double* out_host);
 
-/* Fidelity loss L = 1 - |<psi_target|psi(T)>|^2 after nsteps RK4 steps from
+/* Fidelity loss L = 1 - |<psi_target|psi(T)>|^2 after nsteps RK4 steps
+ * (params->integrator must be GPE_RK4) from
  * psi0 at t0 under an RF_RAMP potential, and dL/dDelta_k for every knot, by
  * the discrete adjoint of the RK4 map (the paper optimises the ramp without
  * gradients, Sec. V; this is the gradient of the same forward scheme).
@@ -218,9 +239,9 @@ gpe_status gpe_batch_destroy(gpe_batch batch);
 gpe_status gpe_batch_work_bytes(gpe_batch batch, gpe_dtype dtype, int32_t mode, int64_t nsteps,
                                 int64_t ckpt_every, size_t* bytes);
 
-/* RK4 real time for every instance: instance i uses ramps[i] (RF_RAMP, with
+/* Real time for every instance: instance i uses ramps[i] (RF_RAMP, with
  * field = its U) and params[i] (g, dt); all instances take nsteps steps from
- * t0.  use_graph != 0 captures one step (all stage kernels of all instances)
+ * t0 with the same integrator (params[i].integrator equal for all i).  use_graph != 0 captures one step (all stage kernels of all instances)
  * into a hipGraph on first use and replays it; the step counter lives in
  * device memory so one graph serves every step.  final_host: optional n
  * observations (per-instance FP64 reductions). */

@@ -11,7 +11,8 @@ GPE_OK, GPE_ERR_ARG, GPE_ERR_ALLOC, GPE_ERR_DEVICE, GPE_ERR_STATE, GPE_ERR_UNSTA
 STATUS_NAMES = ["GPE_OK", "GPE_ERR_ARG", "GPE_ERR_ALLOC", "GPE_ERR_DEVICE", "GPE_ERR_STATE",
                 "GPE_ERR_UNSTABLE", "GPE_ERR_NONFINITE"]
 GPE_C128, GPE_C64 = 0, 1
-GPE_MODE_ITP, GPE_MODE_RT, GPE_MODE_ADJ = 0, 1, 2
+GPE_MODE_ITP, GPE_MODE_RT, GPE_MODE_ADJ, GPE_MODE_RT_RKHE3, GPE_MODE_RT_RKCK = 0, 1, 2, 3, 4
+GPE_RK4, GPE_RKHE3, GPE_RKCK = 0, 1, 2
 GPE_POT_STATIC, GPE_POT_RF_RAMP = 0, 1
 GPE_MAX_KNOTS = 32
 
@@ -27,7 +28,7 @@ class Potential(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("dt", C.c_double), ("norm_target", C.c_double), ("obs_every", C.c_int64),
-                ("check_stability", C.c_int32), ("reserved", C.c_int32)]
+                ("check_stability", C.c_int32), ("integrator", C.c_int32)]
 
 
 class Obs(C.Structure):

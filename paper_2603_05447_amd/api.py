@@ -83,12 +83,23 @@ class Potential:
         return p, keep
 
 
-def make_params(g: float, dt: float, norm_target: float = 1.0, obs_every: int = 0, check_stability: bool = False):
+INTEGRATORS = {"rk4": L.GPE_RK4, "rkhe3": L.GPE_RKHE3, "rkck": L.GPE_RKCK}
+_RT_MODE = {L.GPE_RK4: L.GPE_MODE_RT, L.GPE_RKHE3: L.GPE_MODE_RT_RKHE3, L.GPE_RKCK: L.GPE_MODE_RT_RKCK}
+
+
+def _integrator(name: str) -> int:
+    if name not in INTEGRATORS:
+        raise ValueError(f"integrator must be one of {sorted(INTEGRATORS)}, got {name!r}")
+    return INTEGRATORS[name]
+
+
+def make_params(g: float, dt: float, norm_target: float = 1.0, obs_every: int = 0, check_stability: bool = False,
+                integrator: str = "rk4"):
     p = L.Params()
     p.g, p.dt, p.norm_target = float(g), float(dt), float(norm_target)
     p.obs_every = int(obs_every)
     p.check_stability = 1 if check_stability else 0
-    p.reserved = 0
+    p.integrator = _integrator(integrator)
     return p
 
 
@@ -185,11 +196,11 @@ class Grid:
 
     def real_time(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, steps: int, t0: float = 0.0,
                   obs_every: int = 0, history: Optional[torch.Tensor] = None, stream=None, observe: bool = True,
-                  check_stability: bool = False) -> Optional[dict]:
+                  check_stability: bool = False, integrator: str = "rk4") -> Optional[dict]:
         dt_ = _dtype_of(psi)
         cp, keep = pot.as_c(dt_)
-        prm = make_params(g, dt, 1.0, obs_every, check_stability)
-        w = self.work(dt_, L.GPE_MODE_RT, steps)
+        prm = make_params(g, dt, 1.0, obs_every, check_stability, integrator)
+        w = self.work(dt_, _RT_MODE[prm.integrator], steps)
         o = L.Obs()
         check(L.load().gpe_real_time(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), float(t0),
                                      int(steps), w.data_ptr(), w.numel(), _stream(stream),
@@ -251,11 +262,12 @@ class Grid:
         check(L.load().gpe_grid_get_config(self._h, C.byref(c)))
         return c.value
 
-    def autotune(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, reps: int = 5, stream=None):
+    def autotune(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, reps: int = 5, stream=None,
+                 integrator: str = "rk4"):
         dt_ = _dtype_of(psi)
         cp, keep = pot.as_c(dt_)
-        prm = make_params(g, dt)
-        w = self.work(dt_, L.GPE_MODE_RT, reps)
+        prm = make_params(g, dt, integrator=integrator)
+        w = self.work(dt_, _RT_MODE[prm.integrator], reps)
         n = config_count()
         times = (C.c_double * n)(*([-1.0] * n))
         best = C.c_int32()
@@ -313,18 +325,19 @@ class Batch:
         return arr, keep
 
     @staticmethod
-    def _params(gs, dts):
+    def _params(gs, dts, integrator: str = "rk4"):
         arr = (L.Params * len(gs))()
         for i, (g, dt) in enumerate(zip(gs, dts)):
-            arr[i] = make_params(g, dt)
+            arr[i] = make_params(g, dt, integrator=integrator)
         return arr
 
     def real_time(self, psi: torch.Tensor, field: torch.Tensor, ramps, gs, dts, steps: int, t0: float = 0.0,
-                  use_graph: bool = True, work: Optional[torch.Tensor] = None, stream=None, observe: bool = True):
+                  use_graph: bool = True, work: Optional[torch.Tensor] = None, stream=None, observe: bool = True,
+                  integrator: str = "rk4"):
         dt_ = _dtype_of(psi)
         ra, keep = self._ramps(ramps)
-        pa = self._params(gs, dts)
-        nb = self.work_bytes(dt_, L.GPE_MODE_RT, steps)
+        pa = self._params(gs, dts, integrator)
+        nb = self.work_bytes(dt_, _RT_MODE[pa[0].integrator], steps)
         if work is None or work.numel() < nb:
             work = torch.empty(max(nb, 256), dtype=torch.uint8, device=psi.device)
         obs = (L.Obs * len(self.grids))()

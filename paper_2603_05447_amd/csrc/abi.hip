@@ -176,10 +176,10 @@ struct Problem {
   // captured forward-step graphs, keyed by buffer pointers
   struct GraphKey {
     const void *psi, *field, *work;
-    int dtype, config, scheme;
+    int dtype, config, scheme, integrator;
     bool operator<(const GraphKey& o) const {
-      return std::tie(psi, field, work, dtype, config, scheme) <
-             std::tie(o.psi, o.field, o.work, o.dtype, o.config, o.scheme);
+      return std::tie(psi, field, work, dtype, config, scheme, integrator) <
+             std::tie(o.psi, o.field, o.work, o.dtype, o.config, o.scheme, o.integrator);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -394,14 +394,59 @@ int64_t ckpt_interval(int64_t nsteps, int64_t ckpt_every) {
   return std::max<int64_t>(k, 1);
 }
 
+// Memory-optimised tableaux of App. A (eqs. (A6)-(A7)): y^(i+1) = sum_j
+// astar[i][j] y^(j) + dt asub[i] k_i and y_1 = sum_j bstar[j] y^(j) + dt bs k_s,
+// k_i = f(t + c[i] dt, y^(i)); the coefficients are the ones printed there for
+// Heun's third-order method and the fifth-order Cash-Karp weights.
+struct MemOptTableau {
+  int s;
+  double c[6];
+  double asub[6];
+  double astar[6][6];
+  double bstar[6];
+  double bs;
+};
+
+const MemOptTableau kRKHE3 = {3,
+                              {0.0, 1.0 / 3.0, 2.0 / 3.0},
+                              {1.0 / 3.0, 2.0 / 3.0},
+                              {{1.0}, {1.0, 0.0}},
+                              {1.0 / 4.0, 3.0 / 4.0, 0.0},
+                              3.0 / 4.0};
+
+const MemOptTableau kRKCK = {6,
+                             {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0},
+                             {1.0 / 5.0, 9.0 / 40.0, 6.0 / 5.0, 35.0 / 27.0, 253.0 / 4096.0},
+                             {{1.0},
+                              {5.0 / 8.0, 3.0 / 8.0},
+                              {2.0, 3.0, -4.0},
+                              {-49.0 / 81.0, 35.0 / 27.0, 200.0 / 81.0, -175.0 / 81.0},
+                              {253.0 / 12288.0, -3795.0 / 4096.0, 1375.0 / 1536.0, 2875.0 / 4096.0, 1265.0 / 4096.0}},
+                             {-991.0 / 15939.0, -3865.0 / 5313.0, 5000.0 / 5313.0, 3125.0 / 4554.0, 25.0 / 154.0, 0.0},
+                             512.0 / 1771.0};
+
+const MemOptTableau* integrator_tableau(int integrator) {
+  return integrator == GPE_RKHE3 ? &kRKHE3 : (integrator == GPE_RKCK ? &kRKCK : nullptr);
+}
+
+int rt_work_mode(int integrator) {
+  return integrator == GPE_RKHE3 ? GPE_MODE_RT_RKHE3 : (integrator == GPE_RKCK ? GPE_MODE_RT_RKCK : GPE_MODE_RT);
+}
+
+int integrator_buffers(int integrator) {
+  const MemOptTableau* t = integrator_tableau(integrator);
+  return t ? t->s - 1 : 3;
+}
+
 size_t work_bytes_for(int64_t n, int dtype, int mode, int64_t nsteps, int64_t ckpt_every) {
   Carver c(nullptr);
   const size_t st = (size_t)n * csize(dtype);
   if (mode == GPE_MODE_ITP) {
     c.take(st);
     c.take((size_t)n * rsize(dtype));
-  } else if (mode == GPE_MODE_RT) {
-    for (int i = 0; i < 3; ++i) c.take(st);
+  } else if (mode == GPE_MODE_RT || mode == GPE_MODE_RT_RKHE3 || mode == GPE_MODE_RT_RKCK) {
+    const int integ = mode == GPE_MODE_RT ? GPE_RK4 : (mode == GPE_MODE_RT_RKHE3 ? GPE_RKHE3 : GPE_RKCK);
+    for (int i = 0; i < integrator_buffers(integ); ++i) c.take(st);
   } else {
     // checkpoints + per segment step: state, Y2, Y3, Y4 + 8 vectors
     const int64_t K = ckpt_interval(nsteps, ckpt_every);
@@ -480,7 +525,8 @@ gpe_status check_params(const gpe_params* p) {
   if (!std::isfinite(p->g)) return fail(GPE_ERR_ARG, "g must be finite");
   if (!std::isfinite(p->norm_target)) return fail(GPE_ERR_ARG, "norm_target must be finite");
   if (p->obs_every < 0) return fail(GPE_ERR_ARG, "obs_every must be >= 0");
-  if (p->reserved != 0) return fail(GPE_ERR_ARG, "params.reserved must be 0");
+  if (p->integrator != GPE_RK4 && p->integrator != GPE_RKHE3 && p->integrator != GPE_RKCK)
+    return fail(GPE_ERR_ARG, "params.integrator must be GPE_RK4, GPE_RKHE3 or GPE_RKCK");
   return GPE_OK;
 }
 
@@ -575,6 +621,34 @@ gpe_status rk_step(const Ctx& c, const void* y0, const void* field, void* b1, vo
   return GPE_OK;
 }
 
+// One step of a memory-optimised method: Y[0] = y0 (in/out), Y[1..s-1] scratch.
+template <typename R>
+gpe_status rk_generic_step(const Ctx& c, const MemOptTableau& tb, void* y0, const void* field, void* const* buf,
+                           int64_t step) {
+  std::vector<void*> Y(tb.s);
+  Y[0] = y0;
+  for (int i = 1; i < tb.s; ++i) Y[i] = buf[i - 1];
+  for (int i = 0; i < tb.s; ++i) {
+    const bool final_stage = (i == tb.s - 1);
+    const double* row = final_stage ? tb.bstar : tb.astar[i];
+    // coefficient of the stencil input y^(i) itself, then the earlier states
+    const double ccur = row[i];
+    std::vector<const void*> hist;
+    std::vector<double> hc;
+    for (int j = 0; j < i; ++j)
+      if (row[j] != 0.0) {
+        hist.push_back(Y[j]);
+        hc.push_back(row[j]);
+      }
+    const double cdt = final_stage ? tb.bs : tb.asub[i];
+    void* out = final_stage ? y0 : Y[i + 1];
+    LTRY(run_rk_generic<R>(c.pl, c.cfg, Y[i], ccur, (int)hist.size(), hist.data(), hc.data(), cdt, tb.c[i], field,
+                           out, step, c.s));
+  }
+  if (step < 0) LTRY(run_tick(c.pl.step, 1, c.s));
+  return GPE_OK;
+}
+
 template <typename R>
 gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps, void* work, int64_t obs_every,
                      gpe_obs* hist) {
@@ -601,9 +675,25 @@ gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps,
 
 template <typename R>
 gpe_status drive_rt(const Ctx& c, void* psi, const void* field, int64_t nsteps, void* work, int64_t obs_every,
-                    gpe_obs* hist) {
+                    gpe_obs* hist, int integrator = GPE_RK4) {
   Carver cv(work);
   const size_t st = (size_t)c.P->total * 2 * sizeof(R);
+  const MemOptTableau* tb = integrator_tableau(integrator);
+  if (tb) {
+    std::vector<void*> buf(tb->s - 1);
+    for (auto& b : buf) b = cv.take(st);
+    int64_t k = 0;
+    for (int64_t n = 0; n < nsteps; ++n) {
+      if (hist && obs_every > 0 && n % obs_every == 0) {
+        LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, false, n, c.s));
+        LTRY(run_finalize(c.pl, FIN_OBS, hist + k * c.P->n_inst, c.s));
+        ++k;
+      }
+      gpe_status r = rk_generic_step<R>(c, *tb, psi, field, buf.data(), n);
+      if (r != GPE_OK) return r;
+    }
+    return GPE_OK;
+  }
   void* y2 = cv.take(st);
   void* y3 = cv.take(st);
   void* y4 = cv.take(st);
@@ -643,10 +733,10 @@ gpe_status read_obs(Problem& P, gpe_obs* out_host, hipStream_t s) {
 // Captured graph of one in-place RK4 step of psi (scratch y2, y3, y4); the
 // step index comes from the device counter, so one graph serves every step.
 template <typename R>
-static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* field, void* y2, void* y3, void* y4,
-                             hipGraphExec_t* out) {
+static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* field, int integrator,
+                             void* const* bufs, hipGraphExec_t* out) {
   Problem& P = *c.P;
-  Problem::GraphKey key{psi, field, y2, dtype, P.config, c.cfg.scheme};
+  Problem::GraphKey key{psi, field, bufs[0], dtype, P.config, c.cfg.scheme, integrator};
   auto it = P.graphs.find(key);
   if (it != P.graphs.end()) {
     *out = it->second;
@@ -661,7 +751,9 @@ static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* fie
   if (e == hipSuccess) {
     Ctx cc = c;
     cc.s = cap;
-    r = rk_step<R>(cc, psi, field, y2, y3, y4, psi, false, nullptr, -1);
+    const MemOptTableau* tb = integrator_tableau(integrator);
+    r = tb ? rk_generic_step<R>(cc, *tb, psi, field, bufs, -1)
+           : rk_step<R>(cc, psi, field, bufs[0], bufs[1], bufs[2], psi, false, nullptr, -1);
     hipError_t e2 = hipStreamEndCapture(cap, &graph);
     if (r == GPE_OK && e2 != hipSuccess) r = hip_fail(e2, "hipStreamEndCapture");
   } else {
@@ -716,7 +808,8 @@ gpe_status drive_adjoint(const Ctx& c_in, const void* psi0, const void* target, 
   LTRY(hipMemcpyAsync(cur, psi0, st, hipMemcpyDeviceToDevice, c.s));
   hipGraphExec_t fwd = nullptr;
   if (use_graph) {
-    gpe_status r = step_graph<R>(c, sizeof(R) == 8 ? GPE_C128 : GPE_C64, cur, field, y2, y3, y4, &fwd);
+    void* bufs[3] = {y2, y3, y4};
+    gpe_status r = step_graph<R>(c, sizeof(R) == 8 ? GPE_C128 : GPE_C64, cur, field, GPE_RK4, bufs, &fwd);
     if (r != GPE_OK) return r;
     LTRY(run_set_step(c.pl.step, 0, c.s));
   }
@@ -809,26 +902,33 @@ gpe_status field_vmax(const Ctx& c, const void* field, const std::vector<InstPar
 }  // namespace
 
 template <typename R>
-static gpe_status rt_stability(const Ctx& c, const std::vector<InstParams>& ps, const void* field, double dt_max_g) {
+static gpe_status rt_stability(const Ctx& c, const std::vector<InstParams>& ps, const void* field, double dt_max_g,
+                               int integrator = GPE_RK4) {
   double vmax = 0.0;
   gpe_status st = field_vmax<R>(c, field, ps, &vmax);
   if (st != GPE_OK) return st;
   const double lam = kinetic_bound(*c.P) + vmax;
-  if (dt_max_g * lam > 2.0 * std::sqrt(2.0))
-    return fail(GPE_ERR_UNSTABLE, "dt = %g exceeds the RK4 bound 2*sqrt(2)/lambda = %g (lambda = %g)", dt_max_g,
-                2.0 * std::sqrt(2.0) / lam, lam);
+  // Imaginary-axis bounds of the stability functions: 2 sqrt 2 for RK4,
+  // sqrt 3 for any three-stage third-order method.  The Cash-Karp fifth-order
+  // weights have |R(iy)| = 1 + y^6/7200 + O(y^8) > 1 for every y, so no step
+  // is strictly stable; the check then caps dt lambda at 1, where the
+  // spurious growth per step stays below 2.3e-4.
+  const double bound = integrator == GPE_RKHE3 ? std::sqrt(3.0) : (integrator == GPE_RKCK ? 1.0 : 2.0 * std::sqrt(2.0));
+  if (dt_max_g * lam > bound)
+    return fail(GPE_ERR_UNSTABLE, "dt = %g exceeds the stability bound %g/lambda = %g (lambda = %g)", dt_max_g, bound,
+                bound / lam, lam);
   return GPE_OK;
 }
 
 template <typename R>
-static gpe_status batch_rt_graph(const Ctx& c, int dtype, void* psi, const void* field, int64_t nsteps, void* work) {
+static gpe_status batch_rt_graph(const Ctx& c, int dtype, void* psi, const void* field, int64_t nsteps, void* work,
+                                 int integrator) {
   Carver cv(work);
   const size_t st = (size_t)c.P->total * 2 * sizeof(R);
-  void* y2 = cv.take(st);
-  void* y3 = cv.take(st);
-  void* y4 = cv.take(st);
+  void* bufs[5];
+  for (int i = 0; i < integrator_buffers(integrator); ++i) bufs[i] = cv.take(st);
   hipGraphExec_t exec = nullptr;
-  gpe_status r = step_graph<R>(c, dtype, psi, field, y2, y3, y4, &exec);
+  gpe_status r = step_graph<R>(c, dtype, psi, field, integrator, bufs, &exec);
   if (r != GPE_OK) return r;
   HIP_TRY(run_set_step(c.pl.step, 0, c.s));
   for (int64_t n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(exec, c.s));
@@ -975,7 +1075,7 @@ gpe_status gpe_work_bytes(gpe_grid g, gpe_dtype dtype, int32_t mode, int64_t nst
   if (!g || !bytes) return fail(GPE_ERR_ARG, "grid or bytes is NULL");
   gpe_status st = check_dtype(dtype);
   if (st != GPE_OK) return st;
-  if (mode < GPE_MODE_ITP || mode > GPE_MODE_ADJ) return fail(GPE_ERR_ARG, "unknown mode");
+  if (mode < GPE_MODE_ITP || mode > GPE_MODE_RT_RKCK) return fail(GPE_ERR_ARG, "unknown mode");
   if (nsteps < 0 || ckpt_every < 0) return fail(GPE_ERR_ARG, "nsteps and ckpt_every must be >= 0");
   *bytes = work_bytes_for(g->lay.n_active, dtype, mode, nsteps, ckpt_every);
   return GPE_OK;
@@ -1076,7 +1176,8 @@ gpe_status gpe_real_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_poten
   if (!std::isfinite(t0)) return fail(GPE_ERR_ARG, "t0 must be finite");
   if (nsteps < 0) return fail(GPE_ERR_ARG, "nsteps must be >= 0");
   if (prm->obs_every > 0 && !history_dev) return fail(GPE_ERR_ARG, "obs_every > 0 needs history_dev");
-  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, GPE_MODE_RT, nsteps, 0));
+  st = check_work(work, work_bytes,
+                  work_bytes_for(g->lay.n_active, dtype, rt_work_mode(prm->integrator), nsteps, 0));
   if (st != GPE_OK) return st;
   DeviceGuard dg(g->device);
   hipStream_t s = (hipStream_t)stream;
@@ -1087,12 +1188,13 @@ gpe_status gpe_real_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_poten
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
   if (prm->check_stability) {
-    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, pot->field, prm->dt)
-                           : rt_stability<float>(c, ps, pot->field, prm->dt);
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, pot->field, prm->dt, prm->integrator)
+                           : rt_stability<float>(c, ps, pot->field, prm->dt, prm->integrator);
     if (st != GPE_OK) return st;
   }
-  st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev)
-                         : drive_rt<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev);
+  st = dtype == GPE_C128
+           ? drive_rt<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, prm->integrator)
+           : drive_rt<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, prm->integrator);
   if (st != GPE_OK) return st;
   if (final_host) {
     // observation at the final time t0 + nsteps dt
@@ -1169,6 +1271,7 @@ gpe_status gpe_fidelity_grad(gpe_grid g, gpe_dtype dtype, const void* psi0, cons
   if (st == GPE_OK) st = check_params(prm);
   if (st != GPE_OK) return st;
   if (pot->kind != GPE_POT_RF_RAMP) return fail(GPE_ERR_ARG, "fidelity gradient needs an RF_RAMP potential");
+  if (prm->integrator != GPE_RK4) return fail(GPE_ERR_ARG, "the fidelity gradient is the adjoint of RK4 only");
   if (!loss_host || !grad_host) return fail(GPE_ERR_ARG, "loss_host and grad_host are required");
   if (psi_final) {
     st = check_ptr(psi_final, "psi_final");
@@ -1246,7 +1349,7 @@ gpe_status gpe_batch_work_bytes(gpe_batch b, gpe_dtype dtype, int32_t mode, int6
   if (!b || !bytes) return fail(GPE_ERR_ARG, "batch or bytes is NULL");
   gpe_status st = check_dtype(dtype);
   if (st != GPE_OK) return st;
-  if (mode < GPE_MODE_ITP || mode > GPE_MODE_ADJ) return fail(GPE_ERR_ARG, "unknown mode");
+  if (mode < GPE_MODE_ITP || mode > GPE_MODE_RT_RKCK) return fail(GPE_ERR_ARG, "unknown mode");
   if (nsteps < 0 || ckpt_every < 0) return fail(GPE_ERR_ARG, "nsteps and ckpt_every must be >= 0");
   *bytes = work_bytes_for(b->prob->total, dtype, mode, nsteps, ckpt_every);
   return GPE_OK;
@@ -1287,7 +1390,10 @@ gpe_status gpe_batch_real_time(gpe_batch b, gpe_dtype dtype, void* psi, const vo
   std::vector<InstParams> ps;
   st = batch_params(b, ramps, prms, t0, ps);
   if (st != GPE_OK) return st;
-  st = check_work(work, work_bytes, work_bytes_for(b->prob->total, dtype, GPE_MODE_RT, nsteps, 0));
+  const int integ = prms[0].integrator;
+  for (int i = 1; i < b->prob->n_inst; ++i)
+    if (prms[i].integrator != integ) return fail(GPE_ERR_ARG, "every instance must use the same integrator");
+  st = check_work(work, work_bytes, work_bytes_for(b->prob->total, dtype, rt_work_mode(integ), nsteps, 0));
   if (st != GPE_OK) return st;
   DeviceGuard dg(b->device);
   hipStream_t s = (hipStream_t)stream;
@@ -1301,15 +1407,16 @@ gpe_status gpe_batch_real_time(gpe_batch b, gpe_dtype dtype, void* psi, const vo
   for (auto& p : ps) dtmax = std::max(dtmax, p.dt);
   for (int i = 0; i < b->prob->n_inst; ++i) check = check || prms[i].check_stability;
   if (check) {
-    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, field, dtmax) : rt_stability<float>(c, ps, field, dtmax);
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, field, dtmax, integ)
+                           : rt_stability<float>(c, ps, field, dtmax, integ);
     if (st != GPE_OK) return st;
   }
   if (use_graph) {
-    st = dtype == GPE_C128 ? batch_rt_graph<double>(c, dtype, psi, field, nsteps, work)
-                           : batch_rt_graph<float>(c, dtype, psi, field, nsteps, work);
+    st = dtype == GPE_C128 ? batch_rt_graph<double>(c, dtype, psi, field, nsteps, work, integ)
+                           : batch_rt_graph<float>(c, dtype, psi, field, nsteps, work, integ);
   } else {
-    st = dtype == GPE_C128 ? drive_rt<double>(c, psi, field, nsteps, work, 0, nullptr)
-                           : drive_rt<float>(c, psi, field, nsteps, work, 0, nullptr);
+    st = dtype == GPE_C128 ? drive_rt<double>(c, psi, field, nsteps, work, 0, nullptr, integ)
+                           : drive_rt<float>(c, psi, field, nsteps, work, 0, nullptr, integ);
   }
   if (st != GPE_OK) return st;
   if (final_host) {
@@ -1337,6 +1444,8 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi
   std::vector<InstParams> ps;
   st = batch_params(b, ramps, prms, t0, ps);
   if (st != GPE_OK) return st;
+  for (int i = 0; i < b->prob->n_inst; ++i)
+    if (prms[i].integrator != GPE_RK4) return fail(GPE_ERR_ARG, "the fidelity gradient is the adjoint of RK4 only");
   st = check_work(work, work_bytes, work_bytes_for(b->prob->total, dtype, GPE_MODE_ADJ, nsteps, ckpt_every));
   if (st != GPE_OK) return st;
   DeviceGuard dg(b->device);
@@ -1403,7 +1512,7 @@ gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_p
   if (st == GPE_OK) st = check_params(prm);
   if (st != GPE_OK) return st;
   if (reps < 1) return fail(GPE_ERR_ARG, "reps must be >= 1");
-  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, GPE_MODE_RT, reps, 0));
+  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, rt_work_mode(prm->integrator), reps, 0));
   if (st != GPE_OK) return st;
   DeviceGuard dg(g->device);
   hipStream_t s = (hipStream_t)stream;
@@ -1424,15 +1533,15 @@ gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_p
       st = g->prob->upload(*c.cs, ps, s);
       if (st != GPE_OK) break;
       // one untimed step, then `reps` timed steps
-      st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, 1, work, 0, nullptr)
-                             : drive_rt<float>(c, psi, pot->field, 1, work, 0, nullptr);
+      st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, 1, work, 0, nullptr, prm->integrator)
+                             : drive_rt<float>(c, psi, pot->field, 1, work, 0, nullptr, prm->integrator);
       if (st != GPE_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) {
         st = fail(GPE_ERR_DEVICE, "hipEventRecord");
         break;
       }
-      st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, reps, work, 0, nullptr)
-                             : drive_rt<float>(c, psi, pot->field, reps, work, 0, nullptr);
+      st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, reps, work, 0, nullptr, prm->integrator)
+                             : drive_rt<float>(c, psi, pot->field, reps, work, 0, nullptr, prm->integrator);
       if (st != GPE_OK) break;
       float ms = 0.f;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -90,7 +90,7 @@ inline int chunk_capacity(const LaunchConfig& c) { return c.block * c.spt; }
 // Kernel families (for per-kernel timing).
 enum Family {
   FAM_ITP1 = 0, FAM_ITP2, FAM_RK1, FAM_RK2, FAM_RK3, FAM_RK4, FAM_OBSERVE,
-  FAM_ADJ1, FAM_ADJ2, FAM_ADJ3, FAM_ADJ4, FAM_FINALIZE, FAM_POINTWISE, FAM_COUNT
+  FAM_ADJ1, FAM_ADJ2, FAM_ADJ3, FAM_ADJ4, FAM_FINALIZE, FAM_POINTWISE, FAM_RKG, FAM_COUNT
 };
 const char* family_name(int f);
 
@@ -116,6 +116,12 @@ template <typename R> hipError_t run_rk_stage2_fold(const Plan& p, const LaunchC
 template <typename R> hipError_t run_rk_stage4_fold(const Plan& p, const LaunchConfig& cfg, const void* Y,
                                                     const void* A, const void* field, void* out, int64_t step,
                                                     hipStream_t s);
+// generic memory-optimised RK stage (App. A): out = ccur Y + sum_j hc[j] hist[j] +
+// cdt f(t0 + (step + c_stage) dt, Y), hist read at the site (nh <= 5)
+template <typename R> hipError_t run_rk_generic(const Plan& p, const LaunchConfig& cfg, const void* Y, double ccur,
+                                                int nh, const void* const* hist, const double* hc, double cdt,
+                                                double c_stage, const void* field, void* out, int64_t step,
+                                                hipStream_t s);
 // observation partials (|psi|^2, Re psi^H T psi, V|psi|^2, |psi|^4) of scale*psi
 template <typename R> hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi,
                                              const void* field, double t_offset_steps, bool use_scale,

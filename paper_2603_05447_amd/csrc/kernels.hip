@@ -86,9 +86,9 @@ int config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
 LaunchConfig config_get(int i) { return kConfigs[i]; }
 
 const char* family_name(int f) {
-  static const char* names[FAM_COUNT] = {"itp_pass1", "itp_pass2", "rk_stage1", "rk_stage2", "rk_stage3",
-                                         "rk_stage4", "observe",   "adj_stage1", "adj_stage2", "adj_stage3",
-                                         "adj_stage4", "finalize", "pointwise"};
+  static const char* names[FAM_COUNT] = {"itp_pass1",  "itp_pass2",  "rk_stage1",  "rk_stage2", "rk_stage3",
+                                         "rk_stage4",  "observe",    "adj_stage1", "adj_stage2", "adj_stage3",
+                                         "adj_stage4", "finalize",   "pointwise",  "rk_generic"};
   return (f >= 0 && f < FAM_COUNT) ? names[f] : "?";
 }
 
@@ -181,7 +181,9 @@ enum PassOp {
   OP_ADJ1,
   OP_RK2F,       // as OP_RK2, and out2 = (-y0 + Y + 2 out)/3
   OP_RK4F,       // out = A + Y/3 + dt/6 f(t + dt, Y)    (A read through `a`)
+  OP_RKG,        // generic App. A stage: out = ccur Y + sum_j hc_j h_j + cdt dt f(t + c dt, Y)
 };
+constexpr int RKG_MAX_HIST = 5;
 
 template <typename R> struct PassArgs {
   using C = typename CT<R>::T;
@@ -196,6 +198,13 @@ template <typename R> struct PassArgs {
   double c_stage;   // stage time offset in units of dt
   int64_t step;     // step index; < 0: read the device step counter (graph replay)
   int use_scale;    // OBS: multiply Y by the instance's scale
+  // OP_RKG: earlier stage states read at the site, their coefficients, the
+  // coefficient of the stencil input itself and the k coefficient (in units of dt)
+  int nh;
+  const C* h[RKG_MAX_HIST];
+  double hc[RKG_MAX_HIST];
+  double ccur;
+  double cdt;
 };
 
 template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT>
@@ -203,7 +212,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   using C = typename CT<R>::T;
   constexpr int CH = BLOCK * SPT;
   constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
-  constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4) || OP == OP_RK2F || OP == OP_RK4F;
+  constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4) || OP == OP_RK2F || OP == OP_RK4F || OP == OP_RKG;
   constexpr bool OBSP = (OP == OP_RK1_OBS || OP == OP_OBS);
   constexpr int NR = OBSP ? 4 : ((OP == OP_ITP2 || ADJ) ? 1 : 0);
   // per-site streams read at the lane's own site
@@ -302,6 +311,24 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     if constexpr (NEED_L) rl[m] = at1((const C*)a.out2, sc);
     if constexpr (NEED_F) rf[m] = at1(a.field, sc);
     if constexpr (NEED_P) rp[m] = at1(a.prop, sc);
+  }
+  // OP_RKG: weighted sum of the earlier stage states at the lane's sites
+  C rhist[SPT];
+  if constexpr (OP == OP_RKG) {
+#pragma unroll
+    for (int m = 0; m < SPT; ++m) {
+      const int sc = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
+      R hr = R(0), hi = R(0);
+#pragma unroll
+      for (int j = 0; j < RKG_MAX_HIST; ++j) {
+        if (j < a.nh) {
+          const C v = at1(a.h[j], sc);
+          hr += (R)a.hc[j] * v.x;
+          hi += (R)a.hc[j] * v.y;
+        }
+      }
+      rhist[m] = cmk<R>(hr, hi);
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
   C stg[NSTG];
@@ -424,6 +451,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
           const C A = ra[m];
           const R third = R(1) / R(3), c6 = dt / R(6);
           put(a.out, s, cmk<R>(A.x + third * yc.x + c6 * fr, A.y + third * yc.y + c6 * fi));
+        } else if constexpr (OP == OP_RKG) {
+          const R cc = (R)a.ccur, cdt = (R)a.cdt * dt;
+          put(a.out, s, cmk<R>(rhist[m].x + cc * yc.x + cdt * fr, rhist[m].y + cc * yc.y + cdt * fi));
         } else {
           const C y0 = ra[m], y2 = rb[m], y3 = rc[m];
           const R third = R(1) / R(3), c6 = dt / R(6);
@@ -532,6 +562,13 @@ static PassArgs<R> pass_args() {
   a.c_stage = 0.0;
   a.step = -1;
   a.use_scale = 0;
+  a.nh = 0;
+  for (int j = 0; j < RKG_MAX_HIST; ++j) {
+    a.h[j] = nullptr;
+    a.hc[j] = 0.0;
+  }
+  a.ccur = 0.0;
+  a.cdt = 0.0;
   return a;
 }
 
@@ -623,6 +660,31 @@ hipError_t run_rk_stage4_fold(const Plan& p, const LaunchConfig& cfg, const void
   timing_before(FAM_RK4, s);
   hipError_t e = dispatch_pass<R, OP_RK4F>(p, cfg, a, s);
   timing_after(FAM_RK4, s);
+  return e;
+}
+
+template <typename R>
+hipError_t run_rk_generic(const Plan& p, const LaunchConfig& cfg, const void* Y, double ccur, int nh,
+                          const void* const* hist, const double* hc, double cdt, double c_stage, const void* field,
+                          void* out, int64_t step, hipStream_t s) {
+  using C = typename CT<R>::T;
+  if (nh < 0 || nh > RKG_MAX_HIST) return hipErrorInvalidValue;
+  PassArgs<R> a = pass_args<R>();
+  a.Y = (const C*)Y;
+  a.field = (const R*)field;
+  a.out = (C*)out;
+  a.c_stage = c_stage;
+  a.step = step;
+  a.nh = nh;
+  for (int j = 0; j < nh; ++j) {
+    a.h[j] = (const C*)hist[j];
+    a.hc[j] = hc[j];
+  }
+  a.ccur = ccur;
+  a.cdt = cdt;
+  timing_before(FAM_RKG, s);
+  hipError_t e = dispatch_pass<R, OP_RKG>(p, cfg, a, s);
+  timing_after(FAM_RKG, s);
   return e;
 }
 
@@ -1033,6 +1095,9 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
                                             const void*, void*, void*, int64_t, hipStream_t);                \
   template hipError_t run_rk_stage4_fold<R>(const Plan&, const LaunchConfig&, const void*, const void*,       \
                                             const void*, void*, int64_t, hipStream_t);                       \
+  template hipError_t run_rk_generic<R>(const Plan&, const LaunchConfig&, const void*, double, int,            \
+                                        const void* const*, const double*, double, double, const void*, void*, \
+                                        int64_t, hipStream_t);                                                \
   template hipError_t run_observe<R>(const Plan&, const LaunchConfig&, const void*, const void*, double, bool, \
                                      int64_t, hipStream_t);                                                  \
   template hipError_t run_adj_stage<R>(const Plan&, const LaunchConfig&, int, const void*, const void*,      \

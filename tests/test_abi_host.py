@@ -180,6 +180,18 @@ def test_errors_are_reported_without_side_effects(lib):
     b = C.c_size_t()
     assert lib.gpe_work_bytes(g.handle, 0, _lib.GPE_MODE_RT, 10, 0, C.byref(b)) == 0 and b.value >= 3 * 27 * 16
     assert lib.gpe_work_bytes(g.handle, 5, _lib.GPE_MODE_RT, 10, 0, C.byref(b)) == _lib.GPE_ERR_ARG
+    # stored stage states per integrator: RKHE3 2, RK4 3, RKCK 5 (App. A)
+    sizes = {}
+    for mode in (_lib.GPE_MODE_RT_RKHE3, _lib.GPE_MODE_RT, _lib.GPE_MODE_RT_RKCK):
+        assert lib.gpe_work_bytes(g.handle, 0, mode, 10, 0, C.byref(b)) == 0
+        sizes[mode] = b.value
+    assert 2 * 432 <= sizes[_lib.GPE_MODE_RT_RKHE3] < 3 * 432 <= sizes[_lib.GPE_MODE_RT] < 4 * 432
+    assert 5 * 432 <= sizes[_lib.GPE_MODE_RT_RKCK] < 6 * 432 + 4096
+    assert lib.gpe_work_bytes(g.handle, 0, 5, 10, 0, C.byref(b)) == _lib.GPE_ERR_ARG
+    # an unknown integrator is rejected before anything else runs
+    bad = _lib.Params(1.0, 1e-3, 1.0, 0, 0, 7)
+    st = lib.gpe_real_time(g.handle, 0, 16, C.byref(pot), C.byref(bad), 0.0, 1, 16, 1 << 20, None, None, None)
+    assert st in (_lib.GPE_ERR_ARG, _lib.GPE_ERR_STATE)
 
 
 def test_c5_scale_layout_from_analytic_runs(lib):

@@ -1,0 +1,153 @@
+"""GPU parity of the other explicit integrators the method uses for real time
+(Sec. II.A; memory-optimised forms of App. A, eqs. (A6)-(A7)): Heun's
+third-order method and the fifth-order Cash-Karp weights, run through the C
+ABI and compared element by element with the oracle's plain k-form of the
+same Butcher tableau (rk_step_tableau), on the same seeded inputs.
+
+Tolerances as for RK4: relative L2 <= 1e-10 (complex128), <= 1e-5
+(complex64) over short horizons."""
+import numpy as np
+import pytest
+
+from oracle import observables as ob
+from oracle import realtime as rt
+from oracle import tableau
+from workloads import configs
+
+from gpu_cases import Case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 1e-5}
+TABLEAU = {"rkhe3": tableau.heun3, "rkck": tableau.cash_karp5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_05447_amd as p
+    p.load_library()
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _oracle(c, w, dt, t0, steps, integrator):
+    A, b = TABLEAU[integrator]()
+    return rt.real_time_tableau(c.T, w.psi0, c.opot, w.g, dt, t0, steps, A, b)
+
+
+@pytest.mark.parametrize("integrator", ["rkhe3", "rkck"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("make", [lambda: configs.small_rf_ramp(n=28, steps=30),
+                                  lambda: configs.random_mask_problem(n=(12, 11, 13), density=0.45, seed=31, g=40.0)],
+                         ids=["rframp28", "random"])
+def test_integrator_matches_oracle(integrator, dtype, make):
+    w = make()
+    c = Case(w, dtype)
+    steps, dt, t0 = 30, 1e-3, 0.005
+    _print(f"{integrator} {w.name} n={w.n_active} {dtype}")
+    psi = c.psi()
+    obs = c.grid.real_time(psi, c.pot, w.g, dt, steps, t0=t0, integrator=integrator)
+    ref = _oracle(c, w, dt, t0, steps, integrator)
+    err = rel_l2(psi.cpu().numpy(), ref)
+    _print(f"  rel L2 = {err:.3e}")
+    assert err <= TOL[dtype]
+    N, E, mu = ob.energy_mu(c.T, ref, c.opot(t0 + steps * dt), w.g, w.box.dV)
+    assert abs(obs["norm"] - N) <= TOL[dtype] * N * 10
+    assert abs(obs["energy"] - E) <= TOL[dtype] * abs(E) * 10
+
+
+@pytest.mark.parametrize("integrator", ["rkhe3", "rkck"])
+def test_integrator_history_matches_oracle(integrator):
+    import torch
+    w = configs.small_rf_ramp(n=24, steps=20)
+    c = Case(w, "c128")
+    psi = c.psi()
+    hist = torch.zeros((4, 3), dtype=torch.float64, device=c.dev)
+    c.grid.real_time(psi, c.pot, w.g, 1e-3, 20, t0=0.0, obs_every=5, history=hist, integrator=integrator)
+    A, b = TABLEAU[integrator]()
+    y = np.array(w.psi0, dtype=np.complex128)
+    h = hist.cpu().numpy()
+    for n in range(20):
+        if n % 5 == 0:
+            N, E, mu = ob.energy_mu(c.T, y, c.opot(n * 1e-3), w.g, w.box.dV)
+            k = n // 5
+            assert abs(h[k, 0] - N) <= 1e-12 * N
+            assert abs(h[k, 1] - E) <= 1e-10 * abs(E)
+            assert abs(h[k, 2] - mu) <= 1e-10 * abs(mu)
+        y = rt.rk_step_tableau(c.T, y, n * 1e-3, 1e-3, c.opot, w.g, A, b)
+    assert rel_l2(psi.cpu().numpy(), y) <= 1e-10
+
+
+def test_rkck_every_launch_config_gives_the_same_result():
+    """Six-stage steps with five stored states under every compiled launch
+    variant (workgroup size, sites per lane, chunk order, load flavour)."""
+    from paper_2603_05447_amd import config_count
+    w = configs.small_rf_ramp(n=24, steps=8)
+    ref = None
+    for k in range(config_count()):
+        c = Case(w, "c128", config=k)
+        p = c.psi()
+        c.grid.real_time(p, c.pot, w.g, 1e-3, 8, integrator="rkck", observe=False)
+        out = p.cpu().numpy()
+        if ref is None:
+            ref = _oracle(c, w, 1e-3, 0.0, 8, "rkck")
+        assert rel_l2(out, ref) <= 1e-10, k
+
+
+@pytest.mark.parametrize("integrator", ["rkhe3", "rkck"])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_integrator_matches_single(integrator, use_graph):
+    import torch
+    from paper_2603_05447_amd import Grid, Batch
+    ws = [configs.small_rf_ramp(n=n, steps=10) for n in (14, 18, 20)]
+    for i, w in enumerate(ws):
+        w.g = 10.0 + 7.0 * i
+    grids = [Grid.from_box(w.box, runs=w.runs, device=0) for w in ws]
+    b = Batch(grids, device=0)
+    psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=torch.complex128, device="cuda:0")
+    field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=torch.float64, device="cuda:0")
+    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    dts = [1e-3, 7e-4, 1.3e-3]
+    b.real_time(psi, field, ramps, [w.g for w in ws], dts, 6, use_graph=use_graph, integrator=integrator,
+                observe=False)
+    out = psi.cpu().numpy()
+    for i, w in enumerate(ws):
+        c = Case(w, "c128")
+        ref = _oracle(c, w, dts[i], 0.0, 6, integrator)
+        assert rel_l2(out[b.offsets[i]:b.offsets[i + 1]], ref) <= 1e-10, i
+
+
+def test_integrator_arguments_are_checked():
+    import ctypes as C
+    from paper_2603_05447_amd import GPEError, _lib
+    w = configs.small_rf_ramp(n=16, steps=4)
+    c = Case(w, "c128")
+    psi = c.psi()
+    with pytest.raises(ValueError):
+        c.grid.real_time(psi, c.pot, w.g, 1e-3, 1, integrator="euler")
+    # stability bounds: sqrt(3) for RKHE3 and 1 for RKCK (times 1/lambda,
+    # lambda = Gershgorin bound of T + max |V| over the ramp's knots); a dt
+    # at 1.9/lambda is accepted by RK4 only
+    lam_t = 2 * sum(1 / h ** 2 for h in w.box.h)
+    fmin, fmax = float(np.min(w.field)), float(np.max(w.field))
+    vmax = max(np.hypot(max(abs(fmax - d), abs(fmin - d)), w.omega) for d in w.knot_delta)
+    dt = 1.9 / (lam_t + vmax)
+    for integ in ("rkhe3", "rkck"):
+        with pytest.raises(GPEError) as e:
+            c.grid.real_time(psi, c.pot, w.g, dt, 1, check_stability=True, integrator=integ)
+        assert e.value.status == _lib.GPE_ERR_UNSTABLE
+    assert np.array_equal(psi.cpu().numpy(), w.psi0)     # nothing ran
+    c.grid.real_time(c.psi(), c.pot, w.g, dt, 1, check_stability=True, integrator="rk4", observe=False)
+    # the fidelity gradient is the adjoint of RK4 only
+    prm = _lib.Params(w.g, 1e-3, 1.0, 0, 0, _lib.GPE_RKCK)
+    cp, keep = c.pot.as_c(_lib.GPE_C128)
+    loss = C.c_double()
+    grad = (C.c_double * _lib.GPE_MAX_KNOTS)()
+    st = _lib.load().gpe_fidelity_grad(c.grid._h, _lib.GPE_C128, psi.data_ptr(), psi.data_ptr(), C.byref(cp),
+                                       C.byref(prm), 0.0, 4, 0, None, 0, None, C.byref(loss), grad, None)
+    assert st == _lib.GPE_ERR_ARG
