@@ -233,6 +233,35 @@ def bench_integrators(args, dev, report):
     torch.cuda.empty_cache()
 
 
+def bench_itp_real(args, dev, report):
+    """Imaginary time at the headline size on a real state (Sec. II.A: a
+    real start stays real) against the complex form of the same step."""
+    import torch
+    w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, "c128")
+    n = w.n_active
+    steps = max(args.int_steps, 1)
+    real = psi.real.abs().contiguous()
+    out = {"workload": "rf-bubble 1024x1024x512, 16,028,656 active sites, float64 state vs complex128",
+           "steps": steps}
+    for name, x, b in (("complex128", psi, 2 * algo_bytes("itp_pass1", 8)), ("float64", real, 2 * 3 * 8)):
+        g.imag_time(x, pot_itp, w.g, w.dt, 2, observe=False)      # warm-up
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        g.imag_time(x, pot_itp, w.g, w.dt, steps, observe=False)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": ms, "site_updates_per_s": n / (ms * 1e-3), "algo_bytes_per_site_step": b,
+                     "eff_GBps": b * n / (ms * 1e-3) / 1e9}
+        log(f"[bench] ITP {name}: {ms:.3f} ms/step, {b} B/site/step, {out[name]['eff_GBps']:.0f} GB/s")
+    out["speedup_real_over_complex"] = out["complex128"]["ms_per_step"] / out["float64"]["ms_per_step"]
+    report["itp_real_c2"] = out
+    del psi, real, U, g
+    torch.cuda.empty_cache()
+
+
 def cpu_baseline(args):
     """The FP64 oracle, single-threaded, on a slab of the headline workload:
     the active sites of x-planes [448, 576) of the 1024 x 1024 x 512 grid
@@ -439,6 +468,8 @@ def main():
         log("[bench] batched done")
         bench_integrators(args, dev, report)
         log("[bench] integrators done")
+        bench_itp_real(args, dev, report)
+        log("[bench] real imaginary time done")
     if args.c5 > 0:
         bench_c5(args, dev, report)
         log("[bench] C5 precision study done")
@@ -482,7 +513,7 @@ def main():
     if "c64" in report:
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
-    for key in ("adjoint_c3", "batched_c4", "integrators_c2", "precision_c5"):
+    for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "precision_c5"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)

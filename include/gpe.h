@@ -63,7 +63,8 @@ typedef enum {
   GPE_MODE_RT = 1,        /* gpe_real_time with GPE_RK4 */
   GPE_MODE_ADJ = 2,       /* gpe_fidelity_grad */
   GPE_MODE_RT_RKHE3 = 3,  /* gpe_real_time with GPE_RKHE3 */
-  GPE_MODE_RT_RKCK = 4    /* gpe_real_time with GPE_RKCK */
+  GPE_MODE_RT_RKCK = 4,   /* gpe_real_time with GPE_RKCK */
+  GPE_MODE_ITP_REAL = 5   /* gpe_imag_time_real */
 } gpe_mode;
 
 /* Explicit integrators for real time (Sec. II.A; App. A gives each one's
@@ -150,7 +151,8 @@ gpe_status gpe_grid_runs(gpe_grid grid, int64_t* out_host);
 gpe_status gpe_grid_destroy(gpe_grid grid);
 
 /* Size in bytes of the device work buffer a call needs.
- *   mode GPE_MODE_ITP: gpe_imag_time; GPE_MODE_RT / _RT_RKHE3 / _RT_RKCK:
+ *   mode GPE_MODE_ITP: gpe_imag_time; GPE_MODE_ITP_REAL: gpe_imag_time_real;
+ *   GPE_MODE_RT / _RT_RKHE3 / _RT_RKCK:
  *   gpe_real_time with that integrator (3, 2 and 5 state vectors);
  *   GPE_MODE_ADJ: gpe_fidelity_grad with nsteps and ckpt_every as given. */
 gpe_status gpe_work_bytes(gpe_grid grid, gpe_dtype dtype, int32_t mode, int64_t nsteps, int64_t ckpt_every,
@@ -177,6 +179,18 @@ gpe_status gpe_unpack(gpe_grid grid, gpe_dtype dtype, const void* compact_dev, v
 gpe_status gpe_imag_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
                          const gpe_params* params, int64_t nsteps, void* work, size_t work_bytes,
                          void* stream, gpe_obs* final_host, gpe_obs* history_dev);
+
+/* Imaginary time on a real state (Sec. II.A: with a real start, a real
+ * potential and real g every step of eqs. (6)-(7) keeps psi real).  Same
+ * step, renormalisation, observations and errors as gpe_imag_time, but psi
+ * holds n_active reals (double for GPE_C128, float for GPE_C64), halving
+ * the state traffic; g is used as given (real).
+ *   work: >= gpe_work_bytes(.., GPE_MODE_ITP_REAL, ..) bytes.
+ * The result can seed gpe_real_time after conversion to interleaved complex
+ * (imaginary parts zero). */
+gpe_status gpe_imag_time_real(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                              const gpe_params* params, int64_t nsteps, void* work, size_t work_bytes,
+                              void* stream, gpe_obs* final_host, gpe_obs* history_dev);
 
 /* Real-time evolution (Sec. II.A eq. (8)) with params->integrator, in the
  * memory-optimised form of App. A, eqs. (A6)-(A7): each stage reads one

@@ -11,7 +11,7 @@ GPE_OK, GPE_ERR_ARG, GPE_ERR_ALLOC, GPE_ERR_DEVICE, GPE_ERR_STATE, GPE_ERR_UNSTA
 STATUS_NAMES = ["GPE_OK", "GPE_ERR_ARG", "GPE_ERR_ALLOC", "GPE_ERR_DEVICE", "GPE_ERR_STATE",
                 "GPE_ERR_UNSTABLE", "GPE_ERR_NONFINITE"]
 GPE_C128, GPE_C64 = 0, 1
-GPE_MODE_ITP, GPE_MODE_RT, GPE_MODE_ADJ, GPE_MODE_RT_RKHE3, GPE_MODE_RT_RKCK = 0, 1, 2, 3, 4
+GPE_MODE_ITP, GPE_MODE_RT, GPE_MODE_ADJ, GPE_MODE_RT_RKHE3, GPE_MODE_RT_RKCK, GPE_MODE_ITP_REAL = range(6)
 GPE_RK4, GPE_RKHE3, GPE_RKCK = 0, 1, 2
 GPE_POT_STATIC, GPE_POT_RF_RAMP = 0, 1
 GPE_MAX_KNOTS = 32
@@ -60,6 +60,8 @@ SIGNATURES = {
     "gpe_unpack": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "gpe_imag_time": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), _i64, _vp,
                                 C.c_size_t, _vp, C.POINTER(Obs), _vp]),
+    "gpe_imag_time_real": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), _i64, _vp,
+                                     C.c_size_t, _vp, C.POINTER(Obs), _vp]),
     "gpe_real_time": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), C.c_double, _i64,
                                 _vp, C.c_size_t, _vp, C.POINTER(Obs), _vp]),
     "gpe_observe": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.c_double, C.c_double, _vp,

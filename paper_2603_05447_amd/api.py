@@ -17,6 +17,8 @@ from ._lib import check
 
 _CDT = {torch.complex128: L.GPE_C128, torch.complex64: L.GPE_C64}
 _RDT = {L.GPE_C128: torch.float64, L.GPE_C64: torch.float32}
+# real states (imaginary time from a real start): float64 pairs with GPE_C128
+_RSTATE = {torch.float64: L.GPE_C128, torch.float32: L.GPE_C64}
 
 
 def _stream(stream) -> C.c_void_p:
@@ -184,14 +186,22 @@ class Grid:
     def imag_time(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, steps: int,
                   norm_target: float = 1.0, obs_every: int = 0, history: Optional[torch.Tensor] = None,
                   stream=None, observe: bool = True, check_stability: bool = False) -> Optional[dict]:
-        dt_ = _dtype_of(psi)
+        """Imaginary time in place.  A complex psi (complex128/complex64) runs
+        gpe_imag_time; a real psi (float64/float32) runs gpe_imag_time_real."""
+        real = psi.dtype in _RSTATE
+        if real:
+            if not psi.is_cuda or not psi.is_contiguous():
+                raise ValueError("psi must be a contiguous CUDA/HIP tensor")
+            dt_ = _RSTATE[psi.dtype]
+        else:
+            dt_ = _dtype_of(psi)
         cp, keep = pot.as_c(dt_)
         prm = make_params(g, dt, norm_target, obs_every, check_stability)
-        w = self.work(dt_, L.GPE_MODE_ITP, steps)
+        w = self.work(dt_, L.GPE_MODE_ITP_REAL if real else L.GPE_MODE_ITP, steps)
         o = L.Obs()
-        check(L.load().gpe_imag_time(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), int(steps),
-                                     w.data_ptr(), w.numel(), _stream(stream), C.byref(o) if observe else None,
-                                     _ptr(history)))
+        fn = L.load().gpe_imag_time_real if real else L.load().gpe_imag_time
+        check(fn(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), int(steps), w.data_ptr(), w.numel(),
+                 _stream(stream), C.byref(o) if observe else None, _ptr(history)))
         return _obs_dict(o) if observe else None
 
     def real_time(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, steps: int, t0: float = 0.0,

@@ -441,8 +441,8 @@ int integrator_buffers(int integrator) {
 size_t work_bytes_for(int64_t n, int dtype, int mode, int64_t nsteps, int64_t ckpt_every) {
   Carver c(nullptr);
   const size_t st = (size_t)n * csize(dtype);
-  if (mode == GPE_MODE_ITP) {
-    c.take(st);
+  if (mode == GPE_MODE_ITP || mode == GPE_MODE_ITP_REAL) {
+    c.take(mode == GPE_MODE_ITP ? st : (size_t)n * rsize(dtype));
     c.take((size_t)n * rsize(dtype));
   } else if (mode == GPE_MODE_RT || mode == GPE_MODE_RT_RKHE3 || mode == GPE_MODE_RT_RKCK) {
     const int integ = mode == GPE_MODE_RT ? GPE_RK4 : (mode == GPE_MODE_RT_RKHE3 ? GPE_RKHE3 : GPE_RKCK);
@@ -651,9 +651,9 @@ gpe_status rk_generic_step(const Ctx& c, const MemOptTableau& tb, void* y0, cons
 
 template <typename R>
 gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps, void* work, int64_t obs_every,
-                     gpe_obs* hist) {
+                     gpe_obs* hist, bool real = false) {
   Carver cv(work);
-  void* tmp = cv.take((size_t)c.P->total * 2 * sizeof(R));
+  void* tmp = cv.take((size_t)c.P->total * (real ? 1 : 2) * sizeof(R));
   void* prop = cv.take((size_t)c.P->total * sizeof(R));
   LTRY(run_set_step(c.pl.step, 0, c.s));
   LTRY(run_make_prop<R>(c.pl, c.cfg, field, prop, c.s));
@@ -661,15 +661,15 @@ gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps,
   int64_t k = 0;
   for (int64_t n = 0; n < nsteps; ++n) {
     if (hist && obs_every > 0 && n % obs_every == 0) {
-      LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, true, 0, c.s));
+      LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, true, 0, c.s, real));
       LTRY(run_finalize(c.pl, FIN_OBS, hist + k * c.P->n_inst, c.s));
       ++k;
     }
-    LTRY(run_itp_pass1<R>(c.pl, c.cfg, psi, prop, tmp, c.s));
-    LTRY(run_itp_pass2<R>(c.pl, c.cfg, tmp, prop, psi, c.s));
+    LTRY(run_itp_pass1<R>(c.pl, c.cfg, psi, prop, tmp, real, c.s));
+    LTRY(run_itp_pass2<R>(c.pl, c.cfg, tmp, prop, psi, real, c.s));
     LTRY(run_finalize(c.pl, FIN_NORM_SCALE, nullptr, c.s));
   }
-  if (nsteps > 0) LTRY(run_apply_scale<R>(c.pl, c.cfg, psi, c.s));
+  if (nsteps > 0) LTRY(run_apply_scale<R>(c.pl, c.cfg, psi, real, c.s));
   return GPE_OK;
 }
 
@@ -708,8 +708,9 @@ gpe_status drive_rt(const Ctx& c, void* psi, const void* field, int64_t nsteps, 
 }
 
 template <typename R>
-gpe_status drive_observe(const Ctx& c, const void* psi, const void* field, bool use_scale, int64_t step) {
-  LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, use_scale, step, c.s));
+gpe_status drive_observe(const Ctx& c, const void* psi, const void* field, bool use_scale, int64_t step,
+                         bool real = false) {
+  LTRY(run_observe<R>(c.pl, c.cfg, psi, field, 0.0, use_scale, step, c.s, real));
   LTRY(run_finalize(c.pl, FIN_OBS, nullptr, c.s));
   return GPE_OK;
 }
@@ -1075,7 +1076,7 @@ gpe_status gpe_work_bytes(gpe_grid g, gpe_dtype dtype, int32_t mode, int64_t nst
   if (!g || !bytes) return fail(GPE_ERR_ARG, "grid or bytes is NULL");
   gpe_status st = check_dtype(dtype);
   if (st != GPE_OK) return st;
-  if (mode < GPE_MODE_ITP || mode > GPE_MODE_RT_RKCK) return fail(GPE_ERR_ARG, "unknown mode");
+  if (mode < GPE_MODE_ITP || mode > GPE_MODE_ITP_REAL) return fail(GPE_ERR_ARG, "unknown mode");
   if (nsteps < 0 || ckpt_every < 0) return fail(GPE_ERR_ARG, "nsteps and ckpt_every must be >= 0");
   *bytes = work_bytes_for(g->lay.n_active, dtype, mode, nsteps, ckpt_every);
   return GPE_OK;
@@ -1126,18 +1127,20 @@ static gpe_status check_work(const void* work, size_t have, size_t need) {
   return GPE_OK;
 }
 
-gpe_status gpe_imag_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
-                         int64_t nsteps, void* work, size_t work_bytes, void* stream, gpe_obs* final_host,
-                         gpe_obs* history_dev) {
+static gpe_status imag_time_impl(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                                 const gpe_params* prm, int64_t nsteps, void* work, size_t work_bytes, void* stream,
+                                 gpe_obs* final_host, gpe_obs* history_dev, bool real) {
   gpe_status st = check_grid(g);
   if (st == GPE_OK) st = check_dtype(dtype);
   if (st == GPE_OK) st = check_ptr(psi, "psi");
   if (st == GPE_OK) st = check_pot(pot);
   if (st == GPE_OK) st = check_params(prm);
   if (st != GPE_OK) return st;
+  if (prm->integrator != GPE_RK4) return fail(GPE_ERR_ARG, "params.integrator must be 0 for imaginary time");
   if (nsteps < 0) return fail(GPE_ERR_ARG, "nsteps must be >= 0");
   if (prm->obs_every > 0 && !history_dev) return fail(GPE_ERR_ARG, "obs_every > 0 needs history_dev");
-  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, GPE_MODE_ITP, nsteps, 0));
+  st = check_work(work, work_bytes,
+                  work_bytes_for(g->lay.n_active, dtype, real ? GPE_MODE_ITP_REAL : GPE_MODE_ITP, nsteps, 0));
   if (st != GPE_OK) return st;
   if (prm->check_stability) {
     const double lt = kinetic_bound(*g->prob);
@@ -1152,16 +1155,28 @@ gpe_status gpe_imag_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_poten
   std::vector<InstParams> ps{make_params(pot, prm, 0.0)};
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
-  st = dtype == GPE_C128 ? drive_itp<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev)
-                         : drive_itp<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev);
+  st = dtype == GPE_C128 ? drive_itp<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, real)
+                         : drive_itp<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, real);
   if (st != GPE_OK) return st;
   if (final_host) {
-    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false, 0)
-                           : drive_observe<float>(c, psi, pot->field, false, 0);
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false, 0, real)
+                           : drive_observe<float>(c, psi, pot->field, false, 0, real);
     if (st != GPE_OK) return st;
     return read_obs(*g->prob, final_host, s);
   }
   return GPE_OK;
+}
+
+gpe_status gpe_imag_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
+                         int64_t nsteps, void* work, size_t work_bytes, void* stream, gpe_obs* final_host,
+                         gpe_obs* history_dev) {
+  return imag_time_impl(g, dtype, psi, pot, prm, nsteps, work, work_bytes, stream, final_host, history_dev, false);
+}
+
+gpe_status gpe_imag_time_real(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                              const gpe_params* prm, int64_t nsteps, void* work, size_t work_bytes, void* stream,
+                              gpe_obs* final_host, gpe_obs* history_dev) {
+  return imag_time_impl(g, dtype, psi, pot, prm, nsteps, work, work_bytes, stream, final_host, history_dev, true);
 }
 
 gpe_status gpe_real_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
@@ -1349,7 +1364,7 @@ gpe_status gpe_batch_work_bytes(gpe_batch b, gpe_dtype dtype, int32_t mode, int6
   if (!b || !bytes) return fail(GPE_ERR_ARG, "batch or bytes is NULL");
   gpe_status st = check_dtype(dtype);
   if (st != GPE_OK) return st;
-  if (mode < GPE_MODE_ITP || mode > GPE_MODE_RT_RKCK) return fail(GPE_ERR_ARG, "unknown mode");
+  if (mode < GPE_MODE_ITP || mode > GPE_MODE_ITP_REAL) return fail(GPE_ERR_ARG, "unknown mode");
   if (nsteps < 0 || ckpt_every < 0) return fail(GPE_ERR_ARG, "nsteps and ckpt_every must be >= 0");
   *bytes = work_bytes_for(b->prob->total, dtype, mode, nsteps, ckpt_every);
   return GPE_OK;

@@ -96,11 +96,12 @@ const char* family_name(int f);
 
 // ---- launchers (kernels.hip) -------------------------------------------
 // All return hipSuccess or the launch error.  `cfg` selects the variant.
-// R = double (complex128) or float (complex64).
+// R = double (complex128) or float (complex64).  `real`: the state is one R
+// per site (real imaginary time) instead of a complex pair.
 template <typename R> hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw,
-                                               const void* prop, void* tmp, hipStream_t s);
+                                               const void* prop, void* tmp, bool real, hipStream_t s);
 template <typename R> hipError_t run_itp_pass2(const Plan& p, const LaunchConfig& cfg, const void* tmp,
-                                               const void* prop, void* psi_raw, hipStream_t s);
+                                               const void* prop, void* psi_raw, bool real, hipStream_t s);
 // stage 1..4 of the memory-optimised RK4 step; Y = stencil input, y0 = step start,
 // y2/y3 read by stage 4, out = output (stage 4: may equal y0).  obs: stage 1 also
 // writes observation partials of y0.  `step` is the step index n (stage time
@@ -125,7 +126,7 @@ template <typename R> hipError_t run_rk_generic(const Plan& p, const LaunchConfi
 // observation partials (|psi|^2, Re psi^H T psi, V|psi|^2, |psi|^4) of scale*psi
 template <typename R> hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi,
                                              const void* field, double t_offset_steps, bool use_scale,
-                                             int64_t step, hipStream_t s);
+                                             int64_t step, hipStream_t s, bool real = false);
 // adjoint stage (4..1): X = stencil input (lambda for stage 4, else u_i), Y = forward
 // stage state, lam = lambda (site), lacc = running lambda, uout = next u / new lambda
 template <typename R> hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, const void* X,
@@ -135,7 +136,7 @@ template <typename R> hipError_t run_adj_stage(const Plan& p, const LaunchConfig
 // pointwise helpers (chunk-parallel, one launch each)
 template <typename R> hipError_t run_make_prop(const Plan& p, const LaunchConfig& cfg, const void* field,
                                                void* prop, hipStream_t s);
-template <typename R> hipError_t run_apply_scale(const Plan& p, const LaunchConfig& cfg, void* psi,
+template <typename R> hipError_t run_apply_scale(const Plan& p, const LaunchConfig& cfg, void* psi, bool real,
                                                  hipStream_t s);
 template <typename R> hipError_t run_overlap(const Plan& p, const LaunchConfig& cfg, const void* a,
                                              const void* b, hipStream_t s);

@@ -63,6 +63,8 @@ template <bool NT, typename T> __device__ __forceinline__ T ld(const T* p) {
 template <bool NT, typename T> __device__ __forceinline__ void st(T* p, const T& v) {
   if constexpr (!NT) {
     *p = v;
+  } else if constexpr (std::is_floating_point<T>::value) {
+    __builtin_nontemporal_store(v, p);
   } else {
     typename NVec<T>::T w;
     w.x = v.x;
@@ -207,9 +209,14 @@ template <typename R> struct PassArgs {
   double cdt;
 };
 
-template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT>
+// REAL: the state is real (imaginary time from a real start, Sec. II.A), one
+// R per site instead of two; only the imaginary-time passes and the
+// observation pass exist in that form.
+template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT, bool REAL>
 __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
   using C = typename CT<R>::T;
+  using S = typename std::conditional<REAL, R, C>::type;   // stencil state type
+  static_assert(!REAL || OP == OP_ITP1 || OP == OP_ITP2 || OP == OP_OBS, "real state: ITP and OBS only");
   constexpr int CH = BLOCK * SPT;
   constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
   constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4) || OP == OP_RK2F || OP == OP_RK4F || OP == OP_RKG;
@@ -222,8 +229,10 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   constexpr bool NEED_L = (OP == OP_ADJ3 || OP == OP_ADJ2 || OP == OP_ADJ1);
   constexpr bool NEED_F = (RK || OP == OP_OBS || ADJ);
   constexpr bool NEED_P = (OP == OP_ITP2);
-  __shared__ C sy[CH + 2];
+  __shared__ S sy[CH + 2];
   __shared__ double red[BLOCK / 64][NR > 0 ? NR : 1];
+  const S* const Yin = reinterpret_cast<const S*>(a.Y);
+  S* const Yout = reinterpret_cast<S*>(a.out);
   // dynamic LDS: lateral offsets (max_seg) then segment heads (max_seg + 1)
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   SegNb* snb = reinterpret_cast<SegNb*>(dyn_lds);
@@ -244,7 +253,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   R scale = R(1);
   if (OP == OP_ITP1 || (OP == OP_OBS && a.use_scale)) scale = (R)pl.out[ch.inst].scale;
   const R hg = g * dt * R(0.5);
-  const C zero = cmk<R>(R(0), R(0));
+  S zero;
+  if constexpr (REAL) zero = R(0); else zero = cmk<R>(R(0), R(0));
 
   // address of element i of a per-site array; with OFF32 the byte offset is
   // formed in 32 bits (every array is below 4 GiB), giving base-register +
@@ -261,11 +271,18 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   };
   auto at = [&](auto* base, int i) { return ld<false>(ptr(base, i)); };       // reused stream
   auto at1 = [&](auto* base, int i) { return ld<NT>(ptr(base, i)); };         // touched once
-  auto put = [&](auto* base, int i, const C& v) { st<NT>(ptr(base, i), v); };
+  auto put = [&](auto* base, int i, const auto& v) { st<NT>(ptr(base, i), v); };
   // value of the stencil input at compact site s (ITP1 applies the diagonal half-step on load)
-  auto load = [&](int s) -> C {
-    C v = at(a.Y, s);
-    if (OP == OP_ITP1) {
+  auto load = [&](int s) -> S {
+    S v = at(Yin, s);
+    if constexpr (REAL) {
+      if (OP == OP_ITP1) {
+        const R vr = v * scale;
+        v = vr * (at(a.prop, s) * (R(1) - hg * vr * vr));
+      } else if (OP == OP_OBS) {
+        v = v * scale;
+      }
+    } else if (OP == OP_ITP1) {
       const R p = at(a.prop, s);
       const R vr = v.x * scale, vi = v.y * scale;
       const R f = p * (R(1) - hg * (vr * vr + vi * vi));
@@ -331,7 +348,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     }
   }
   __builtin_amdgcn_sched_barrier(0);
-  C stg[NSTG];
+  S stg[NSTG];
 #pragma unroll
   for (int q = 0; q < NSTG; ++q) {
     const int t = threadIdx.x + q * BLOCK;
@@ -352,7 +369,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const int nseg = ch.seg_count;
   const int top = nseg > 1 ? (1 << (31 - __clz(nseg - 1))) : 0;
   int js[SPT];
-  C xm[SPT], xp[SPT], ym[SPT], yp[SPT];
+  S xm[SPT], xp[SPT], ym[SPT], yp[SPT];
   R wxm[SPT], wxp[SPT], wym[SPT], wyp[SPT];
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
@@ -397,10 +414,29 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       const int s = ch.site_begin + l;
       const SegHead hd = sh[js[m]];
       const int send = sh[js[m] + 1].start;
-      const C yc = sy[l + 1];
-      const C zm = sy[l], zp = sy[l + 2];
+      const S yc = sy[l + 1];
+      const S zm = sy[l], zp = sy[l + 2];
       const R wzm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? R(0) : cz;
       const R wzp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? R(0) : cz;
+      if constexpr (REAL) {
+        // T~ y at s, real state
+        const R lt = wxm[m] * xm[m] + wxp[m] * xp[m] + wym[m] * ym[m] + wyp[m] * yp[m] + wzm * zm + wzp * zp + cd * yc;
+        if constexpr (OP == OP_ITP1) {
+          put(Yout, s, yc - R(0.5) * dt * lt);
+        } else if constexpr (OP == OP_ITP2) {
+          const R q = yc - R(0.5) * dt * lt;
+          const R w = q * (rp[m] * (R(1) - hg * q * q));
+          put(Yout, s, w);
+          acc[0] += (double)w * (double)w;
+        } else {
+          const R V = potential<R>(kind, rf[m], delta, omega2);
+          const double d = (double)yc * (double)yc;
+          acc[0] += d;
+          acc[1] += (double)yc * (double)lt;
+          acc[2] += (double)V * d;
+          acc[3] += d * d;
+        }
+      } else {
       // T~ y at s
       const R lr = wxm[m] * xm[m].x + wxp[m] * xp[m].x + wym[m] * ym[m].x + wyp[m] * yp[m].x + wzm * zm.x +
                    wzp * zp.x + cd * yc.x;
@@ -495,6 +531,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
           put(a.out, s, cmk<R>(lacc.x + thr, lacc.y + thi));
         }
       }
+      }  // complex state
     }
   }
 
@@ -527,29 +564,29 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   }
 }
 
-template <int BLOCK, int SPT, typename R, int OP>
+template <int BLOCK, int SPT, typename R, int OP, bool REAL>
 static hipError_t launch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   const size_t dyn = (size_t)p.max_seg * sizeof(SegNb) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
   if (p.off32 && cfg.nt)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
   else if (p.off32)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false, REAL>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
   else
-    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
   return hipGetLastError();
 }
 
-template <typename R, int OP>
+template <typename R, int OP, bool REAL = false>
 static hipError_t dispatch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   if (p.n_chunks <= 0) return hipSuccess;
   // arrays of 4 GiB or more use 64-bit addressing with the 256 x 2 shape (the
   // chunk table of a grid that large is built for that shape)
-  if (cfg.block == 256 && cfg.spt == 1) return launch_pass<256, 1, R, OP>(p, cfg, a, s);
-  if (cfg.block == 256 && cfg.spt == 2) return launch_pass<256, 2, R, OP>(p, cfg, a, s);
-  if (cfg.block == 256 && cfg.spt == 4) return launch_pass<256, 4, R, OP>(p, cfg, a, s);
-  if (cfg.block == 512 && cfg.spt == 1) return launch_pass<512, 1, R, OP>(p, cfg, a, s);
-  if (cfg.block == 512 && cfg.spt == 2) return launch_pass<512, 2, R, OP>(p, cfg, a, s);
-  if (cfg.block == 1024 && cfg.spt == 1) return launch_pass<1024, 1, R, OP>(p, cfg, a, s);
+  if (cfg.block == 256 && cfg.spt == 1) return launch_pass<256, 1, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 256 && cfg.spt == 2) return launch_pass<256, 2, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 256 && cfg.spt == 4) return launch_pass<256, 4, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 512 && cfg.spt == 1) return launch_pass<512, 1, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 512 && cfg.spt == 2) return launch_pass<512, 2, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 1024 && cfg.spt == 1) return launch_pass<1024, 1, R, OP, REAL>(p, cfg, a, s);
   return hipErrorInvalidValue;
 }
 
@@ -574,28 +611,28 @@ static PassArgs<R> pass_args() {
 
 template <typename R>
 hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw, const void* prop, void* tmp,
-                         hipStream_t s) {
+                         bool real, hipStream_t s) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
   a.Y = (const C*)psi_raw;
   a.prop = (const R*)prop;
   a.out = (C*)tmp;
   timing_before(FAM_ITP1, s);
-  hipError_t e = dispatch_pass<R, OP_ITP1>(p, cfg, a, s);
+  hipError_t e = real ? dispatch_pass<R, OP_ITP1, true>(p, cfg, a, s) : dispatch_pass<R, OP_ITP1>(p, cfg, a, s);
   timing_after(FAM_ITP1, s);
   return e;
 }
 
 template <typename R>
 hipError_t run_itp_pass2(const Plan& p, const LaunchConfig& cfg, const void* tmp, const void* prop, void* psi_raw,
-                         hipStream_t s) {
+                         bool real, hipStream_t s) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
   a.Y = (const C*)tmp;
   a.prop = (const R*)prop;
   a.out = (C*)psi_raw;
   timing_before(FAM_ITP2, s);
-  hipError_t e = dispatch_pass<R, OP_ITP2>(p, cfg, a, s);
+  hipError_t e = real ? dispatch_pass<R, OP_ITP2, true>(p, cfg, a, s) : dispatch_pass<R, OP_ITP2>(p, cfg, a, s);
   timing_after(FAM_ITP2, s);
   return e;
 }
@@ -690,7 +727,7 @@ hipError_t run_rk_generic(const Plan& p, const LaunchConfig& cfg, const void* Y,
 
 template <typename R>
 hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi, const void* field,
-                       double t_offset_steps, bool use_scale, int64_t step, hipStream_t s) {
+                       double t_offset_steps, bool use_scale, int64_t step, hipStream_t s, bool real) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
   a.Y = (const C*)psi;
@@ -699,7 +736,7 @@ hipError_t run_observe(const Plan& p, const LaunchConfig& cfg, const void* psi, 
   a.step = step;
   a.use_scale = use_scale ? 1 : 0;
   timing_before(FAM_OBSERVE, s);
-  hipError_t e = dispatch_pass<R, OP_OBS>(p, cfg, a, s);
+  hipError_t e = real ? dispatch_pass<R, OP_OBS, true>(p, cfg, a, s) : dispatch_pass<R, OP_OBS>(p, cfg, a, s);
   timing_after(FAM_OBSERVE, s);
   return e;
 }
@@ -735,7 +772,7 @@ hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, cons
 // ---------------------------------------------------------------------------
 // pointwise passes (one workgroup of 256 lanes per chunk)
 // ---------------------------------------------------------------------------
-enum PointOp { PT_PROP = 0, PT_SCALE, PT_OVERLAP, PT_SEED, PT_RANGE };
+enum PointOp { PT_PROP = 0, PT_SCALE, PT_OVERLAP, PT_SEED, PT_RANGE, PT_SCALE_REAL };
 
 template <typename R> struct PointArgs {
   using C = typename CT<R>::T;
@@ -768,7 +805,7 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   }
   R sc = R(1);
   double cre = 0.0, cim = 0.0;
-  if (OP == PT_SCALE) sc = (R)pl.out[ch.inst].scale;
+  if (OP == PT_SCALE || OP == PT_SCALE_REAL) sc = (R)pl.out[ch.inst].scale;
   if (OP == PT_SEED) {
     cre = pl.out[ch.inst].ov_re;
     cim = pl.out[ch.inst].ov_im;
@@ -781,6 +818,8 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
     } else if constexpr (OP == PT_SCALE) {
       const C v = a.out[s];
       a.out[s] = cmk<R>(v.x * sc, v.y * sc);
+    } else if constexpr (OP == PT_SCALE_REAL) {
+      a.rout[s] = a.rout[s] * sc;
     } else if constexpr (OP == PT_OVERLAP) {
       const C x = a.a[s], y = a.b[s];
       acc[0] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
@@ -851,8 +890,12 @@ hipError_t run_make_prop(const Plan& p, const LaunchConfig&, const void* field, 
 }
 
 template <typename R>
-hipError_t run_apply_scale(const Plan& p, const LaunchConfig&, void* psi, hipStream_t s) {
+hipError_t run_apply_scale(const Plan& p, const LaunchConfig&, void* psi, bool real, hipStream_t s) {
   PointArgs<R> a = point_args<R>();
+  if (real) {
+    a.rout = (R*)psi;
+    return launch_point<R, PT_SCALE_REAL>(p, a, s);
+  }
   a.out = (typename CT<R>::T*)psi;
   return launch_point<R, PT_SCALE>(p, a, s);
 }
@@ -1086,9 +1129,9 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
 // explicit instantiations
 #define GPE_INST(R)                                                                                            \
   template hipError_t run_itp_pass1<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
-                                       hipStream_t);                                                         \
+                                       bool, hipStream_t);                                                   \
   template hipError_t run_itp_pass2<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
-                                       hipStream_t);                                                         \
+                                       bool, hipStream_t);                                                   \
   template hipError_t run_rk_stage<R>(const Plan&, const LaunchConfig&, int, bool, const void*, const void*, \
                                       const void*, const void*, const void*, void*, int64_t, hipStream_t);   \
   template hipError_t run_rk_stage2_fold<R>(const Plan&, const LaunchConfig&, const void*, const void*,       \
@@ -1099,11 +1142,11 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
                                         const void* const*, const double*, double, double, const void*, void*, \
                                         int64_t, hipStream_t);                                                \
   template hipError_t run_observe<R>(const Plan&, const LaunchConfig&, const void*, const void*, double, bool, \
-                                     int64_t, hipStream_t);                                                  \
+                                     int64_t, hipStream_t, bool);                                            \
   template hipError_t run_adj_stage<R>(const Plan&, const LaunchConfig&, int, const void*, const void*,      \
                                        const void*, const void*, void*, void*, int64_t, hipStream_t);        \
   template hipError_t run_make_prop<R>(const Plan&, const LaunchConfig&, const void*, void*, hipStream_t);   \
-  template hipError_t run_apply_scale<R>(const Plan&, const LaunchConfig&, void*, hipStream_t);              \
+  template hipError_t run_apply_scale<R>(const Plan&, const LaunchConfig&, void*, bool, hipStream_t);        \
   template hipError_t run_overlap<R>(const Plan&, const LaunchConfig&, const void*, const void*, hipStream_t); \
   template hipError_t run_seed_lambda<R>(const Plan&, const LaunchConfig&, const void*, void*, hipStream_t); \
   template hipError_t run_field_range<R>(const Plan&, const LaunchConfig&, const void*, hipStream_t);        \

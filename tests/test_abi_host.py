@@ -187,7 +187,12 @@ def test_errors_are_reported_without_side_effects(lib):
         sizes[mode] = b.value
     assert 2 * 432 <= sizes[_lib.GPE_MODE_RT_RKHE3] < 3 * 432 <= sizes[_lib.GPE_MODE_RT] < 4 * 432
     assert 5 * 432 <= sizes[_lib.GPE_MODE_RT_RKCK] < 6 * 432 + 4096
-    assert lib.gpe_work_bytes(g.handle, 0, 5, 10, 0, C.byref(b)) == _lib.GPE_ERR_ARG
+    # imaginary time on a real state: one real per site for the temporary
+    assert lib.gpe_work_bytes(g.handle, 0, _lib.GPE_MODE_ITP, 10, 0, C.byref(b)) == 0
+    itp_c = b.value
+    assert lib.gpe_work_bytes(g.handle, 0, _lib.GPE_MODE_ITP_REAL, 10, 0, C.byref(b)) == 0
+    assert 2 * 27 * 8 <= b.value < itp_c
+    assert lib.gpe_work_bytes(g.handle, 0, 6, 10, 0, C.byref(b)) == _lib.GPE_ERR_ARG
     # an unknown integrator is rejected before anything else runs
     bad = _lib.Params(1.0, 1e-3, 1.0, 0, 0, 7)
     st = lib.gpe_real_time(g.handle, 0, 16, C.byref(pot), C.byref(bad), 0.0, 1, 16, 1 << 20, None, None, None)

@@ -1,0 +1,115 @@
+"""GPU parity of imaginary time on a real state (Sec. II.A: a real start
+stays real under eqs. (6)-(7)), through gpe_imag_time_real, against the FP64
+oracle run on the same real start.
+
+Tolerances: relative L2 <= 1e-10 (float64 state), <= 1e-5 (float32)."""
+import numpy as np
+import pytest
+
+from oracle import itp, observables as ob
+from workloads import configs
+
+from gpu_cases import Case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_05447_amd as p
+    p.load_library()
+
+
+def _real_start(w, seed):
+    rng = np.random.default_rng(seed)
+    x = np.abs(w.psi0) * (1.0 + 0.3 * rng.standard_normal(w.n_active))
+    return x / np.sqrt(np.sum(x * x) * w.box.dV)
+
+
+def _real_psi(c, x):
+    import torch
+    return torch.tensor(x, dtype=c.rdt, device=c.dev)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("make", [lambda: configs.small_shell(n=24),
+                                  lambda: configs.random_mask_problem(n=(12, 11, 13), density=0.45, seed=31, g=40.0),
+                                  lambda: configs.small_rf_ramp(n=28, steps=30)],
+                         ids=["shell24", "random", "rframp28"])
+def test_real_imag_time_matches_oracle(dtype, make):
+    w = make()
+    c = Case(w, dtype)
+    x = _real_start(w, 4)
+    psi = _real_psi(c, x)
+    steps, dt = 25, 2e-3
+    print(f"ITP-real {w.name} n={w.n_active} {dtype}", flush=True)
+    obs = c.grid.imag_time(psi, c.pot, w.g, dt, steps)
+    V = w.field if w.kind != "rf" else c.opot(0.0)
+    ref, _ = itp.imaginary_time(c.T, x.astype(complex), V, w.g, dt, w.box.dV, steps)
+    assert np.all(ref.imag == 0.0)
+    err = rel_l2(psi.cpu().numpy(), ref.real)
+    print(f"  rel L2 = {err:.3e}", flush=True)
+    assert err <= TOL[dtype]
+    N, E, mu = ob.energy_mu(c.T, ref, V, w.g, w.box.dV)
+    assert abs(obs["norm"] - 1.0) <= (1e-12 if dtype == "c128" else 1e-6)
+    assert abs(obs["energy"] - E) <= TOL[dtype] * abs(E) * 10
+    assert abs(obs["mu"] - mu) <= TOL[dtype] * abs(mu) * 10
+
+
+def test_real_and_complex_paths_agree_with_history():
+    """The real path equals the complex path on the same start (imaginary
+    parts zero), observation history included."""
+    import torch
+    w = configs.small_shell(n=24)
+    c = Case(w, "c128")
+    x = _real_start(w, 9)
+    pr = _real_psi(c, x)
+    pc = c.psi(x.astype(complex))
+    hr = torch.zeros((4, 3), dtype=torch.float64, device=c.dev)
+    hc = torch.zeros((4, 3), dtype=torch.float64, device=c.dev)
+    c.grid.imag_time(pr, c.pot, w.g, 1e-3, 20, obs_every=5, history=hr)
+    c.grid.imag_time(pc, c.pot, w.g, 1e-3, 20, obs_every=5, history=hc)
+    out_c = pc.cpu().numpy()
+    assert np.max(np.abs(out_c.imag)) == 0.0
+    assert rel_l2(pr.cpu().numpy(), out_c.real) <= 1e-14
+    assert np.allclose(hr.cpu().numpy(), hc.cpu().numpy(), rtol=1e-13, atol=0)
+
+
+def test_real_imag_time_every_launch_config():
+    from paper_2603_05447_amd import config_count
+    w = configs.random_mask_problem(n=(12, 11, 13), density=0.45, seed=31, g=40.0)
+    x = _real_start(w, 11)
+    ref = None
+    for k in range(config_count()):
+        c = Case(w, "c128", config=k)
+        p = _real_psi(c, x)
+        c.grid.imag_time(p, c.pot, w.g, 2e-3, 10, observe=False)
+        if ref is None:
+            r, _ = itp.imaginary_time(c.T, x.astype(complex), w.field, w.g, 2e-3, w.box.dV, 10)
+            ref = r.real
+        assert rel_l2(p.cpu().numpy(), ref) <= 1e-10, k
+
+
+def test_real_imag_time_single_site_and_zero_steps():
+    from workloads import Box
+    import torch
+    from paper_2603_05447_amd import Grid, Potential, GPEError, _lib
+    box = Box.centred(3, 1.5)
+    runs = np.array([[1, 1, 1, 2]], dtype=np.int64)
+    g = Grid.from_box(box, runs=runs, device=0)
+    field = torch.tensor([0.5], dtype=torch.float64, device="cuda:0")
+    pot = Potential.static(field)
+    psi = torch.tensor([3.0], dtype=torch.float64, device="cuda:0")
+    o = g.imag_time(psi, pot, 1.0, 1e-3, 0)
+    assert psi.item() == 3.0 and abs(o["norm"] - 9.0 * box.dV) <= 1e-12 * 9.0 * box.dV
+    g.imag_time(psi, pot, 1.0, 1e-3, 3)
+    assert abs(psi.item() ** 2 * box.dV - 1.0) <= 1e-14
+    z = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(GPEError) as e:
+        g.imag_time(z, pot, 1.0, 1e-3, 2)
+    assert e.value.status == _lib.GPE_ERR_NONFINITE

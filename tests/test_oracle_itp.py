@@ -121,3 +121,25 @@ def test_observables_on_eigenvector():
     _, E0, mu0 = ob.energy_mu(T, psi, w.field, 0.0, w.box.dV)
     _, E1, mu1 = ob.energy_mu(T, psi, w.field, 2.0, w.box.dV)
     assert abs((E1 - E0) - 0.49) < 1e-14 and abs((mu1 - mu0) - 0.98) < 1e-14
+
+
+def test_real_start_stays_real_and_phase_is_carried():
+    """Sec. II.A: with a real start, real V and real g every factor of one
+    step (the diagonal half-steps and the Euler substeps with the real
+    symmetric T~) is real, so psi stays real: the oracle's complex step on a
+    real input leaves exactly zero imaginary parts.  The step is also
+    equivariant under a global phase (it depends on psi only through psi and
+    |psi|^2), so a start e^{i theta} x ends at e^{i theta} times the real
+    result; a stray conjugation or a dropped imaginary term breaks this."""
+    w = configs.random_mask_problem(n=(9, 8, 10), density=0.5, seed=5, g=30.0)
+    lin = site_linear_index(w.box, w.runs)
+    T = op.kinetic_direct(w.box.n, w.box.h, lin)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(lin.size)
+    x /= np.sqrt(np.sum(x * x) * w.box.dV)
+    dt = 1e-3
+    out, _ = itp.imaginary_time(T, x.astype(complex), w.field, w.g, dt, w.box.dV, 12)
+    assert np.all(out.imag == 0.0)
+    ph = np.exp(0.7j)
+    rot, _ = itp.imaginary_time(T, ph * x, w.field, w.g, dt, w.box.dV, 12)
+    assert np.max(np.abs(rot - ph * out.real)) <= 1e-13 * np.max(np.abs(out))
