@@ -279,7 +279,8 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch batch, gpe_dtype dtype, const void*
  * A launch configuration is an index into the table of compiled kernel
  * variants: workgroup size x sites per lane, the order in which chunks are
  * handed to the XCDs (0 array order, 1 contiguous eighths, 2/3 blocks of
- * 64/256 chunks dealt round-robin), and the
+ * 64/256 chunks dealt round-robin, 4 the x-th eighth of every x-plane's
+ * chunks to XCD x, plane after plane), and the
  * RK4 storage scheme (0: the App. A form, whose last stage reads y0, y2, y3;
  * 1: the second stage also stores A = (-y0 + y2 + 2 y3)/3 so the last stage
  * reads A alone, 16 fewer bytes per site per complex128 step; both give the

@@ -148,7 +148,9 @@ struct ChunkSet {
   int n_chunks = 0;
   int max_seg = 1;
   Chunk* d_chunks = nullptr;
+  int32_t* d_order = nullptr;          // workgroup -> chunk for order mode 4 (built on first use)
   std::vector<int> inst_begin, inst_count;
+  std::vector<int32_t> site_begin;     // host copy of each chunk's first site
 };
 
 struct Problem {
@@ -160,6 +162,7 @@ struct Problem {
   std::vector<int64_t> inst_seg;       // n_inst + 1
   std::vector<double> inst_h;          // 3 per instance
   std::vector<SegHead> heads;          // host copy (n_segs + 1)
+  std::vector<int64_t> plane_begin;    // first compact site of every non-empty x-plane of every instance
   SegHead* d_heads = nullptr;
   SegNb* d_nbs = nullptr;
   std::map<int, ChunkSet> chunksets;
@@ -190,7 +193,10 @@ struct Problem {
     DeviceGuard g(device);
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
-    for (auto& kv : chunksets) (void)hipFree(kv.second.d_chunks);
+    for (auto& kv : chunksets) {
+      (void)hipFree(kv.second.d_chunks);
+      (void)hipFree(kv.second.d_order);
+    }
     chunksets.clear();
     (void)hipFree(d_heads);
     (void)hipFree(d_nbs);
@@ -240,6 +246,12 @@ struct Problem {
       }
     }
     heads[n_segs] = {(int32_t)total, 0};
+    plane_begin.clear();
+    for (int i = 0; i < n_inst; ++i) {
+      const Layout& L = *lays[i];
+      for (int64_t r = 0; r < L.n_runs(); ++r)
+        if (r == 0 || L.run_i[r] != L.run_i[r - 1]) plane_begin.push_back(inst_site[i] + L.run_start[r]);
+    }
     DeviceGuard g(device);
     if (!g.ok) return fail(GPE_ERR_DEVICE, "hipSetDevice(%d) failed", device);
     // chunks of >= 256 sites each, plus at most one extra chunk per
@@ -312,6 +324,7 @@ struct Problem {
         c.pad[0] = c.pad[1] = c.pad[2] = 0;
         cs.max_seg = std::max(cs.max_seg, c.seg_count);
         tab.push_back(c);
+        cs.site_begin.push_back(c.site_begin);
         b = e;
       }
       cs.inst_count[i] = (int)tab.size() - cs.inst_begin[i];
@@ -330,6 +343,52 @@ struct Problem {
     return GPE_OK;
   }
 
+  // Order mode 4: workgroup b runs on XCD b % 8, so XCD x is given, plane
+  // after plane, the x-th eighth of every x-plane's chunks.  The i-1 / i+1
+  // neighbours of a site then lie in chunks the same XCD streamed just
+  // before or will stream next (same L2), while all XCDs still work on the
+  // same few planes at a time.  Which XCDs take the one-larger groups of a
+  // plane rotates so the eight lists stay within one chunk of each other.
+  gpe_status order_for(ChunkSet& cs) {
+    if (cs.d_order) return GPE_OK;
+    std::vector<std::vector<int32_t>> lists(8);
+    size_t c = 0;
+    const size_t G = (size_t)cs.n_chunks;
+    size_t pl = 0;
+    while (c < G) {
+      // chunks whose first site lies in the plane of chunk c
+      while (pl + 1 < plane_begin.size() && plane_begin[pl + 1] <= cs.site_begin[c]) ++pl;
+      const int64_t plane_end = (pl + 1 < plane_begin.size()) ? plane_begin[pl + 1] : INT64_MAX;
+      size_t e = c;
+      while (e < G && cs.site_begin[e] < plane_end) ++e;
+      const size_t m = e - c, q = m / 8, r = m % 8;
+      std::vector<int> by(8);
+      for (int x = 0; x < 8; ++x) by[x] = x;
+      std::stable_sort(by.begin(), by.end(), [&](int a, int b) { return lists[a].size() < lists[b].size(); });
+      std::vector<char> big(8, 0);
+      for (size_t k = 0; k < r; ++k) big[by[k]] = 1;
+      for (int x = 0; x < 8; ++x) {
+        const size_t take = q + (big[x] ? 1 : 0);
+        for (size_t k = 0; k < take; ++k) lists[x].push_back((int32_t)(c++));
+      }
+      if (c != e) return fail(GPE_ERR_STATE, "internal: plane split of the chunk table");
+    }
+    // longer lists take the low XCD numbers so that b = 8 w + x < G covers them exactly
+    std::stable_sort(lists.begin(), lists.end(),
+                     [](const std::vector<int32_t>& a, const std::vector<int32_t>& b) { return a.size() > b.size(); });
+    std::vector<int32_t> order(G);
+    for (size_t b = 0; b < G; ++b) order[b] = lists[b % 8][b / 8];
+    DeviceGuard g(device);
+    if (dalloc(&cs.d_order, G) != hipSuccess) return fail(GPE_ERR_ALLOC, "chunk order allocation failed");
+    hipError_t err = hipMemcpy(cs.d_order, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+      (void)hipFree(cs.d_order);
+      cs.d_order = nullptr;
+      return hip_fail(err, "chunk order upload");
+    }
+    return GPE_OK;
+  }
+
   Plan plan(const ChunkSet& cs, const LaunchConfig& cfg) const {
     Plan p;
     p.heads = d_heads;
@@ -343,6 +402,7 @@ struct Problem {
     p.n_chunks = cs.n_chunks;
     p.n_inst = n_inst;
     p.xcd_map = cfg.xcd;
+    p.order = cs.d_order;
     p.pstride = (int32_t)max_chunks;
     // complex128 is the widest per-site element (16 bytes)
     p.off32 = ((uint64_t)total * 16u < (uint64_t(1) << 32)) ? 1 : 0;
@@ -587,6 +647,10 @@ gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
   }
   gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs);
   if (st != GPE_OK) return st;
+  if (c.cfg.xcd == 4) {
+    st = P->order_for(*c.cs);
+    if (st != GPE_OK) return st;
+  }
   c.pl = P->plan(*c.cs, c.cfg);
   c.s = s;
   return GPE_OK;

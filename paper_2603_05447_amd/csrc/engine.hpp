@@ -63,6 +63,7 @@ struct Plan {
   int32_t n_chunks;
   int32_t n_inst;
   int32_t xcd_map;        // chunk order mode (see chunk_index in kernels.hip)
+  const int32_t* order;   // mode 4: chunk of each workgroup (n_chunks entries)
   int32_t pstride;        // stride between partial-sum components (>= n_chunks)
   int32_t off32;          // 1: every per-site array is below 4 GiB (32-bit byte offsets)
   int32_t max_seg;        // largest seg_count of any chunk (sizes the dynamic LDS)
