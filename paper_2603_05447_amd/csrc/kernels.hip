@@ -369,11 +369,17 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 
   // ---- segment search and the lateral loads of all of the lane's sites ----
-  // An absent lateral neighbour (offset 0) loads the site itself and gets
-  // stencil weight 0, so every lane issues the same four loads.
+  // An absent lateral neighbour (offset 0) stands for the site itself and
+  // gets stencil weight 0, so there is no divergence on presence.  The j-1 /
+  // j+1 neighbours lie a column away in compact order, usually inside the
+  // chunk's staged window (sy[t] holds site site_begin - 1 + t for
+  // t < count + 2): those are read from LDS after the staging barrier, and
+  // only the rest are loaded from global memory here.  The i-1 / i+1
+  // neighbours are a plane away and always loaded.
   const int nseg = ch.seg_count;
   const int top = nseg > 1 ? (1 << (31 - __clz(nseg - 1))) : 0;
-  int js[SPT];
+  const int wbase = ch.site_begin - 1;
+  int js[SPT], tym[SPT], typ[SPT];
   S xm[SPT], xp[SPT], ym[SPT], yp[SPT];
   R wxm[SPT], wxp[SPT], wym[SPT], wyp[SPT];
 #pragma unroll
@@ -388,8 +394,13 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     const SegNb nb = snb[j];
     xm[m] = load(s + nb.xm);
     xp[m] = load(s + nb.xp);
-    ym[m] = load(s + nb.ym);
-    yp[m] = load(s + nb.yp);
+    const int tm = s - wbase + nb.ym, tp = s - wbase + nb.yp;
+    tym[m] = (tm >= 0 && tm < ch.count + 2) ? tm : -1;
+    typ[m] = (tp >= 0 && tp < ch.count + 2) ? tp : -1;
+    ym[m] = zero;
+    yp[m] = zero;
+    if (tym[m] < 0) ym[m] = load(s + nb.ym);
+    if (typ[m] < 0) yp[m] = load(s + nb.yp);
     wxm[m] = nb.xm ? cx : R(0);
     wxp[m] = nb.xp ? cx : R(0);
     wym[m] = nb.ym ? cy : R(0);
@@ -421,6 +432,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       const int send = sh[js[m] + 1].start;
       const S yc = sy[l + 1];
       const S zm = sy[l], zp = sy[l + 2];
+      if (tym[m] >= 0) ym[m] = sy[tym[m]];
+      if (typ[m] >= 0) yp[m] = sy[typ[m]];
       const R wzm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? R(0) : cz;
       const R wzp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? R(0) : cz;
       if constexpr (REAL) {
