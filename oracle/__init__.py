@@ -22,7 +22,10 @@ beyond what the paper's own equations state:
                   respect to ramp knots, with sqrt(N) checkpointing (the
                   paper is silent here; see the module docstring);
 * tableau.py      the memory-optimised Runge-Kutta coefficients of App. A,
-                  derived in exact rational arithmetic.
+                  derived in exact rational arithmetic;
+* restage.py      staged ramps of Sec. V: potentials interpolated linearly
+                  between stage arrays, re-post-selection at each stage end
+                  and the carry-over of psi between grids.
 
 Units: hbar = m = 1, so T~ = -1/2 Laplacian restricted to the active set.
 """
