@@ -81,4 +81,5 @@ def test_a_stage_with_equal_end_potentials_is_the_static_run():
     psi = (rng.standard_normal(lin.size) + 1j * rng.standard_normal(lin.size)) * 0.1
     a = rt.real_time(T, psi, restage.LerpPotential(V, V, 0.0, 0.1), 2.0, 1e-3, 0.0, 20)
     b = rt.real_time(T, psi, StaticPotential(V), 2.0, 1e-3, 0.0, 20)
-    assert np.array_equal(a, b)
+    # (1 - lam) V + lam V equals V up to one rounding per evaluation
+    assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(b))
