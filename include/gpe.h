@@ -87,10 +87,17 @@ typedef struct gpe_batch_s* gpe_batch;
  *            potential with bare trap U = field; Delta(t) is the
  *            piecewise-linear interpolant of (knot_t[k], knot_delta[k]),
  *            constant before the first and after the last knot.
- * `field` is a device pointer to n_active reals (double for GPE_C128, float
- * for GPE_C64).  knot_t/knot_delta are host arrays of n_knots (1..GPE_MAX_KNOTS)
- * entries, knot_t strictly increasing; ignored for STATIC. */
-typedef enum { GPE_POT_STATIC = 0, GPE_POT_RF_RAMP = 1 } gpe_pot_kind;
+ *   LERP   : one stage of a staged ramp (Sec. V: precomputed potentials,
+ *            linear interpolation in time between consecutive ones):
+ *            V(x,t) = (1 - l) field[x] + l field2[x], l = clamp((t - knot_t[0]) /
+ *            (knot_t[1] - knot_t[0]), 0, 1); n_knots = 2, knot_delta unused.
+ *            Real time and imaginary time only (not the fidelity gradient
+ *            or batches).
+ * `field` (and `field2`) are device pointers to n_active reals (double for
+ * GPE_C128, float for GPE_C64).  knot_t/knot_delta are host arrays of n_knots
+ * (1..GPE_MAX_KNOTS) entries, knot_t strictly increasing; ignored for STATIC.
+ * field2 is ignored except for LERP. */
+typedef enum { GPE_POT_STATIC = 0, GPE_POT_RF_RAMP = 1, GPE_POT_LERP = 2 } gpe_pot_kind;
 
 typedef struct {
   int32_t kind;
@@ -99,6 +106,7 @@ typedef struct {
   double omega;
   const double* knot_t;
   const double* knot_delta;
+  const void* field2;
 } gpe_potential;
 
 typedef struct {
@@ -134,6 +142,27 @@ gpe_status gpe_grid_create(const gpe_geometry* geom, const uint8_t* mask_host, i
 gpe_status gpe_grid_create_runs(const gpe_geometry* geom, int64_t nruns, const int64_t* runs_host,
                                 int device, gpe_grid* out);
 
+/* Post-selection from potentials on the device (Sec. II.A; repeated at the
+ * end of every stage of a staged ramp in Sec. V): the active set is
+ * {x : min(va_box[x], vb_box[x]) < cutoff} over the whole box (vb_box may be
+ * NULL: va_box alone).  va_box/vb_box are device arrays of n0*n1*n2 reals in
+ * box linear order (double for GPE_C128, float for GPE_C64) on `device`
+ * (>= 0).  For a stage between potentials V_i and V_{i+1} the paper's cutoff
+ * is 5 max(mu_i, mu_{i+1}).  The mask is built by a device kernel, copied to
+ * the host and compacted as in gpe_grid_create; the call synchronises the
+ * device.  Errors as gpe_grid_create (an empty selection is GPE_ERR_ARG). */
+gpe_status gpe_grid_create_threshold(const gpe_geometry* geom, gpe_dtype dtype, const void* va_box,
+                                     const void* vb_box, double cutoff, int device, gpe_grid* out);
+
+/* Carry a wavefunction from one compact layout to another of the same box
+ * (Sec. V: psi is remapped from the old grid to the new one at every stage
+ * end): every site active in both keeps its value, sites only in `dst` are
+ * set to zero, sites only in `src` are dropped.  psi_src holds src's
+ * n_active complex values, psi_dst receives dst's; they must not alias.
+ * Both grids must be on the same device with the same box dimensions.  The
+ * copy is exact (no arithmetic).  The call synchronises `stream`. */
+gpe_status gpe_remap(gpe_grid src, gpe_grid dst, gpe_dtype dtype, const void* psi_src, void* psi_dst, void* stream);
+
 gpe_status gpe_grid_info(gpe_grid grid, int64_t* n_active, int64_t* n_runs, int64_t* n_segments);
 
 /* Host copy of the segment table: n_segments x 8 int32 per segment
@@ -162,6 +191,10 @@ gpe_status gpe_work_bytes(gpe_grid grid, gpe_dtype dtype, int32_t mode, int64_t 
  * gpe_unpack writes zeros at inactive box points. */
 gpe_status gpe_pack(gpe_grid grid, gpe_dtype dtype, const void* box_dev, void* compact_dev, void* stream);
 gpe_status gpe_unpack(gpe_grid grid, gpe_dtype dtype, const void* compact_dev, void* box_dev, void* stream);
+/* Box -> compact for a real field (a potential on the full grid, Sec. V's
+ * precomputed stage potentials): n0*n1*n2 reals in, n_active reals out
+ * (double for GPE_C128, float for GPE_C64). */
+gpe_status gpe_pack_real(gpe_grid grid, gpe_dtype dtype, const void* box_dev, void* compact_dev, void* stream);
 
 /* Imaginary-time propagation with renormalisation (Sec. II.A, eqs. (6)-(7)).
  * Each step: psi <- psi exp(-V dt/2)(1 - g|psi|^2 dt/2); two forward-Euler

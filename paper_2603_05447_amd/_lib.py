@@ -13,7 +13,7 @@ STATUS_NAMES = ["GPE_OK", "GPE_ERR_ARG", "GPE_ERR_ALLOC", "GPE_ERR_DEVICE", "GPE
 GPE_C128, GPE_C64 = 0, 1
 GPE_MODE_ITP, GPE_MODE_RT, GPE_MODE_ADJ, GPE_MODE_RT_RKHE3, GPE_MODE_RT_RKCK, GPE_MODE_ITP_REAL = range(6)
 GPE_RK4, GPE_RKHE3, GPE_RKCK = 0, 1, 2
-GPE_POT_STATIC, GPE_POT_RF_RAMP = 0, 1
+GPE_POT_STATIC, GPE_POT_RF_RAMP, GPE_POT_LERP = 0, 1, 2
 GPE_MAX_KNOTS = 32
 
 
@@ -23,7 +23,7 @@ class Geometry(C.Structure):
 
 class Potential(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_knots", C.c_int32), ("field", C.c_void_p), ("omega", C.c_double),
-                ("knot_t", C.POINTER(C.c_double)), ("knot_delta", C.POINTER(C.c_double))]
+                ("knot_t", C.POINTER(C.c_double)), ("knot_delta", C.POINTER(C.c_double)), ("field2", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -51,6 +51,9 @@ SIGNATURES = {
     "gpe_abi_version": (C.c_int, []),
     "gpe_grid_create": (C.c_int, [C.POINTER(Geometry), _vp, C.c_int, C.POINTER(_vp)]),
     "gpe_grid_create_runs": (C.c_int, [C.POINTER(Geometry), _i64, _vp, C.c_int, C.POINTER(_vp)]),
+    "gpe_grid_create_threshold": (C.c_int, [C.POINTER(Geometry), C.c_int, _vp, _vp, C.c_double, C.c_int,
+                                            C.POINTER(_vp)]),
+    "gpe_remap": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _vp]),
     "gpe_grid_info": (C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "gpe_grid_segments": (C.c_int, [_vp, _vp]),
     "gpe_grid_runs": (C.c_int, [_vp, _vp]),
@@ -58,6 +61,7 @@ SIGNATURES = {
     "gpe_work_bytes": (C.c_int, [_vp, C.c_int, _i32, _i64, _i64, C.POINTER(C.c_size_t)]),
     "gpe_pack": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "gpe_unpack": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "gpe_pack_real": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "gpe_imag_time": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), _i64, _vp,
                                 C.c_size_t, _vp, C.POINTER(Obs), _vp]),
     "gpe_imag_time_real": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), _i64, _vp,

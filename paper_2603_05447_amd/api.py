@@ -45,11 +45,14 @@ def _dbl(a) -> C.Array:
 
 
 class Potential:
-    """Static V(x) or RF-dressed ramp V = sqrt((U - Delta(t))^2 + omega^2)."""
+    """Static V(x), RF-dressed ramp V = sqrt((U - Delta(t))^2 + omega^2), or
+    one stage of a staged ramp V = (1 - l) V_a + l V_b (LERP)."""
 
-    def __init__(self, kind: int, field: torch.Tensor, omega: float = 0.0, knot_t=None, knot_delta=None):
+    def __init__(self, kind: int, field: torch.Tensor, omega: float = 0.0, knot_t=None, knot_delta=None,
+                 field2: Optional[torch.Tensor] = None):
         self.kind = kind
         self.field = field
+        self.field2 = field2
         self.omega = float(omega)
         self.knot_t = None if knot_t is None else np.asarray(knot_t, np.float64)
         self.knot_delta = None if knot_delta is None else np.asarray(knot_delta, np.float64)
@@ -61,6 +64,11 @@ class Potential:
     @staticmethod
     def rf(U: torch.Tensor, omega: float, knot_t, knot_delta) -> "Potential":
         return Potential(L.GPE_POT_RF_RAMP, U, omega, knot_t, knot_delta)
+
+    @staticmethod
+    def lerp(Va: torch.Tensor, Vb: torch.Tensor, t_a: float, t_b: float) -> "Potential":
+        """Stage potential interpolated linearly in time from Va (at t_a) to Vb (at t_b)."""
+        return Potential(L.GPE_POT_LERP, Va, 0.0, [t_a, t_b], None, field2=Vb)
 
     def with_knots(self, knot_delta) -> "Potential":
         return Potential(self.kind, self.field, self.omega, self.knot_t, knot_delta)
@@ -80,6 +88,15 @@ class Potential:
             p.n_knots = len(self.knot_t)
             p.knot_t = C.cast(kt, C.POINTER(C.c_double))
             p.knot_delta = C.cast(kd, C.POINTER(C.c_double))
+        elif self.kind == L.GPE_POT_LERP:
+            f2 = self.field2
+            if f2 is None or f2.dtype != want or not f2.is_cuda or not f2.is_contiguous():
+                raise TypeError(f"stage end field must be a contiguous CUDA tensor of {want}")
+            kt = _dbl(self.knot_t)
+            keep = [kt]
+            p.n_knots = 2
+            p.knot_t = C.cast(kt, C.POINTER(C.c_double))
+            p.field2 = f2.data_ptr()
         else:
             p.n_knots = 0
         return p, keep
@@ -128,6 +145,7 @@ class Grid:
             raise ValueError("need runs or mask")
         self._h = handle
         self.device = int(device)
+        self.x0 = tuple(float(v) for v in x0)
         self.n = tuple(int(v) for v in n)
         self.h = tuple(float(v) for v in h)
         self.dV = self.h[0] * self.h[1] * self.h[2]
@@ -139,6 +157,55 @@ class Grid:
     @staticmethod
     def from_box(box, runs=None, mask=None, device: int = 0) -> "Grid":
         return Grid(box.n, box.h, box.x0, runs=runs, mask=mask, device=device)
+
+    @staticmethod
+    def from_threshold(n, h, x0, Va_box: torch.Tensor, Vb_box: Optional[torch.Tensor], cutoff: float,
+                       device: int = 0) -> "Grid":
+        """Post-selection on the device: keep the box points where
+        min(Va_box, Vb_box) < cutoff (gpe_grid_create_threshold)."""
+        dt_ = {torch.float64: L.GPE_C128, torch.float32: L.GPE_C64}.get(Va_box.dtype)
+        if dt_ is None:
+            raise TypeError("Va_box must be float64 or float32")
+        for t in (Va_box, Vb_box):
+            if t is not None and (t.dtype != Va_box.dtype or not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() != int(n[0]) * int(n[1]) * int(n[2])):
+                raise ValueError("potentials must be contiguous CUDA box arrays of one real dtype")
+        geom = L.Geometry()
+        for d in range(3):
+            geom.n[d], geom.h[d], geom.x0[d] = int(n[d]), float(h[d]), float(x0[d])
+        handle = C.c_void_p()
+        check(L.load().gpe_grid_create_threshold(C.byref(geom), dt_, Va_box.data_ptr(), _ptr(Vb_box),
+                                                  float(cutoff), int(device), C.byref(handle)))
+        return Grid._wrap(handle, n, h, x0, int(device))
+
+    @staticmethod
+    def _wrap(handle, n, h, x0, device: int) -> "Grid":
+        g = Grid.__new__(Grid)
+        g._h = handle
+        g.device = device
+        g.x0 = tuple(float(v) for v in x0)
+        g.n = tuple(int(v) for v in n)
+        g.h = tuple(float(v) for v in h)
+        g.dV = g.h[0] * g.h[1] * g.h[2]
+        na, nr, ns = C.c_int64(), C.c_int64(), C.c_int64()
+        check(L.load().gpe_grid_info(handle, C.byref(na), C.byref(nr), C.byref(ns)))
+        g.n_active, g.n_runs, g.n_segments = na.value, nr.value, ns.value
+        g._work = {}
+        return g
+
+    def remap_from(self, src: "Grid", psi_src: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+        """psi on this grid from psi on `src` (same box): common sites copied,
+        new sites zero (gpe_remap)."""
+        dt_ = _dtype_of(psi_src)
+        if psi_src.numel() != src.n_active:
+            raise ValueError("psi_src must hold the source grid's n_active values")
+        if out is None:
+            out = torch.empty(self.n_active, dtype=psi_src.dtype, device=psi_src.device)
+        if out.numel() != self.n_active or out.dtype != psi_src.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of this grid's n_active values")
+        check(L.load().gpe_remap(src._h, self._h, dt_, psi_src.data_ptr(), out.data_ptr(), _stream(stream)))
+        return out
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -250,16 +317,33 @@ class Grid:
         return loss.value, np.array(grad[:n])
 
     def pack(self, box: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        dt_ = _dtype_of(box)
+        """Box array -> compact.  Complex (psi) or real (a potential field)."""
+        nbox = self.n[0] * self.n[1] * self.n[2]
+        if box.numel() != nbox:
+            raise ValueError(f"box array has {box.numel()} elements, the grid's box {nbox}")
+        real = box.dtype in _RSTATE
+        if real:
+            if not box.is_cuda or not box.is_contiguous():
+                raise ValueError("box must be a contiguous CUDA/HIP tensor")
+            dt_ = _RSTATE[box.dtype]
+        else:
+            dt_ = _dtype_of(box)
         if out is None:
             out = torch.empty(self.n_active, dtype=box.dtype, device=box.device)
-        check(L.load().gpe_pack(self._h, dt_, box.data_ptr(), out.data_ptr(), _stream(stream)))
+        if out.numel() != self.n_active or out.dtype != box.dtype or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor of n_active elements of the box's dtype")
+        fn = L.load().gpe_pack_real if real else L.load().gpe_pack
+        check(fn(self._h, dt_, box.data_ptr(), out.data_ptr(), _stream(stream)))
         return out
 
     def unpack(self, compact: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         dt_ = _dtype_of(compact)
+        if compact.numel() != self.n_active:
+            raise ValueError("compact array must hold n_active elements")
         if out is None:
             out = torch.empty(self.n, dtype=compact.dtype, device=compact.device)
+        if out.numel() != self.n[0] * self.n[1] * self.n[2]:
+            raise ValueError("out must hold the whole box")
         check(L.load().gpe_unpack(self._h, dt_, compact.data_ptr(), out.data_ptr(), _stream(stream)))
         return out
 
@@ -425,3 +509,35 @@ class KernelTimer:
             check(lib.gpe_timing_read(f, C.byref(n), C.byref(ms)))
             out[lib.gpe_timing_name(f).decode()] = {"launches": n.value, "total_ms": ms.value}
         return out
+
+
+def staged_ramp(grid: Grid, psi: torch.Tensor, stage_fields: Sequence[torch.Tensor], mus: Sequence[float], g: float,
+                dt: float, steps_per_stage: int, t0: float = 0.0, integrator: str = "rk4", stream=None):
+    """The staged ramp of Sec. V.  stage_fields[i] is the potential V_i on the
+    whole box (device, real, box order); mus[i] the chemical potential of the
+    ground state in V_i.  Stage i (i = 0 .. S-1) first re-post-selects the
+    grid, keeping min(V_i, V_{i+1}) < 5 max(mu_i, mu_{i+1}), carries psi over,
+    then runs `steps_per_stage` real-time steps with V interpolated linearly
+    from V_i to V_{i+1} over the stage.  Returns the final grid, psi on it
+    and per-stage records (active sites, norm kept by the carry-over, norm at
+    the stage end)."""
+    if len(mus) != len(stage_fields):
+        raise ValueError("one chemical potential per stage potential")
+    records = []
+    n, h, x0 = grid.n, grid.h, grid.x0
+    for i in range(len(stage_fields) - 1):
+        cut = 5.0 * max(float(mus[i]), float(mus[i + 1]))
+        new = Grid.from_threshold(n, h, x0, stage_fields[i], stage_fields[i + 1], cut, device=grid.device)
+        if new.n_active == grid.n_active and np.array_equal(new.runs(), grid.runs()):
+            new = grid
+        else:
+            psi = new.remap_from(grid, psi, stream=stream)
+        ta = t0 + i * steps_per_stage * dt
+        tb = ta + steps_per_stage * dt
+        pot = Potential.lerp(new.pack(stage_fields[i]), new.pack(stage_fields[i + 1]), ta, tb)
+        kept = new.observe(psi, pot, ta, g, stream=stream)["norm"]
+        obs = new.real_time(psi, pot, g, dt, steps_per_stage, t0=ta, stream=stream, integrator=integrator)
+        records.append({"stage": i, "cutoff": cut, "n_active": new.n_active, "norm_after_remap": kept,
+                        "norm_end": obs["norm"], "energy_end": obs["energy"]})
+        grid = new
+    return grid, psi, records

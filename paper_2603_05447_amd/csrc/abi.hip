@@ -569,9 +569,18 @@ gpe_status check_knots(int32_t n, const double* kt, const double* kv, const char
 
 gpe_status check_pot(const gpe_potential* pot) {
   if (!pot) return fail(GPE_ERR_ARG, "potential is NULL");
-  if (pot->kind != GPE_POT_STATIC && pot->kind != GPE_POT_RF_RAMP) return fail(GPE_ERR_ARG, "unknown potential kind");
+  if (pot->kind != GPE_POT_STATIC && pot->kind != GPE_POT_RF_RAMP && pot->kind != GPE_POT_LERP)
+    return fail(GPE_ERR_ARG, "unknown potential kind");
   gpe_status st = check_ptr(pot->field, "potential field");
   if (st != GPE_OK) return st;
+  if (pot->kind == GPE_POT_LERP) {
+    st = check_ptr(pot->field2, "potential field2");
+    if (st != GPE_OK) return st;
+    if (pot->n_knots != 2 || !pot->knot_t) return fail(GPE_ERR_ARG, "a LERP potential needs n_knots = 2 stage times");
+    if (!std::isfinite(pot->knot_t[0]) || !std::isfinite(pot->knot_t[1]) || !(pot->knot_t[1] > pot->knot_t[0]))
+      return fail(GPE_ERR_ARG, "LERP stage times must be finite and increasing");
+    return GPE_OK;
+  }
   if (pot->kind == GPE_POT_RF_RAMP) {
     if (!std::isfinite(pot->omega)) return fail(GPE_ERR_ARG, "omega must be finite");
     return check_knots(pot->n_knots, pot->knot_t, pot->knot_delta, "potential");
@@ -606,6 +615,13 @@ InstParams make_params(const gpe_potential* pot, const gpe_params* prm, double t
   ip.pot_kind = pot ? pot->kind : GPE_POT_STATIC;
   ip.omega = (pot && pot->kind == GPE_POT_RF_RAMP) ? pot->omega : 0.0;
   ip.n_knots = 1;
+  ip.field2 = nullptr;
+  if (pot && pot->kind == GPE_POT_LERP) {
+    ip.n_knots = 2;
+    ip.knot_t[0] = pot->knot_t[0];
+    ip.knot_t[1] = pot->knot_t[1];
+    ip.field2 = pot->field2;
+  }
   if (pot && pot->kind == GPE_POT_RF_RAMP) {
     ip.n_knots = pot->n_knots;
     for (int k = 0; k < pot->n_knots; ++k) {
@@ -949,6 +965,16 @@ gpe_status field_vmax(const Ctx& c, const void* field, const std::vector<InstPar
   HIP_TRY(hipMemcpyAsync(o.data(), c.P->d_out, sizeof(InstOut) * c.P->n_inst, hipMemcpyDeviceToHost, c.s));
   HIP_TRY(hipStreamSynchronize(c.s));
   double m = 0.0;
+  if (c.P->n_inst == 1 && ps[0].pot_kind == GPE_POT_LERP) {
+    // V is a convex combination of the two stage arrays: |V| <= max of both ranges
+    m = std::max(std::fabs(o[0].fmin), std::fabs(o[0].fmax));
+    LTRY(run_field_range<R>(c.pl, c.cfg, ps[0].field2, c.s));
+    LTRY(run_finalize(c.pl, FIN_RANGE, nullptr, c.s));
+    HIP_TRY(hipMemcpyAsync(o.data(), c.P->d_out, sizeof(InstOut), hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    *vmax = std::max(m, std::max(std::fabs(o[0].fmin), std::fabs(o[0].fmax)));
+    return GPE_OK;
+  }
   for (int i = 0; i < c.P->n_inst; ++i) {
     const InstParams& ip = ps[i];
     if (ip.pot_kind == GPE_POT_RF_RAMP) {
@@ -1092,6 +1118,95 @@ gpe_status gpe_grid_create_runs(const gpe_geometry* geom, int64_t nruns, const i
   return finish_grid(geom, std::move(lay), device, out);
 }
 
+gpe_status gpe_grid_create_threshold(const gpe_geometry* geom, gpe_dtype dtype, const void* va_box,
+                                     const void* vb_box, double cutoff, int device, gpe_grid* out) {
+  if (!out) return fail(GPE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  gpe_status st = check_geom(geom);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(va_box, "va_box");
+  if (st != GPE_OK) return st;
+  if (vb_box) {
+    st = check_ptr(vb_box, "vb_box");
+    if (st != GPE_OK) return st;
+  }
+  if (std::isnan(cutoff)) return fail(GPE_ERR_ARG, "cutoff is NaN");
+  if (device < 0) return fail(GPE_ERR_ARG, "the potentials live on a device: device must be >= 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return fail(GPE_ERR_DEVICE, "device %d not available", device);
+  const int64_t npts = geom->n[0] * geom->n[1] * geom->n[2];
+  std::vector<uint8_t> mask((size_t)npts);
+  {
+    DeviceGuard dg(device);
+    uint8_t* d_mask = nullptr;
+    HIP_TRY(hipMalloc((void**)&d_mask, (size_t)npts));
+    hipError_t e = dtype == GPE_C128 ? run_threshold<double>(va_box, vb_box, npts, cutoff, d_mask, nullptr)
+                                     : run_threshold<float>(va_box, vb_box, npts, cutoff, d_mask, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(mask.data(), d_mask, (size_t)npts, hipMemcpyDeviceToHost);
+    (void)hipFree(d_mask);
+    if (e != hipSuccess) return hip_fail(e, "post-selection mask");
+  }
+  Layout lay;
+  std::string err = layout_from_mask(geom->n, mask.data(), lay);
+  if (!err.empty()) return fail(GPE_ERR_ARG, "%s", err.c_str());
+  return finish_grid(geom, std::move(lay), device, out);
+}
+
+gpe_status gpe_remap(gpe_grid src, gpe_grid dst, gpe_dtype dtype, const void* psi_src, void* psi_dst, void* stream) {
+  gpe_status st = check_grid(src);
+  if (st == GPE_OK) st = check_grid(dst);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi_src, "psi_src");
+  if (st == GPE_OK) st = check_ptr(psi_dst, "psi_dst");
+  if (st != GPE_OK) return st;
+  if (src->device != dst->device) return fail(GPE_ERR_ARG, "source and destination grids are on different devices");
+  for (int d = 0; d < 3; ++d)
+    if (src->lay.n[d] != dst->lay.n[d]) return fail(GPE_ERR_ARG, "source and destination grids have different boxes");
+  if (psi_src == psi_dst) return fail(GPE_ERR_ARG, "psi_src and psi_dst must not be the same buffer");
+  // intervals of the destination array: copied from consecutive source sites or zero
+  const Layout& A = src->lay;
+  const Layout& B = dst->lay;
+  std::vector<int64_t> ivd, ivs;
+  auto emit = [&](int64_t d0, int64_t s0) {
+    if (!ivd.empty() && ((s0 < 0 && ivs.back() < 0) ||
+                         (s0 >= 0 && ivs.back() >= 0 && ivs.back() + (d0 - ivd.back()) == s0)))
+      return;   // continues the previous interval
+    ivd.push_back(d0);
+    ivs.push_back(s0);
+  };
+  int64_t q = 0;
+  const int64_t na = A.n_runs();
+  for (int64_t r = 0; r < B.n_runs(); ++r) {
+    const int64_t i = B.run_i[r], j = B.run_j[r], k0 = B.run_k0[r], k1 = B.run_k1[r], d0 = B.run_start[r];
+    auto before = [&](int64_t x) {   // source run x lies wholly before this destination run
+      return A.run_i[x] < i || (A.run_i[x] == i && (A.run_j[x] < j || (A.run_j[x] == j && A.run_k1[x] <= k0)));
+    };
+    while (q < na && before(q)) ++q;
+    int64_t cur = k0;
+    for (int64_t x = q; x < na && A.run_i[x] == i && A.run_j[x] == j && A.run_k0[x] < k1; ++x) {
+      const int64_t o0 = std::max(k0, A.run_k0[x]), o1 = std::min(k1, A.run_k1[x]);
+      if (o0 > cur) emit(d0 + (cur - k0), -1);
+      if (o0 < o1) emit(d0 + (o0 - k0), A.run_start[x] + (o0 - A.run_k0[x]));
+      cur = std::max(cur, o1);
+    }
+    if (cur < k1) emit(d0 + (cur - k0), -1);
+  }
+  DeviceGuard dg(dst->device);
+  hipStream_t s = (hipStream_t)stream;
+  int64_t* d_iv = nullptr;
+  const int64_t n_iv = (int64_t)ivd.size();
+  HIP_TRY(hipMalloc((void**)&d_iv, sizeof(int64_t) * 2 * n_iv));
+  hipError_t e = hipMemcpy(d_iv, ivd.data(), sizeof(int64_t) * n_iv, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_iv + n_iv, ivs.data(), sizeof(int64_t) * n_iv, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = dtype == GPE_C128 ? run_remap<double>(d_iv, d_iv + n_iv, n_iv, B.n_active, psi_src, psi_dst, s)
+                          : run_remap<float>(d_iv, d_iv + n_iv, n_iv, B.n_active, psi_src, psi_dst, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_iv);
+  if (e != hipSuccess) return hip_fail(e, "remap");
+  return GPE_OK;
+}
+
 gpe_status gpe_grid_info(gpe_grid g, int64_t* n_active, int64_t* n_runs, int64_t* n_segments) {
   if (!g) return fail(GPE_ERR_ARG, "grid is NULL");
   if (n_active) *n_active = g->lay.n_active;
@@ -1160,6 +1275,23 @@ gpe_status gpe_pack(gpe_grid g, gpe_dtype dtype, const void* box_dev, void* comp
                      : run_pack<float>(g->d_run_base, g->d_run_start, g->lay.n_runs(), g->lay.n_active, box_dev,
                                        compact_dev, false, s);
   if (e != hipSuccess) return hip_fail(e, "pack");
+  return GPE_OK;
+}
+
+gpe_status gpe_pack_real(gpe_grid g, gpe_dtype dtype, const void* box_dev, void* compact_dev, void* stream) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(box_dev, "box");
+  if (st == GPE_OK) st = check_ptr(compact_dev, "compact");
+  if (st != GPE_OK) return st;
+  DeviceGuard dg(g->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = dtype == GPE_C128
+                     ? run_pack<double>(g->d_run_base, g->d_run_start, g->lay.n_runs(), g->lay.n_active, box_dev,
+                                        compact_dev, false, s, true)
+                     : run_pack<float>(g->d_run_base, g->d_run_start, g->lay.n_runs(), g->lay.n_active, box_dev,
+                                       compact_dev, false, s, true);
+  if (e != hipSuccess) return hip_fail(e, "pack_real");
   return GPE_OK;
 }
 

@@ -35,6 +35,7 @@ struct InstParams {
   int32_t pot_kind, n_knots;
   int32_t chunk_begin, chunk_count;
   int64_t site_begin, n_sites;
+  const void* field2;   // GPE_POT_LERP: the stage's end array (field is its start array)
   double knot_t[GPE_MAX_KNOTS];
   double knot_v[GPE_MAX_KNOTS];
 };
@@ -145,10 +146,17 @@ template <typename R> hipError_t run_seed_lambda(const Plan& p, const LaunchConf
                                                  void* lam, hipStream_t s);
 template <typename R> hipError_t run_field_range(const Plan& p, const LaunchConfig& cfg, const void* field,
                                                  hipStream_t s);
+// real = true: one R per element (potential fields) instead of a complex pair
 template <typename R> hipError_t run_pack(const int64_t* run_base, const int32_t* run_start, int64_t nruns,
                                           int64_t n_active, const void* src, void* dst, bool to_box,
-                                          hipStream_t s);
+                                          hipStream_t s, bool real = false);
 template <typename R> hipError_t run_fill_zero(void* dst, int64_t n_complex, hipStream_t s);
+// box mask of min(va, vb) < cutoff (vb may be null), n box points
+template <typename R> hipError_t run_threshold(const void* va, const void* vb, int64_t n, double cutoff,
+                                               uint8_t* mask, hipStream_t s);
+// destination site i <- src[iv_src[q] + i - iv_dst[q]] for its interval q, or 0 when iv_src[q] < 0
+template <typename R> hipError_t run_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv,
+                                           int64_t n_dst, const void* src, void* dst, hipStream_t s);
 
 // finalize kinds
 enum FinalKind { FIN_NORM_SCALE = 0, FIN_OBS = 1, FIN_OVERLAP = 2, FIN_LOSS = 3, FIN_RANGE = 4 };

@@ -23,6 +23,7 @@
 // bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "engine.hpp"
@@ -129,12 +130,28 @@ __device__ __forceinline__ double delta_at(const InstParams& ip, double t) {
   return ip.knot_v[k] + (ip.knot_v[k + 1] - ip.knot_v[k]) * (t - ip.knot_t[k]) / (ip.knot_t[k + 1] - ip.knot_t[k]);
 }
 
+// fraction of the way through a stage [knot_t[0], knot_t[1]], clamped to [0, 1]
+__device__ __forceinline__ double stage_lambda(const InstParams& ip, double t) {
+  const double l = (t - ip.knot_t[0]) / (ip.knot_t[1] - ip.knot_t[0]);
+  return l < 0.0 ? 0.0 : (l > 1.0 ? 1.0 : l);
+}
+
+// the time parameter of a potential kind: Delta(t) for RF_RAMP, the stage
+// fraction for LERP, unused for STATIC
+__device__ __forceinline__ double pot_param(const InstParams& ip, double t) {
+  if (ip.pot_kind == GPE_POT_RF_RAMP) return delta_at(ip, t);
+  if (ip.pot_kind == GPE_POT_LERP) return stage_lambda(ip, t);
+  return 0.0;
+}
+
+// V at a site: u = field, u2 = second field (LERP only), p = pot_param
 template <typename R>
-__device__ __forceinline__ R potential(int kind, R u, R delta, R omega2) {
+__device__ __forceinline__ R potential(int kind, R u, R u2, R p, R omega2) {
   if (kind == GPE_POT_RF_RAMP) {
-    const R d = u - delta;
+    const R d = u - p;
     return sqrt(d * d + omega2);
   }
+  if (kind == GPE_POT_LERP) return (R(1) - p) * u + p * u2;
   return u;
 }
 
@@ -254,7 +271,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const R omega2 = (R)(ip.omega * ip.omega);
   const int64_t step = a.step >= 0 ? a.step : *pl.step;
   const double tstage = ip.t0 + ((double)step + a.c_stage) * ip.dt;
-  const R delta = (kind == GPE_POT_RF_RAMP) ? (R)delta_at(ip, tstage) : R(0);
+  const R delta = (R)pot_param(ip, tstage);
+  const R* const field2 = reinterpret_cast<const R*>(ip.field2);
   R scale = R(1);
   if (OP == OP_ITP1 || (OP == OP_OBS && a.use_scale)) scale = (R)pl.out[ch.inst].scale;
   const R hg = g * dt * R(0.5);
@@ -323,7 +341,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // skip their stores.
   const int last = ch.site_begin + ch.count - 1;
   C ra[SPT], rb[SPT], rc[SPT], rl[SPT];
-  R rf[SPT], rp[SPT];
+  R rf[SPT], rf2[SPT], rp[SPT];
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int sc = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
@@ -332,6 +350,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     if constexpr (NEED_C) rc[m] = at1(a.c, sc);
     if constexpr (NEED_L) rl[m] = at1((const C*)a.out2, sc);
     if constexpr (NEED_F) rf[m] = at1(a.field, sc);
+    if constexpr (NEED_F) rf2[m] = (kind == GPE_POT_LERP) ? at1(field2, sc) : R(0);
     if constexpr (NEED_P) rp[m] = at1(a.prop, sc);
   }
   // OP_RKG: weighted sum of the earlier stage states at the lane's sites
@@ -447,7 +466,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
           put(Yout, s, w);
           acc[0] += (double)w * (double)w;
         } else {
-          const R V = potential<R>(kind, rf[m], delta, omega2);
+          const R V = potential<R>(kind, rf[m], rf2[m], delta, omega2);
           const double d = (double)yc * (double)yc;
           acc[0] += d;
           acc[1] += (double)yc * (double)lt;
@@ -470,14 +489,14 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         put(a.out, s, cmk<R>(wr, wi));
         acc[0] += (double)wr * (double)wr + (double)wi * (double)wi;
       } else if constexpr (OP == OP_OBS) {
-        const R V = potential<R>(kind, rf[m], delta, omega2);
+        const R V = potential<R>(kind, rf[m], rf2[m], delta, omega2);
         const double d = (double)yc.x * (double)yc.x + (double)yc.y * (double)yc.y;
         acc[0] += d;
         acc[1] += (double)yc.x * (double)lr + (double)yc.y * (double)li;
         acc[2] += (double)V * d;
         acc[3] += d * d;
       } else if constexpr (RK) {
-        const R V = potential<R>(kind, rf[m], delta, omega2);
+        const R V = potential<R>(kind, rf[m], rf2[m], delta, omega2);
         const R dens = yc.x * yc.x + yc.y * yc.y;
         const R w = V + g * dens;
         const R hr = lr + w * yc.x, hi = li + w * yc.y;   // H y
@@ -522,7 +541,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         const R tur = fx * lr, tui = fx * li;
         const C Y = ra[m];
         const R u0 = rf[m];
-        const R V = potential<R>(kind, u0, delta, omega2);
+        const R V = potential<R>(kind, u0, R(0), delta, omega2);
         const R dVd = dpot_ddelta<R>(kind, u0, delta, omega2);
         const R d2 = Y.x * Y.x + Y.y * Y.y;
         const R w = V + R(2) * g * d2;
@@ -812,7 +831,8 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   const int kind = ip.pot_kind;
   const R omega2 = (R)(ip.omega * ip.omega);
   const double t = ip.t0 + (double)(*pl.step) * ip.dt;
-  const R delta = (kind == GPE_POT_RF_RAMP) ? (R)delta_at(ip, t) : R(0);
+  const R delta = (R)pot_param(ip, t);
+  const R* const field2 = reinterpret_cast<const R*>(ip.field2);
   double acc[NR];
   if (OP == PT_RANGE) {
     acc[0] = 1e300;
@@ -831,7 +851,7 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   for (int l = threadIdx.x; l < ch.count; l += 256) {
     const int64_t s = (int64_t)ch.site_begin + l;
     if constexpr (OP == PT_PROP) {
-      const R V = potential<R>(kind, a.field[s], delta, omega2);
+      const R V = potential<R>(kind, a.field[s], kind == GPE_POT_LERP ? field2[s] : R(0), delta, omega2);
       a.rout[s] = exp(-V * (R)ip.dt * R(0.5));
     } else if constexpr (OP == PT_SCALE) {
       const C v = a.out[s];
@@ -1100,9 +1120,9 @@ hipError_t run_tick(int64_t* step, int64_t delta, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // box <-> compact
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename E>
 __global__ void k_pack(const int64_t* run_base, const int32_t* run_start, int64_t nruns, int64_t n,
-                       const typename CT<R>::T* src, typename CT<R>::T* dst, int to_box) {
+                       const E* src, E* dst, int to_box) {
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
     int64_t lo = 0, hi = nruns - 1;
     while (lo < hi) {
@@ -1117,13 +1137,73 @@ __global__ void k_pack(const int64_t* run_base, const int32_t* run_start, int64_
 
 template <typename R>
 hipError_t run_pack(const int64_t* run_base, const int32_t* run_start, int64_t nruns, int64_t n_active,
-                    const void* src, void* dst, bool to_box, hipStream_t s) {
+                    const void* src, void* dst, bool to_box, hipStream_t s, bool real) {
   using C = typename CT<R>::T;
   int64_t blocks = (n_active + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   timing_before(FAM_POINTWISE, s);
-  hipLaunchKernelGGL((k_pack<R>), dim3((unsigned)blocks), dim3(256), 0, s, run_base, run_start, nruns, n_active,
-                     (const C*)src, (C*)dst, to_box ? 1 : 0);
+  if (real)
+    hipLaunchKernelGGL((k_pack<R>), dim3((unsigned)blocks), dim3(256), 0, s, run_base, run_start, nruns, n_active,
+                       (const R*)src, (R*)dst, to_box ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_pack<C>), dim3((unsigned)blocks), dim3(256), 0, s, run_base, run_start, nruns, n_active,
+                       (const C*)src, (C*)dst, to_box ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  timing_after(FAM_POINTWISE, s);
+  return e;
+}
+
+// Post-selection (Sec. II.A, repeated per ramp stage in Sec. V): mask[x] =
+// min(Va[x], Vb[x]) < cutoff over the whole box (Vb may be null).
+template <typename R>
+__global__ void k_threshold(const R* va, const R* vb, int64_t n, R cutoff, uint8_t* mask) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    R v = va[i];
+    if (vb) {
+      const R w = vb[i];
+      v = w < v ? w : v;
+    }
+    mask[i] = (v < cutoff) ? 1 : 0;
+  }
+}
+
+template <typename R>
+hipError_t run_threshold(const void* va, const void* vb, int64_t n, double cutoff, uint8_t* mask, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_threshold<R>), dim3((unsigned)blocks), dim3(256), 0, s, (const R*)va, (const R*)vb, n,
+                     (R)cutoff, mask);
+  return hipGetLastError();
+}
+
+// Carry psi between two compact layouts of one box: the destination array is
+// cut into intervals (iv_dst[q] = first destination site, sorted, iv_dst[0]
+// = 0), each copied from consecutive source sites starting at iv_src[q] or
+// zero-filled when iv_src[q] < 0.  One lane per destination site finds its
+// interval by binary search.
+template <typename R>
+__global__ void k_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv, int64_t n_dst,
+                        const typename CT<R>::T* src, typename CT<R>::T* dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_dst; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = n_iv - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (iv_dst[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int64_t o = iv_src[lo];
+    dst[i] = o >= 0 ? src[o + (i - iv_dst[lo])] : cmk<R>(R(0), R(0));
+  }
+}
+
+template <typename R>
+hipError_t run_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv, int64_t n_dst, const void* src,
+                     void* dst, hipStream_t s) {
+  using C = typename CT<R>::T;
+  if (n_dst <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n_dst + 255) / 256, 65536);
+  timing_before(FAM_POINTWISE, s);
+  hipLaunchKernelGGL((k_remap<R>), dim3((unsigned)blocks), dim3(256), 0, s, iv_dst, iv_src, n_iv, n_dst,
+                     (const C*)src, (C*)dst);
   hipError_t e = hipGetLastError();
   timing_after(FAM_POINTWISE, s);
   return e;
@@ -1169,8 +1249,11 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
   template hipError_t run_seed_lambda<R>(const Plan&, const LaunchConfig&, const void*, void*, hipStream_t); \
   template hipError_t run_field_range<R>(const Plan&, const LaunchConfig&, const void*, hipStream_t);        \
   template hipError_t run_pack<R>(const int64_t*, const int32_t*, int64_t, int64_t, const void*, void*, bool, \
-                                  hipStream_t);                                                              \
-  template hipError_t run_fill_zero<R>(void*, int64_t, hipStream_t);
+                                  hipStream_t, bool);                                                        \
+  template hipError_t run_fill_zero<R>(void*, int64_t, hipStream_t);                                         \
+  template hipError_t run_threshold<R>(const void*, const void*, int64_t, double, uint8_t*, hipStream_t);     \
+  template hipError_t run_remap<R>(const int64_t*, const int64_t*, int64_t, int64_t, const void*, void*,      \
+                                   hipStream_t);
 
 GPE_INST(double)
 GPE_INST(float)

@@ -247,3 +247,35 @@ def small_rf_ramp(n: int = 32, half_width: float = 6.4, steps: int = 40, g: floa
     kd = np.linspace(d0, d1, n_knots) + rng.uniform(-1.0, 1.0, n_knots)
     return Workload(f"rf ramp {n}^3", box, runs, U, "rf", omega=omega,
                     knot_t=np.linspace(0.0, T, n_knots), knot_delta=kd, g=g, dt=dt, steps=steps, psi0=psi)
+
+
+@dataclass
+class StagedRamp:
+    """Inputs of a staged ramp (Sec. V): stage potentials on the whole box,
+    their chemical potentials, and a start state on the whole box."""
+    name: str
+    box: Box
+    fields: list            # V_0 .. V_S, each a box array (n0, n1, n2)
+    mus: list               # mu_0 .. mu_S
+    g: float
+    dt: float
+    steps_per_stage: int
+    psi0_box: np.ndarray    # complex box array
+
+
+def staged_rf_shells(n: int = 24, half_width: float = 6.0, n_stages: int = 3, steps_per_stage: int = 12,
+                     g: float = 60.0, seed: int = 7) -> StagedRamp:
+    """A small hollowing ramp given as stage arrays: RF-dressed shells
+    sqrt((U - Delta_i)^2 + Omega^2), U = (x^2 + y^2 + 4 z^2)/2, with Delta_i
+    stepped from 2 to 9; stage chemical potentials grow slowly with i."""
+    box = Box.centred(n, half_width)
+    ax = [box.axis(d) for d in range(3)]
+    x, y, z = np.meshgrid(ax[0], ax[1], ax[2], indexing="ij")
+    U = 0.5 * (x * x + y * y + 4.0 * z * z)
+    omega = 1.5
+    deltas = np.linspace(2.0, 9.0, n_stages + 1)
+    fields = [np.sqrt((U - d) ** 2 + omega ** 2) for d in deltas]
+    mus = [2.5 + 0.2 * i for i in range(n_stages + 1)]
+    rng = np.random.default_rng(seed)
+    psi = tf_trial(fields[0].ravel(), mus[0], g, box.dV, rng, 1e-3).reshape(box.n)
+    return StagedRamp(f"staged rf shells {n}^3", box, fields, mus, g, 2e-3, steps_per_stage, psi)
