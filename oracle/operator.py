@@ -15,6 +15,11 @@ Two independent constructions are provided and must agree:
                      (searchsorted on the +-1, +-n2, +-n1*n2 shifts);
                      memory ~ number of active sites.
 
+The 19-point higher-order compact (HOC) stencil of App. B eq. (B2) adds to
+the Kronecker sum the mixed terms (1/12)(d_a^2 + d_b^2) delta_a^2 (x) delta_b^2
+for each pair of axes (a, b); the same two constructions are provided for it
+(`kinetic_kron_19`, `kinetic_direct_19`).
+
 Sites are ordered by box linear index (i*n1 + j)*n2 + k (z fastest).
 """
 from __future__ import annotations
@@ -67,6 +72,82 @@ def kinetic_direct(n, h, lin: np.ndarray) -> sp.csr_matrix:
             rows.append(np.nonzero(hit)[0])
             cols.append(pos_c[hit])
             vals.append(np.full(int(hit.sum()), wd))
+    L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(m, m))
+    L.sum_duplicates()
+    return (-0.5 * L).tocsr()
+
+
+def laplacian_kron_19(n, h) -> sp.csr_matrix:
+    """Full-box 19-point HOC Laplacian, eq. (B2), from Kronecker products."""
+    D = [second_difference_1d(n[d], h[d]) for d in range(3)]
+    I = [sp.identity(n[d], format="csr") for d in range(3)]
+
+    def k3(a, b, c):
+        return sp.kron(sp.kron(a, b), c)
+
+    L = laplacian_kron(n, h)
+    h2 = [h[d] * h[d] for d in range(3)]
+    L = L + (1.0 / 12.0) * ((h2[0] + h2[1]) * k3(D[0], D[1], I[2]) + (h2[0] + h2[2]) * k3(D[0], I[1], D[2])
+                            + (h2[1] + h2[2]) * k3(I[0], D[1], D[2]))
+    return L.tocsr()
+
+
+def kinetic_kron_19(n, h, lin: np.ndarray) -> sp.csr_matrix:
+    """T~ from the 19-point stencil with the rows and columns outside the ROI removed."""
+    L = laplacian_kron_19(n, h)
+    lin = np.asarray(lin, dtype=np.int64)
+    return (-0.5 * L[lin][:, lin]).tocsr()
+
+
+def stencil_19_weights(h):
+    """Weights of eq. (B2) by neighbour offset (di, dj, dk): the 1D second
+    differences contribute 1/d^2 at the faces and -2/d^2 at the centre; each
+    mixed term e_ab = (d_a^2 + d_b^2) / (12 d_a^2 d_b^2) times
+    [1, -2, 1] (x) [1, -2, 1] contributes e_ab at the four edge points of the
+    (a, b) plane, -2 e_ab at the four faces in that plane and 4 e_ab at the
+    centre."""
+    h2 = [h[d] * h[d] for d in range(3)]
+    e = {}
+    for a in range(3):
+        for b in range(a + 1, 3):
+            e[(a, b)] = (h2[a] + h2[b]) / (12.0 * h2[a] * h2[b])
+    w = {}
+    w[(0, 0, 0)] = sum(-2.0 / h2[d] for d in range(3)) + 4.0 * sum(e.values())
+    for d in range(3):
+        face = 1.0 / h2[d] - 2.0 * sum(v for (a, b), v in e.items() if d in (a, b))
+        for sgn in (-1, 1):
+            off = [0, 0, 0]
+            off[d] = sgn
+            w[tuple(off)] = face
+    for (a, b), v in e.items():
+        for sa in (-1, 1):
+            for sb in (-1, 1):
+                off = [0, 0, 0]
+                off[a], off[b] = sa, sb
+                w[tuple(off)] = v
+    return w
+
+
+def kinetic_direct_19(n, h, lin: np.ndarray) -> sp.csr_matrix:
+    """The 19-point operator assembled directly on the active set."""
+    lin = np.asarray(lin, dtype=np.int64)
+    m = lin.size
+    n0, n1, n2 = (int(v) for v in n)
+    coords = (lin // (n1 * n2), (lin // n2) % n1, lin % n2)
+    ext = (n0, n1, n2)
+    strides = (n1 * n2, n2, 1)
+    rows, cols, vals = [], [], []
+    for off, wv in stencil_19_weights(h).items():
+        inside = np.ones(m, bool)
+        for d in range(3):
+            inside &= (coords[d] + off[d] >= 0) & (coords[d] + off[d] < ext[d])
+        target = lin + sum(off[d] * strides[d] for d in range(3))
+        pos = np.searchsorted(lin, target)
+        pos_c = np.minimum(pos, m - 1)
+        hit = inside & (pos < m) & (lin[pos_c] == target)
+        rows.append(np.nonzero(hit)[0])
+        cols.append(pos_c[hit])
+        vals.append(np.full(int(hit.sum()), wv))
     L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(m, m))
     L.sum_duplicates()
     return (-0.5 * L).tocsr()

@@ -88,3 +88,81 @@ def test_c1_geometry_counts():
     i, j, k = site_ijk(w.runs)
     lin = (i * 64 + j) * 64 + k
     assert np.all(np.diff(lin) > 0)
+
+
+# ---- 19-point HOC stencil, App. B eq. (B2) ----------------------------------
+
+def test_19pt_constructions_agree_on_a_random_mask():
+    from oracle import operator as op
+    rng = np.random.default_rng(19)
+    n, h = (7, 6, 8), (0.3, 0.45, 0.25)
+    mask = rng.uniform(size=n) < 0.55
+    lin = np.flatnonzero(mask.ravel())
+    A = op.kinetic_kron_19(n, h, lin).toarray()
+    B = op.kinetic_direct_19(n, h, lin).toarray()
+    assert np.max(np.abs(A - B)) <= 1e-12 * np.max(np.abs(A))
+    assert np.max(np.abs(A - A.T)) == 0.0                      # restriction keeps the symmetry
+
+
+def test_19pt_full_box_spectrum_closed_form():
+    """On the full box the Dirichlet sine modes diagonalise every Kronecker
+    factor, so the eigenvalues of eq. (B2) are sum_d mu_d + (1/12) sum_{a<b}
+    (h_a^2 + h_b^2) mu_a mu_b with mu_d = -(4/h_d^2) sin^2(k_d pi / (2(n_d + 1)))."""
+    from oracle import operator as op
+    n, h = (5, 4, 6), (0.5, 0.35, 0.6)
+    lin = np.arange(n[0] * n[1] * n[2])
+    T = op.kinetic_kron_19(n, h, lin).toarray()
+    mu = [-(4.0 / h[d] ** 2) * np.sin(np.arange(1, n[d] + 1) * np.pi / (2 * (n[d] + 1))) ** 2 for d in range(3)]
+    a, b, c = np.meshgrid(mu[0], mu[1], mu[2], indexing="ij")
+    h2 = [v * v for v in h]
+    lam = a + b + c + ((h2[0] + h2[1]) * a * b + (h2[0] + h2[2]) * a * c + (h2[1] + h2[2]) * b * c) / 12.0
+    want = np.sort((-0.5 * lam).ravel())
+    got = np.linalg.eigvalsh(T)
+    assert np.max(np.abs(np.sort(got) - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+def test_19pt_isotropic_weights_are_the_classical_stencil():
+    """For equal spacings eq. (B2) is the classical 19-point Laplacian
+    (1/(6 h^2)) [-24 at the centre, 2 at the faces, 1 at the edges]."""
+    from oracle import operator as op
+    h = 0.37
+    w = op.stencil_19_weights((h, h, h))
+    assert len(w) == 19
+    for off, v in w.items():
+        nz = sum(1 for x in off if x != 0)
+        want = {0: -24.0, 1: 2.0, 2: 1.0}[nz] / (6 * h * h)
+        assert abs(v - want) <= 1e-13 * abs(want)
+
+
+@pytest.mark.parametrize("aniso", [False, True])
+def test_19pt_truncation_error_is_fourth_order_beyond_the_hoc_term(aniso):
+    """Taylor expansion: the 19-point operator equals Lap u + (1/12)[sum_d h_d^2
+    d_d^4 u + sum_{a<b} (h_a^2 + h_b^2) d_a^2 d_b^2 u] + O(h^4).  Checked on a
+    Gaussian (closed-form derivatives) at interior points: halving h cuts the
+    remainder by ~16, which fails for a wrong 1/12 or a wrong sign."""
+    from oracle import operator as op
+
+    def remainder(hs):
+        L = 6.0
+        n = tuple(int(round(2 * L / hd)) for hd in hs)
+        ax = [-L + (np.arange(n[d]) + 0.5) * hs[d] for d in range(3)]
+        x, y, z = np.meshgrid(*ax, indexing="ij")
+        G = np.exp(-(x * x + y * y + z * z) / 2)
+        lin = np.arange(G.size)
+        Lu = (-2.0 * op.kinetic_direct_19(n, hs, lin) @ G.ravel()).reshape(n)
+        c = [x, y, z]
+        d2 = [(v * v - 1) for v in c]
+        d4 = [(v ** 4 - 6 * v * v + 3) for v in c]
+        lap = (d2[0] + d2[1] + d2[2]) * G
+        hoc = sum(hs[d] ** 2 * d4[d] for d in range(3))
+        for a in range(3):
+            for b in range(a + 1, 3):
+                hoc = hoc + (hs[a] ** 2 + hs[b] ** 2) * d2[a] * d2[b]
+        ref = lap + hoc * G / 12.0
+        inner = (np.abs(x) < 2.5) & (np.abs(y) < 2.5) & (np.abs(z) < 2.5)
+        return np.max(np.abs(Lu - ref)[inner])
+
+    base = (0.4, 0.5, 0.3) if aniso else (0.4, 0.4, 0.4)
+    e1 = remainder(base)
+    e2 = remainder(tuple(v / 2 for v in base))
+    assert 12.0 < e1 / e2 < 20.0
