@@ -231,6 +231,23 @@ class Grid:
         check(L.load().gpe_grid_runs(self._h, out.ctypes.data))
         return out
 
+    def set_stencil(self, points: int) -> None:
+        """7-point (default) or 19-point HOC Laplacian (App. B eq. (B2))."""
+        check(L.load().gpe_grid_set_stencil(self._h, int(points)))
+
+    def get_stencil(self) -> int:
+        c = C.c_int32()
+        check(L.load().gpe_grid_get_stencil(self._h, C.byref(c)))
+        return c.value
+
+    def hoc_segments(self) -> np.ndarray:
+        """The 19-point segment table: rows {start, length, flags, off[16], 0}."""
+        n = C.c_int64()
+        check(L.load().gpe_grid_hoc_segments(self._h, C.byref(n), None))
+        out = np.zeros((n.value, 20), np.int32)
+        check(L.load().gpe_grid_hoc_segments(self._h, C.byref(n), out.ctypes.data))
+        return out
+
     # ---- work buffers ---------------------------------------------------
     def work_bytes(self, dtype: int, mode: int, nsteps: int = 0, ckpt_every: int = 0) -> int:
         b = C.c_size_t()

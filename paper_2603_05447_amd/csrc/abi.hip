@@ -163,6 +163,11 @@ struct Problem {
   std::vector<double> inst_h;          // 3 per instance
   std::vector<SegHead> heads;          // host copy (n_segs + 1)
   std::vector<int64_t> plane_begin;    // first compact site of every non-empty x-plane of every instance
+  // 19-point stencil tables (single grids only, built by enable_hoc)
+  int stencil = 7;
+  std::vector<SegHead> hoc_heads;      // host copy (n_hoc_segs + 1)
+  SegHead* d_hoc_heads = nullptr;
+  SegHoc* d_hoc_nbs = nullptr;
   SegHead* d_heads = nullptr;
   SegNb* d_nbs = nullptr;
   std::map<int, ChunkSet> chunksets;
@@ -179,10 +184,10 @@ struct Problem {
   // captured forward-step graphs, keyed by buffer pointers
   struct GraphKey {
     const void *psi, *field, *work;
-    int dtype, config, scheme, integrator;
+    int dtype, config, scheme, integrator, stencil;
     bool operator<(const GraphKey& o) const {
-      return std::tie(psi, field, work, dtype, config, scheme, integrator) <
-             std::tie(o.psi, o.field, o.work, o.dtype, o.config, o.scheme, o.integrator);
+      return std::tie(psi, field, work, dtype, config, scheme, integrator, stencil) <
+             std::tie(o.psi, o.field, o.work, o.dtype, o.config, o.scheme, o.integrator, o.stencil);
     }
   };
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -200,6 +205,10 @@ struct Problem {
     chunksets.clear();
     (void)hipFree(d_heads);
     (void)hipFree(d_nbs);
+    (void)hipFree(d_hoc_heads);
+    (void)hipFree(d_hoc_nbs);
+    d_hoc_heads = nullptr;
+    d_hoc_nbs = nullptr;
     (void)hipFree(d_inst);
     (void)hipFree(d_out);
     (void)hipFree(d_step);
@@ -290,13 +299,50 @@ struct Problem {
     return GPE_OK;
   }
 
-  // chunk table for a chunk capacity (built on first use)
-  gpe_status chunks_for(int capacity, ChunkSet** out) {
-    auto it = chunksets.find(capacity);
+  // Upload the 19-point segment tables of a single grid's layout (built on
+  // the host on first use) and make sure the partial-sum scratch covers the
+  // larger chunk count.
+  gpe_status enable_hoc(Layout& lay) {
+    if (n_inst != 1) return fail(GPE_ERR_STATE, "the 19-point stencil is available for single grids only");
+    if (d_hoc_heads) return GPE_OK;
+    build_hoc_segments(lay);
+    const int64_t nh = (int64_t)lay.hoc_nbs.size();
+    hoc_heads = lay.hoc_heads;
+    DeviceGuard g(device);
+    if (dalloc(&d_hoc_heads, nh + 1) != hipSuccess || dalloc(&d_hoc_nbs, nh) != hipSuccess) {
+      (void)hipFree(d_hoc_heads);
+      (void)hipFree(d_hoc_nbs);
+      d_hoc_heads = nullptr;
+      d_hoc_nbs = nullptr;
+      return fail(GPE_ERR_ALLOC, "19-point segment table allocation failed");
+    }
+    hipError_t e = hipMemcpy(d_hoc_heads, hoc_heads.data(), sizeof(SegHead) * (nh + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_hoc_nbs, lay.hoc_nbs.data(), sizeof(SegHoc) * nh, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "19-point segment table upload");
+    const int64_t need = (lay.n_active + 255) / 256 + nh / MAX_CHUNK_SEGS + 1;
+    if (need > max_chunks) {
+      for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+      graphs.clear();
+      (void)hipFree(d_partials);
+      (void)hipFree(d_knot_acc);
+      d_partials = d_knot_acc = nullptr;
+      max_chunks = need;
+      if (dalloc(&d_partials, max_chunks * NPART) != hipSuccess ||
+          dalloc(&d_knot_acc, max_chunks * GPE_MAX_KNOTS) != hipSuccess)
+        return fail(GPE_ERR_ALLOC, "partial-sum scratch allocation failed");
+    }
+    return GPE_OK;
+  }
+
+  // chunk table for a chunk capacity and stencil (built on first use)
+  gpe_status chunks_for(int capacity, ChunkSet** out, bool hoc = false) {
+    const int key = capacity * 2 + (hoc ? 1 : 0);
+    auto it = chunksets.find(key);
     if (it != chunksets.end()) {
       *out = &it->second;
       return GPE_OK;
     }
+    const std::vector<SegHead>& heads = hoc ? hoc_heads : this->heads;
     ChunkSet cs;
     cs.capacity = capacity;
     std::vector<Chunk> tab;
@@ -338,7 +384,7 @@ struct Problem {
       (void)hipFree(cs.d_chunks);
       return hip_fail(e, "chunk table upload");
     }
-    auto res = chunksets.emplace(capacity, std::move(cs));
+    auto res = chunksets.emplace(key, std::move(cs));
     *out = &res.first->second;
     return GPE_OK;
   }
@@ -391,8 +437,11 @@ struct Problem {
 
   Plan plan(const ChunkSet& cs, const LaunchConfig& cfg) const {
     Plan p;
-    p.heads = d_heads;
+    const bool hoc = stencil == 19;
+    p.heads = hoc ? d_hoc_heads : d_heads;
     p.nbs = d_nbs;
+    p.hoc = hoc ? 1 : 0;
+    p.hocnb = d_hoc_nbs;
     p.chunks = cs.d_chunks;
     p.inst = d_inst;
     p.partials = d_partials;
@@ -424,6 +473,18 @@ struct Problem {
       h_inst[i].cy = -0.5 / (h[1] * h[1]);
       h_inst[i].cz = -0.5 / (h[2] * h[2]);
       h_inst[i].cd = 1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2]);
+      // eq. (B2): Lap_19 = Lap_7 + sum_{a<b} (h_a^2 + h_b^2)/12 delta_a^2 delta_b^2, as weights of -Lap/2
+      const double h2[3] = {h[0] * h[0], h[1] * h[1], h[2] * h[2]};
+      const double exy = (h2[0] + h2[1]) / (12.0 * h2[0] * h2[1]);
+      const double exz = (h2[0] + h2[2]) / (12.0 * h2[0] * h2[2]);
+      const double eyz = (h2[1] + h2[2]) / (12.0 * h2[1] * h2[2]);
+      h_inst[i].qx = -0.5 * (1.0 / h2[0] - 2.0 * exy - 2.0 * exz);
+      h_inst[i].qy = -0.5 * (1.0 / h2[1] - 2.0 * exy - 2.0 * eyz);
+      h_inst[i].qz = -0.5 * (1.0 / h2[2] - 2.0 * exz - 2.0 * eyz);
+      h_inst[i].qd = -0.5 * (-2.0 / h2[0] - 2.0 / h2[1] - 2.0 / h2[2] + 4.0 * (exy + exz + eyz));
+      h_inst[i].qxy = -0.5 * exy;
+      h_inst[i].qxz = -0.5 * exz;
+      h_inst[i].qyz = -0.5 * eyz;
       h_inst[i].dV = h[0] * h[1] * h[2];
     }
     HIP_TRY(hipMemcpyAsync(d_inst, h_inst, sizeof(InstParams) * n_inst, hipMemcpyHostToDevice, s));
@@ -632,11 +693,24 @@ InstParams make_params(const gpe_potential* pot, const gpe_params* prm, double t
   return ip;
 }
 
+// Gershgorin bound of the spectrum of T~: |centre| + sum |off-diagonal weights|
 double kinetic_bound(const Problem& P) {
   double m = 0.0;
   for (int i = 0; i < P.n_inst; ++i) {
     const double* h = &P.inst_h[3 * i];
-    m = std::max(m, 2.0 * (1.0 / (h[0] * h[0]) + 1.0 / (h[1] * h[1]) + 1.0 / (h[2] * h[2])));
+    const double h2[3] = {h[0] * h[0], h[1] * h[1], h[2] * h[2]};
+    if (P.stencil == 19) {
+      const double exy = (h2[0] + h2[1]) / (12.0 * h2[0] * h2[1]);
+      const double exz = (h2[0] + h2[2]) / (12.0 * h2[0] * h2[2]);
+      const double eyz = (h2[1] + h2[2]) / (12.0 * h2[1] * h2[2]);
+      const double fx = std::fabs(1.0 / h2[0] - 2.0 * exy - 2.0 * exz);
+      const double fy = std::fabs(1.0 / h2[1] - 2.0 * exy - 2.0 * eyz);
+      const double fz = std::fabs(1.0 / h2[2] - 2.0 * exz - 2.0 * eyz);
+      const double c = std::fabs(-2.0 / h2[0] - 2.0 / h2[1] - 2.0 / h2[2] + 4.0 * (exy + exz + eyz));
+      m = std::max(m, 0.5 * (c + 2.0 * (fx + fy + fz) + 4.0 * (exy + exz + eyz)));
+    } else {
+      m = std::max(m, 2.0 * (1.0 / h2[0] + 1.0 / h2[1] + 1.0 / h2[2]));
+    }
   }
   return m;
 }
@@ -655,13 +729,20 @@ struct Ctx {
 gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
   c.P = P;
   c.cfg = config_get(config);
+  const bool hoc = P->stencil == 19;
   if ((uint64_t)P->total * 16u >= (uint64_t(1) << 32)) {
+    if (hoc) return fail(GPE_ERR_ARG, "the 19-point stencil needs arrays below 4 GiB");
     // 64-bit addressing is compiled for one shape only
     c.cfg.block = 256;
     c.cfg.spt = 2;
     c.cfg.nt = 0;
   }
-  gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs);
+  if (hoc) {
+    // the 19-point kernels are compiled for 256 lanes x 1 site
+    c.cfg.block = 256;
+    c.cfg.spt = 1;
+  }
+  gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs, hoc);
   if (st != GPE_OK) return st;
   if (c.cfg.xcd == 4) {
     st = P->order_for(*c.cs);
@@ -817,7 +898,7 @@ template <typename R>
 static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* field, int integrator,
                              void* const* bufs, hipGraphExec_t* out) {
   Problem& P = *c.P;
-  Problem::GraphKey key{psi, field, bufs[0], dtype, P.config, c.cfg.scheme, integrator};
+  Problem::GraphKey key{psi, field, bufs[0], dtype, P.config, c.cfg.scheme, integrator, P.stencil};
   auto it = P.graphs.find(key);
   if (it != P.graphs.end()) {
     *out = it->second;
@@ -1204,6 +1285,43 @@ gpe_status gpe_remap(gpe_grid src, gpe_grid dst, gpe_dtype dtype, const void* ps
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d_iv);
   if (e != hipSuccess) return hip_fail(e, "remap");
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_set_stencil(gpe_grid g, int32_t points) {
+  if (!g) return fail(GPE_ERR_ARG, "grid is NULL");
+  if (points != 7 && points != 19) return fail(GPE_ERR_ARG, "stencil must have 7 or 19 points");
+  if (points == 19) build_hoc_segments(g->lay);
+  if (g->device < 0 || !g->prob) return GPE_OK;
+  if (points == 19) {
+    DeviceGuard dg(g->device);
+    gpe_status st = g->prob->enable_hoc(g->lay);
+    if (st != GPE_OK) return st;
+  }
+  g->prob->stencil = points;
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_get_stencil(gpe_grid g, int32_t* points) {
+  if (!g || !points) return fail(GPE_ERR_ARG, "grid or points is NULL");
+  *points = (g->prob ? g->prob->stencil : 7);
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_hoc_segments(gpe_grid g, int64_t* n_segments, int32_t* out_host) {
+  if (!g || !n_segments) return fail(GPE_ERR_ARG, "grid or n_segments is NULL");
+  build_hoc_segments(g->lay);
+  const int64_t n = (int64_t)g->lay.hoc_nbs.size();
+  *n_segments = n;
+  if (!out_host) return GPE_OK;
+  for (int64_t q = 0; q < n; ++q) {
+    int32_t* o = out_host + 20 * q;
+    o[0] = g->lay.hoc_heads[q].start;
+    o[1] = g->lay.hoc_heads[q + 1].start - g->lay.hoc_heads[q].start;
+    o[2] = g->lay.hoc_heads[q].flags;
+    for (int t = 0; t < HOC_TAPS; ++t) o[3 + t] = g->lay.hoc_nbs[q].off[t];
+    o[19] = 0;
+  }
   return GPE_OK;
 }
 

@@ -31,6 +31,9 @@ struct InstParams {
   // T~ y = cx (y[i-1] + y[i+1]) + cy (y[j-1] + y[j+1]) + cz (y[k-1] + y[k+1]) + cd y,
   // cx = -1/(2 hx^2), ..., cd = 1/hx^2 + 1/hy^2 + 1/hz^2   (App. B, eq. (B1), hbar = m = 1)
   double cx, cy, cz, cd;
+  // 19-point HOC stencil of App. B eq. (B2) as weights of T~ = -1/2 Lap:
+  // faces qx, qy, qz, centre qd, edges qxy (i+-1, j+-1), qxz, qyz
+  double qx, qy, qz, qd, qxy, qxz, qyz;
   double omega, norm_target;
   int32_t pot_kind, n_knots;
   int32_t chunk_begin, chunk_count;
@@ -68,6 +71,8 @@ struct Plan {
   int32_t pstride;        // stride between partial-sum components (>= n_chunks)
   int32_t off32;          // 1: every per-site array is below 4 GiB (32-bit byte offsets)
   int32_t max_seg;        // largest seg_count of any chunk (sizes the dynamic LDS)
+  int32_t hoc;            // 1: 19-point stencil; heads/chunks are the HOC segments
+  const SegHoc* hocnb;    // HOC lateral taps (hoc = 1)
 };
 
 // Compiled launch variants (workgroup size x sites per lane, chunk capacity

@@ -53,6 +53,57 @@ struct ColumnIndex {
   }
 };
 
+// Cut every run into stretches on which each tap (di, dj, dk) is absent or at
+// one constant compact offset, and call emit(head, offsets) per stretch.
+// For run q of column (i+di, j+dj) the tap of site k lies in q exactly when
+// k + dk is in [k0_q, k1_q), i.e. k in [k0_q - dk, k1_q - dk), at offset
+// (start_q - k0_q + dk) - (S - k0).
+template <typename Emit>
+void cut_runs(const Layout& L, const ColumnIndex& col, int ntaps, const int8_t (*taps)[3], Emit emit) {
+  struct Piece { int64_t a, b, off; };
+  std::vector<std::vector<Piece>> pieces(ntaps);
+  std::vector<int64_t> cuts;
+  std::vector<int32_t> off(ntaps);
+  for (int64_t r = 0; r < L.n_runs(); ++r) {
+    const int64_t i = L.run_i[r], j = L.run_j[r];
+    const int64_t k0 = L.run_k0[r], k1 = L.run_k1[r], S = L.run_start[r];
+    cuts.clear();
+    cuts.push_back(k0);
+    cuts.push_back(k1);
+    for (int d = 0; d < ntaps; ++d) {
+      pieces[d].clear();
+      const int64_t ii = i + taps[d][0], jj = j + taps[d][1], dk = taps[d][2];
+      if (ii < 0 || ii >= L.n[0] || jj < 0 || jj >= L.n[1]) continue;
+      int64_t b, e;
+      col.range(ii, jj, b, e);
+      for (int64_t q = b; q < e; ++q) {
+        const int64_t a = std::max(k0, L.run_k0[q] - dk);
+        const int64_t z = std::min(k1, L.run_k1[q] - dk);
+        if (a >= z) continue;
+        pieces[d].push_back({a, z, (L.run_start[q] - L.run_k0[q] + dk) - (S - k0)});
+        cuts.push_back(a);
+        cuts.push_back(z);
+      }
+    }
+    std::sort(cuts.begin(), cuts.end());
+    cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+      const int64_t a = cuts[c], z = cuts[c + 1];
+      SegHead hd;
+      hd.start = (int32_t)(S + (a - k0));
+      hd.flags = (a == k0 ? SEG_RUN_BEGIN : 0) | (z == k1 ? SEG_RUN_END : 0);
+      for (int d = 0; d < ntaps; ++d) {
+        off[d] = 0;
+        for (const Piece& p : pieces[d])
+          if (p.a <= a && z <= p.b) { off[d] = (int32_t)p.off; break; }
+      }
+      emit(hd, off.data());
+    }
+  }
+}
+
+const int8_t kFaceTap[4][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}};
+
 std::string build_segments(Layout& L) {
   const int64_t nr = L.n_runs();
   L.run_start.resize(nr);
@@ -68,60 +119,38 @@ std::string build_segments(Layout& L) {
 
   ColumnIndex col;
   col.build(L);
-  const int64_t di[4] = {-1, 1, 0, 0};
-  const int64_t dj[4] = {0, 0, -1, 1};
-
   L.heads.clear();
   L.nbs.clear();
   L.heads.reserve(nr * 2 + 1);
   L.nbs.reserve(nr * 2);
-
-  struct Piece { int64_t a, b, off; };
-  std::vector<Piece> pieces[4];
-  std::vector<int64_t> cuts;
-  for (int64_t r = 0; r < nr; ++r) {
-    const int64_t i = L.run_i[r], j = L.run_j[r];
-    const int64_t k0 = L.run_k0[r], k1 = L.run_k1[r], S = L.run_start[r];
-    cuts.clear();
-    cuts.push_back(k0);
-    cuts.push_back(k1);
-    for (int d = 0; d < 4; ++d) {
-      pieces[d].clear();
-      const int64_t ii = i + di[d], jj = j + dj[d];
-      if (ii < 0 || ii >= L.n[0] || jj < 0 || jj >= L.n[1]) continue;
-      int64_t b, e;
-      col.range(ii, jj, b, e);
-      for (int64_t q = b; q < e; ++q) {
-        const int64_t a = std::max(k0, L.run_k0[q]);
-        const int64_t z = std::min(k1, L.run_k1[q]);
-        if (a >= z) continue;
-        // site at height k: self = S + (k - k0), neighbour = S' + (k - k0')
-        const int64_t off = (L.run_start[q] - L.run_k0[q]) - (S - k0);
-        pieces[d].push_back({a, z, off});
-        cuts.push_back(a);
-        cuts.push_back(z);
-      }
-    }
-    std::sort(cuts.begin(), cuts.end());
-    cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
-    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
-      const int64_t a = cuts[c], z = cuts[c + 1];
-      SegHead hd;
-      hd.start = (int32_t)(S + (a - k0));
-      hd.flags = (a == k0 ? SEG_RUN_BEGIN : 0) | (z == k1 ? SEG_RUN_END : 0);
-      int64_t off[4] = {0, 0, 0, 0};
-      for (int d = 0; d < 4; ++d)
-        for (const Piece& p : pieces[d])
-          if (p.a <= a && z <= p.b) { off[d] = p.off; break; }
-      L.heads.push_back(hd);
-      L.nbs.push_back({(int32_t)off[0], (int32_t)off[1], (int32_t)off[2], (int32_t)off[3]});
-    }
-  }
+  cut_runs(L, col, 4, kFaceTap, [&](const SegHead& hd, const int32_t* off) {
+    L.heads.push_back(hd);
+    L.nbs.push_back({off[0], off[1], off[2], off[3]});
+  });
   L.heads.push_back({(int32_t)L.n_active, 0});
   return "";
 }
 
 }  // namespace
+
+const int8_t kHocTap[HOC_TAPS][3] = {{-1, 0, 0},  {1, 0, 0},   {0, -1, 0},  {0, 1, 0},   {-1, 0, -1}, {-1, 0, 1},
+                                     {1, 0, -1},  {1, 0, 1},   {0, -1, -1}, {0, -1, 1},  {0, 1, -1},  {0, 1, 1},
+                                     {-1, -1, 0}, {-1, 1, 0},  {1, -1, 0},  {1, 1, 0}};
+
+void build_hoc_segments(Layout& L) {
+  if (!L.hoc_heads.empty()) return;
+  ColumnIndex col;
+  col.build(L);
+  L.hoc_heads.reserve(L.heads.size() * 2);
+  L.hoc_nbs.reserve(L.nbs.size() * 2);
+  cut_runs(L, col, HOC_TAPS, kHocTap, [&](const SegHead& hd, const int32_t* off) {
+    L.hoc_heads.push_back(hd);
+    SegHoc s;
+    for (int d = 0; d < HOC_TAPS; ++d) s.off[d] = off[d];
+    L.hoc_nbs.push_back(s);
+  });
+  L.hoc_heads.push_back({(int32_t)L.n_active, 0});
+}
 
 std::string layout_from_runs(const int64_t n[3], int64_t nruns, const int64_t* runs, Layout& out) {
   std::string err = check_box(n);

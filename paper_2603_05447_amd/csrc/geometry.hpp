@@ -26,6 +26,20 @@ struct SegNb {        // constant lateral offsets (0 = neighbour absent)
   int32_t xm, xp, ym, yp;
 };
 
+// The 19-point HOC stencil (App. B eq. (B2)) needs, besides the k+-1
+// neighbours of the site's own run, sixteen lateral taps (di, dj, dk):
+//   0-3   (-1,0,0) (1,0,0) (0,-1,0) (0,1,0)        faces
+//   4-7   (-1,0,-1) (-1,0,1) (1,0,-1) (1,0,1)      xz edges
+//   8-11  (0,-1,-1) (0,-1,1) (0,1,-1) (0,1,1)      yz edges
+//   12-15 (-1,-1,0) (-1,1,0) (1,-1,0) (1,1,0)      xy edges
+// HOC segments are stretches of a run on which every tap is absent or at one
+// constant compact offset.
+constexpr int HOC_TAPS = 16;
+struct SegHoc {
+  int32_t off[HOC_TAPS];
+};
+extern const int8_t kHocTap[HOC_TAPS][3];
+
 struct Layout {
   int64_t n[3] = {0, 0, 0};
   double h[3] = {0, 0, 0};
@@ -36,9 +50,15 @@ struct Layout {
   // segments; heads has n_segments + 1 entries, the last = {n_active, 0}
   std::vector<SegHead> heads;
   std::vector<SegNb> nbs;
+  // HOC segments (built on demand by build_hoc_segments)
+  std::vector<SegHead> hoc_heads;
+  std::vector<SegHoc> hoc_nbs;
   int64_t n_runs() const { return (int64_t)run_i.size(); }
   int64_t n_segments() const { return (int64_t)nbs.size(); }
 };
+
+// Fill L.hoc_heads / L.hoc_nbs (no-op when already built).
+void build_hoc_segments(Layout& L);
 
 // Returns an empty string on success, else a description of the problem.
 std::string layout_from_mask(const int64_t n[3], const uint8_t* mask, Layout& out);

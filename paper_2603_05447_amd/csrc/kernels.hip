@@ -234,10 +234,13 @@ template <typename R> struct PassArgs {
 // REAL: the state is real (imaginary time from a real start, Sec. II.A), one
 // R per site instead of two; only the imaginary-time passes and the
 // observation pass exist in that form.
-template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT, bool REAL>
+// HOC: the 19-point stencil of App. B eq. (B2) instead of the 7-point one;
+// the segment descriptors then hold the sixteen lateral taps of SegHoc.
+template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT, bool REAL, bool HOC>
 __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
   using C = typename CT<R>::T;
   using S = typename std::conditional<REAL, R, C>::type;   // stencil state type
+  using D = typename std::conditional<HOC, SegHoc, SegNb>::type;   // lateral descriptor
   static_assert(!REAL || OP == OP_ITP1 || OP == OP_ITP2 || OP == OP_OBS, "real state: ITP and OBS only");
   constexpr int CH = BLOCK * SPT;
   constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
@@ -257,8 +260,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   S* const Yout = reinterpret_cast<S*>(a.out);
   // dynamic LDS: lateral offsets (max_seg) then segment heads (max_seg + 1)
   extern __shared__ __align__(16) unsigned char dyn_lds[];
-  SegNb* snb = reinterpret_cast<SegNb*>(dyn_lds);
-  SegHead* sh = reinterpret_cast<SegHead*>(dyn_lds + (size_t)pl.max_seg * sizeof(SegNb));
+  D* snb = reinterpret_cast<D*>(dyn_lds);
+  SegHead* sh = reinterpret_cast<SegHead*>(dyn_lds + (size_t)pl.max_seg * sizeof(D));
 
   const int cidx = pl.xcd_map == 4 ? pl.order[blockIdx.x] : chunk_index((int)blockIdx.x, (int)gridDim.x, pl.xcd_map);
   const Chunk ch = pl.chunks[cidx];
@@ -329,7 +332,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // Segment-table slots past the end re-load the last entry (same value to
   // the same LDS slot), so these loads are unconditional and issue first.
   const SegHead* hsrc = pl.heads + ch.seg_begin;
-  const SegNb* nsrc = pl.nbs + ch.seg_begin;
+  const D* nsrc;
+  if constexpr (HOC) nsrc = pl.hocnb + ch.seg_begin; else nsrc = pl.nbs + ch.seg_begin;
   const int t0 = threadIdx.x;
   // a chunk holds at most MAX_CHUNK_SEGS (< 256 <= BLOCK) segments, so one
   // slot per lane covers its table
@@ -401,6 +405,39 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   int js[SPT], tym[SPT], typ[SPT];
   S xm[SPT], xp[SPT], ym[SPT], yp[SPT];
   R wxm[SPT], wxp[SPT], wym[SPT], wyp[SPT];
+  // HOC: value, LDS slot (-1: loaded from global) and weight of every tap
+  constexpr int NT16 = HOC ? HOC_TAPS : 1;
+  S hv[SPT][NT16];
+  int hs[SPT][NT16];
+  R hw[SPT][NT16];
+  if constexpr (HOC) {
+    // tap weights by class: faces x, y; xz, yz, xy edges (App. B eq. (B2))
+    const R cls[5] = {(R)ip.qx, (R)ip.qy, (R)ip.qxz, (R)ip.qyz, (R)ip.qxy};
+#pragma unroll
+    for (int m = 0; m < SPT; ++m) {
+      const int s = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
+      int j = 0;
+      for (int st = top; st > 0; st >>= 1) {
+        const int cand = j + st;
+        if (cand < nseg && sh[cand].start <= s) j = cand;
+      }
+      js[m] = j;
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        const int o = snb[j].off[t];
+        // taps in the site's own x-plane (dj != 0, di == 0) are a column away
+        // and usually inside the staged window
+        constexpr int ytap_mask = (1 << 2) | (1 << 3) | (1 << 8) | (1 << 9) | (1 << 10) | (1 << 11);
+        const int win = s - wbase + o;
+        const bool lds = ((ytap_mask >> t) & 1) && win >= 0 && win < ch.count + 2;
+        hs[m][t] = lds ? win : -1;
+        hv[m][t] = zero;
+        if (!lds) hv[m][t] = load(s + o);
+        const int c = t < 2 ? 0 : (t < 4 ? 1 : (t < 8 ? 2 : (t < 12 ? 3 : 4)));
+        hw[m][t] = o ? cls[c] : R(0);
+      }
+    }
+  } else {
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int s = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
@@ -424,6 +461,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     wxp[m] = nb.xp ? cx : R(0);
     wym[m] = nb.ym ? cy : R(0);
     wyp[m] = nb.yp ? cy : R(0);
+  }
   }
   __builtin_amdgcn_sched_barrier(0);
 
@@ -451,13 +489,37 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       const int send = sh[js[m] + 1].start;
       const S yc = sy[l + 1];
       const S zm = sy[l], zp = sy[l + 2];
-      if (tym[m] >= 0) ym[m] = sy[tym[m]];
-      if (typ[m] >= 0) yp[m] = sy[typ[m]];
-      const R wzm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? R(0) : cz;
-      const R wzp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? R(0) : cz;
+      // own-column k-1 / k+1 weight and the centre weight of the stencil
+      const R wz = HOC ? (R)ip.qz : cz, wc = HOC ? (R)ip.qd : cd;
+      const R wzm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? R(0) : wz;
+      const R wzp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? R(0) : wz;
+      // sum of the weighted lateral taps (both stencils)
+      R latr = R(0), lati = R(0);
+      if constexpr (HOC) {
+#pragma unroll
+        for (int t = 0; t < NT16; ++t) {
+          if (hs[m][t] >= 0) hv[m][t] = sy[hs[m][t]];
+          if constexpr (REAL) {
+            latr += hw[m][t] * hv[m][t];
+          } else {
+            latr += hw[m][t] * hv[m][t].x;
+            lati += hw[m][t] * hv[m][t].y;
+          }
+        }
+      } else {
+        if (tym[m] >= 0) ym[m] = sy[tym[m]];
+        if (typ[m] >= 0) yp[m] = sy[typ[m]];
+        if constexpr (REAL) {
+          latr = wxm[m] * xm[m] + wxp[m] * xp[m] + wym[m] * ym[m] + wyp[m] * yp[m];
+        } else {
+          latr = wxm[m] * xm[m].x + wxp[m] * xp[m].x + wym[m] * ym[m].x + wyp[m] * yp[m].x;
+          lati = wxm[m] * xm[m].y + wxp[m] * xp[m].y + wym[m] * ym[m].y + wyp[m] * yp[m].y;
+        }
+      }
+      (void)lati;
       if constexpr (REAL) {
         // T~ y at s, real state
-        const R lt = wxm[m] * xm[m] + wxp[m] * xp[m] + wym[m] * ym[m] + wyp[m] * yp[m] + wzm * zm + wzp * zp + cd * yc;
+        const R lt = latr + wzm * zm + wzp * zp + wc * yc;
         if constexpr (OP == OP_ITP1) {
           put(Yout, s, yc - R(0.5) * dt * lt);
         } else if constexpr (OP == OP_ITP2) {
@@ -475,10 +537,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         }
       } else {
       // T~ y at s
-      const R lr = wxm[m] * xm[m].x + wxp[m] * xp[m].x + wym[m] * ym[m].x + wyp[m] * yp[m].x + wzm * zm.x +
-                   wzp * zp.x + cd * yc.x;
-      const R li = wxm[m] * xm[m].y + wxp[m] * xp[m].y + wym[m] * ym[m].y + wyp[m] * yp[m].y + wzm * zm.y +
-                   wzp * zp.y + cd * yc.y;
+      const R lr = latr + wzm * zm.x + wzp * zp.x + wc * yc.x;
+      const R li = lati + wzm * zm.y + wzp * zp.y + wc * yc.y;
 
       if constexpr (OP == OP_ITP1) {
         put(a.out, s, cmk<R>(yc.x - R(0.5) * dt * lr, yc.y - R(0.5) * dt * li));
@@ -605,17 +665,33 @@ template <int BLOCK, int SPT, typename R, int OP, bool REAL>
 static hipError_t launch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   const size_t dyn = (size_t)p.max_seg * sizeof(SegNb) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
   if (p.off32 && cfg.nt)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s,
+                       p, a);
   else if (p.off32)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false, REAL>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false, REAL, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s,
+                       p, a);
   else
-    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL, false>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+  return hipGetLastError();
+}
+
+// The 19-point stencil holds sixteen lateral values per site in registers, so
+// it is compiled for one site per lane and 32-bit offsets only.
+template <typename R, int OP, bool REAL>
+static hipError_t launch_pass_hoc(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
+  if (!p.off32 || cfg.block != 256 || cfg.spt != 1) return hipErrorInvalidValue;
+  const size_t dyn = (size_t)p.max_seg * sizeof(SegHoc) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
+  if (cfg.nt)
+    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, true, REAL, true>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+  else
+    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, false, REAL, true>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
   return hipGetLastError();
 }
 
 template <typename R, int OP, bool REAL = false>
 static hipError_t dispatch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   if (p.n_chunks <= 0) return hipSuccess;
+  if (p.hoc) return launch_pass_hoc<R, OP, REAL>(p, cfg, a, s);
   // arrays of 4 GiB or more use 64-bit addressing with the 256 x 2 shape (the
   // chunk table of a grid that large is built for that shape)
   if (cfg.block == 256 && cfg.spt == 1) return launch_pass<256, 1, R, OP, REAL>(p, cfg, a, s);

@@ -105,6 +105,49 @@ def test_segments_reproduce_brute_force_neighbours(lib, name, make):
     assert np.array_equal(r[:, 4], np.concatenate([[0], np.cumsum(lens)[:-1]]))
 
 
+HOC_TAPS = ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (-1, 0, -1), (-1, 0, 1), (1, 0, -1), (1, 0, 1),
+            (0, -1, -1), (0, -1, 1), (0, 1, -1), (0, 1, 1), (-1, -1, 0), (-1, 1, 0), (1, -1, 0), (1, 1, 0))
+
+
+@pytest.mark.parametrize("name,make", CASES)
+def test_hoc_segments_reproduce_brute_force_taps(lib, name, make):
+    """The 19-point tables: every active site's sixteen lateral taps (and
+    the run-end flags for k+-1) match a dense box lookup exactly."""
+    w = make()
+    g = _host_grid(w.box, runs=w.runs)
+    segs = g.hoc_segments()
+    n0, n1, n2 = w.box.n
+    idx = -np.ones(w.box.n, np.int64)
+    i, j, k = site_ijk(w.runs)
+    idx[i, j, k] = np.arange(i.size)
+    want = -np.ones((i.size, 16), np.int64)
+    for t, (di, dj, dk) in enumerate(HOC_TAPS):
+        a, b, c = i + di, j + dj, k + dk
+        ok = (a >= 0) & (a < n0) & (b >= 0) & (b < n1) & (c >= 0) & (c < n2)
+        want[ok, t] = idx[a[ok], b[ok], c[ok]]
+    got = -np.ones_like(want)
+    covered = np.zeros(i.size, np.int64)
+    zgot = -np.ones((i.size, 2), np.int64)
+    for row in segs:
+        start, length, flags = row[0], row[1], row[2]
+        s = np.arange(start, start + length)
+        covered[s] += 1
+        for t in range(16):
+            if row[3 + t] != 0:
+                got[s, t] = s + row[3 + t]
+        zm, zp = s - 1, s + 1
+        if flags & 1:
+            zm[0] = -1
+        if flags & 2:
+            zp[-1] = -1
+        zgot[s, 0], zgot[s, 1] = zm, zp
+    assert np.all(covered == 1)
+    assert np.array_equal(got, want)
+    ref = _expected_neighbours(w.box, w.runs)
+    assert np.array_equal(zgot, ref[:, 4:6])
+    assert segs.shape[0] >= g.n_segments
+
+
 def test_mask_and_runs_give_same_layout(lib):
     w = configs.random_mask_problem(n=(8, 9, 10), density=0.5, seed=3)
     a = _host_grid(w.box, mask=w.extra["mask"])
