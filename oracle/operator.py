@@ -18,7 +18,11 @@ Two independent constructions are provided and must agree:
 The 19-point higher-order compact (HOC) stencil of App. B eq. (B2) adds to
 the Kronecker sum the mixed terms (1/12)(d_a^2 + d_b^2) delta_a^2 (x) delta_b^2
 for each pair of axes (a, b); the same two constructions are provided for it
-(`kinetic_kron_19`, `kinetic_direct_19`).
+(`kinetic_kron_19`, `kinetic_direct_19`), and for the cubic 27-point stencil
+used in Sec. II.B / III (weights not printed; taken here for equal spacings
+as (1/(30 h^2)) [-128, 14, 3, 1] at the centre, faces, edges and corners, a
+stencil whose leading error is the same isotropic (h^2/12) Lap^2 as eq.
+(B2)'s) (`kinetic_kron_27`, `kinetic_direct_27`).
 
 Sites are ordered by box linear index (i*n1 + j)*n2 + k (z fastest).
 """
@@ -128,8 +132,47 @@ def stencil_19_weights(h):
     return w
 
 
-def kinetic_direct_19(n, h, lin: np.ndarray) -> sp.csr_matrix:
-    """The 19-point operator assembled directly on the active set."""
+def laplacian_kron_27(n, h) -> sp.csr_matrix:
+    """Full-box cubic 27-point Laplacian for equal spacings h: (1/(30 h^2))
+    [-128 I + 14 F + 3 E + C] with F, E, C the sums over the faces, edges and
+    corners, built from Kronecker products of the 1D neighbour sum
+    P = [1, 0, 1] (Dirichlet) and identities."""
+    hh = float(h[0])
+    if max(abs(h[1] - hh), abs(h[2] - hh)) > 1e-12 * hh:
+        raise ValueError("the 27-point stencil is defined here for equal spacings")
+    P = [sp.diags([np.ones(n[d] - 1), np.ones(n[d] - 1)], [-1, 1], shape=(n[d], n[d]), format="csr")
+         for d in range(3)]
+    I = [sp.identity(n[d], format="csr") for d in range(3)]
+
+    def k3(a, b, c):
+        return sp.kron(sp.kron(a, b), c)
+
+    F = k3(P[0], I[1], I[2]) + k3(I[0], P[1], I[2]) + k3(I[0], I[1], P[2])
+    E = k3(P[0], P[1], I[2]) + k3(P[0], I[1], P[2]) + k3(I[0], P[1], P[2])
+    Cn = k3(P[0], P[1], P[2])
+    Id = k3(I[0], I[1], I[2])
+    return ((-128.0 * Id + 14.0 * F + 3.0 * E + Cn) / (30.0 * hh * hh)).tocsr()
+
+
+def kinetic_kron_27(n, h, lin: np.ndarray) -> sp.csr_matrix:
+    L = laplacian_kron_27(n, h)
+    lin = np.asarray(lin, dtype=np.int64)
+    return (-0.5 * L[lin][:, lin]).tocsr()
+
+
+def stencil_27_weights(h):
+    """Weights of the cubic 27-point stencil by offset, for equal spacings."""
+    hh = float(h[0])
+    w = {}
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            for dk in (-1, 0, 1):
+                nz = (di != 0) + (dj != 0) + (dk != 0)
+                w[(di, dj, dk)] = {0: -128.0, 1: 14.0, 2: 3.0, 3: 1.0}[nz] / (30.0 * hh * hh)
+    return w
+
+
+def _kinetic_direct_weights(n, lin: np.ndarray, weights) -> sp.csr_matrix:
     lin = np.asarray(lin, dtype=np.int64)
     m = lin.size
     n0, n1, n2 = (int(v) for v in n)
@@ -137,7 +180,7 @@ def kinetic_direct_19(n, h, lin: np.ndarray) -> sp.csr_matrix:
     ext = (n0, n1, n2)
     strides = (n1 * n2, n2, 1)
     rows, cols, vals = [], [], []
-    for off, wv in stencil_19_weights(h).items():
+    for off, wv in weights.items():
         inside = np.ones(m, bool)
         for d in range(3):
             inside &= (coords[d] + off[d] >= 0) & (coords[d] + off[d] < ext[d])
@@ -151,6 +194,16 @@ def kinetic_direct_19(n, h, lin: np.ndarray) -> sp.csr_matrix:
     L = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(m, m))
     L.sum_duplicates()
     return (-0.5 * L).tocsr()
+
+
+def kinetic_direct_27(n, h, lin: np.ndarray) -> sp.csr_matrix:
+    """The 27-point operator assembled directly on the active set."""
+    return _kinetic_direct_weights(n, lin, stencil_27_weights(h))
+
+
+def kinetic_direct_19(n, h, lin: np.ndarray) -> sp.csr_matrix:
+    """The 19-point operator assembled directly on the active set."""
+    return _kinetic_direct_weights(n, lin, stencil_19_weights(h))
 
 
 def apply(T: sp.csr_matrix, psi: np.ndarray) -> np.ndarray:
