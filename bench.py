@@ -262,6 +262,88 @@ def bench_itp_real(args, dev, report):
     torch.cuda.empty_cache()
 
 
+def bench_restage(args, dev, report):
+    """One stage of a staged ramp at the headline size (Sec. V): post-selection
+    on the device from two box potentials, the carry-over of psi to the new
+    grid, and real time with the potential interpolated between the stage
+    arrays (two field reads per stage instead of one)."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    w, g, U_c, psi, pot_itp, pot_rt = setup_c2(dev, "c128")
+    box = w.box
+    ax = [torch.tensor(box.axis(d), dtype=torch.float64, device=dev) for d in range(3)]
+    U = 0.5 * (ax[0][:, None, None] ** 2 + ax[1][None, :, None] ** 2 + 4.0 * ax[2][None, None, :] ** 2)
+    Va = torch.sqrt((U - 60.0) ** 2 + 4.0).contiguous()
+    Vb = torch.sqrt((U - 62.0) ** 2 + 4.0).contiguous()
+    del U
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g2 = Grid.from_threshold(box.n, box.h, box.x0, Va, Vb, 27.0, device=0)
+    t_sel = time.perf_counter() - t
+    t = time.perf_counter()
+    psi2 = g2.remap_from(g, psi)
+    torch.cuda.synchronize()
+    t_remap = time.perf_counter() - t
+    fa, fb = g2.pack(Va), g2.pack(Vb)
+    del Va, Vb
+    steps = max(args.int_steps, 1)
+    pot = Potential.lerp(fa, fb, 0.0, steps * w.dt)
+    g2.real_time(psi2, pot, w.g, w.dt, 2, observe=False)       # warm-up
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    g2.real_time(psi2, pot, w.g, w.dt, steps, observe=False)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    b = 224 + 4 * 8
+    report["restage_c2"] = {
+        "workload": "stage Delta 60 -> 62 of the rf-bubble 1024x1024x512 box, cutoff 27 on min(V_a, V_b)",
+        "n_active_before": w.n_active, "n_active_after": g2.n_active, "post_selection_s": t_sel,
+        "remap_ms": 1e3 * t_remap, "lerp_rk4_ms_per_step": ms, "algo_bytes_per_site_step": b,
+        "eff_GBps": b * g2.n_active / (ms * 1e-3) / 1e9}
+    log(f"[bench] restage: select {t_sel:.2f}s, remap {1e3 * t_remap:.1f} ms, LERP RK4 {ms:.3f} ms/step "
+        f"({g2.n_active} sites)")
+    del psi, psi2, fa, fb, g, g2
+    torch.cuda.empty_cache()
+
+
+def bench_hoc(args, dev, report):
+    """The 19-point HOC stencil (App. B eq. (B2)) and the cubic 27-point one
+    at the headline size: the same passes as the 7-point path with 16 / 24
+    lateral taps per site."""
+    import torch
+    w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, "c128")
+    n = w.n_active
+    steps = max(args.int_steps, 1)
+    out = {"workload": "rf-bubble 1024x1024x512, 16,028,656 active sites, complex128", "steps": steps}
+    for pts in (7, 19, 27):
+        g.set_stencil(pts)
+        res = {}
+        for name, fn, b in (("itp", lambda k: g.imag_time(psi, pot_itp, w.g, w.dt, k, observe=False), 80),
+                            ("rk4", lambda k: g.real_time(psi, pot_rt, w.g, w.dt, k, observe=False), 224)):
+            fn(2)
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn(steps)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            res[name] = {"ms_per_step": ms, "site_updates_per_s": n / (ms * 1e-3),
+                         "eff_GBps": b * n / (ms * 1e-3) / 1e9}
+        if pts != 7:
+            res["segments"] = int(g.hoc_segments(pts).shape[0])
+        out[f"{pts}pt"] = res
+        log(f"[bench] {pts}-point: ITP {res['itp']['ms_per_step']:.3f} ms, RK4 {res['rk4']['ms_per_step']:.3f} ms")
+    g.set_stencil(7)
+    report["hoc19_c2"] = out
+    del psi, U, g
+    torch.cuda.empty_cache()
+
+
 def cpu_baseline(args):
     """The FP64 oracle, single-threaded, on a slab of the headline workload:
     the active sites of x-planes [448, 576) of the 1024 x 1024 x 512 grid
@@ -470,6 +552,10 @@ def main():
         log("[bench] integrators done")
         bench_itp_real(args, dev, report)
         log("[bench] real imaginary time done")
+        bench_restage(args, dev, report)
+        log("[bench] restage done")
+        bench_hoc(args, dev, report)
+        log("[bench] 19-point stencil done")
     if args.c5 > 0:
         bench_c5(args, dev, report)
         log("[bench] C5 precision study done")
@@ -513,7 +599,8 @@ def main():
     if "c64" in report:
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
-    for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "precision_c5"):
+    for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "restage_c2", "hoc19_c2",
+                "precision_c5"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)

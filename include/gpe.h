@@ -177,27 +177,35 @@ gpe_status gpe_grid_segments(gpe_grid grid, int32_t* out_host);
 /* Host copy of the run table: n_runs x 5 int64 {i, j, k0, k1, start}. */
 gpe_status gpe_grid_runs(gpe_grid grid, int64_t* out_host);
 
-/* Laplacian stencil used by every later call on the grid: 7 (the default,
- * App. B eq. (B1)) or 19, the higher-order compact stencil of App. B eq.
- * (B2): Lap_7 + (1/12) sum over axis pairs (a, b) of (h_a^2 + h_b^2)
- * delta_a^2 (x) delta_b^2, restricted to the active set like Lap_7 (rows and
- * columns outside A removed, i.e. psi = 0 off A).  The 19-point tables (sixteen
- * lateral taps per segment) are built on first use.  19 is available for
- * single grids whose per-site arrays are below 4 GiB; its kernels run 256
+/* Laplacian stencil used by every later call on the grid:
+ *   7  (the default) App. B eq. (B1);
+ *   19 the higher-order compact stencil of App. B eq. (B2): Lap_7 + (1/12)
+ *      sum over axis pairs (a, b) of (h_a^2 + h_b^2) delta_a^2 (x) delta_b^2;
+ *   27 the cubic 27-point stencil (Sec. II.B and III use a 3^3 HOC stencil
+ *      without printing it): for equal spacings h, (1/(30 h^2)) times
+ *      -128 at the centre, 14 at the 6 faces, 3 at the 12 edges and 1 at the
+ *      8 corners; like eq. (B2) its leading error is the isotropic
+ *      (h^2/12) Lap^2.  Equal spacings are required (GPE_ERR_ARG otherwise).
+ * Every stencil is restricted to the active set like Lap_7 (rows and columns
+ * outside A removed, i.e. psi = 0 off A).  The 19/27-point tables (16/24
+ * lateral taps per segment) are built on first use.  They are available for
+ * single grids whose per-site arrays are below 4 GiB; their kernels run 256
  * lanes x 1 site whatever the launch configuration says.  The stability
  * checks use the Gershgorin bound of the selected operator.
  * Errors: GPE_ERR_ARG for another point count. */
 gpe_status gpe_grid_set_stencil(gpe_grid grid, int32_t points);
 gpe_status gpe_grid_get_stencil(gpe_grid grid, int32_t* points);
 
-/* Host copy of the 19-point segment table (built on demand, also for
- * host-only grids): *n_segments rows of 20 int32 {start, length, flags,
- * off[16], 0}; off[t] is the constant compact offset of lateral tap t
- * (0 = absent), taps in the order
+/* Host copy of the 19- or 27-point segment table (built on demand, also for
+ * host-only grids): *n_segments rows of 4 + T int32 {start, length, flags,
+ * off[T], 0}, T = 16 (points = 19) or 24 (points = 27); off[t] is the
+ * constant compact offset of lateral tap t (0 = absent), taps as (di, dj, dk)
  *   (-1,0,0) (1,0,0) (0,-1,0) (0,1,0)  (-1,0,-1) (-1,0,1) (1,0,-1) (1,0,1)
  *   (0,-1,-1) (0,-1,1) (0,1,-1) (0,1,1)  (-1,-1,0) (-1,1,0) (1,-1,0) (1,1,0)
- * as (di, dj, dk).  out_host may be NULL to query the count only. */
-gpe_status gpe_grid_hoc_segments(gpe_grid grid, int64_t* n_segments, int32_t* out_host);
+ * and for 27 points the corners (-1,-1,-1) (-1,-1,1) (-1,1,-1) (-1,1,1)
+ * (1,-1,-1) (1,-1,1) (1,1,-1) (1,1,1).  out_host may be NULL to query the
+ * count only. */
+gpe_status gpe_grid_stencil_segments(gpe_grid grid, int32_t points, int64_t* n_segments, int32_t* out_host);
 
 gpe_status gpe_grid_destroy(gpe_grid grid);
 

@@ -59,7 +59,7 @@ SIGNATURES = {
     "gpe_grid_runs": (C.c_int, [_vp, _vp]),
     "gpe_grid_set_stencil": (C.c_int, [_vp, _i32]),
     "gpe_grid_get_stencil": (C.c_int, [_vp, C.POINTER(_i32)]),
-    "gpe_grid_hoc_segments": (C.c_int, [_vp, C.POINTER(_i64), _vp]),
+    "gpe_grid_stencil_segments": (C.c_int, [_vp, _i32, C.POINTER(_i64), _vp]),
     "gpe_grid_destroy": (C.c_int, [_vp]),
     "gpe_work_bytes": (C.c_int, [_vp, C.c_int, _i32, _i64, _i64, C.POINTER(C.c_size_t)]),
     "gpe_pack": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),

@@ -232,7 +232,7 @@ class Grid:
         return out
 
     def set_stencil(self, points: int) -> None:
-        """7-point (default) or 19-point HOC Laplacian (App. B eq. (B2))."""
+        """7-point (default), 19-point HOC (App. B eq. (B2)) or 27-point cubic Laplacian."""
         check(L.load().gpe_grid_set_stencil(self._h, int(points)))
 
     def get_stencil(self) -> int:
@@ -240,12 +240,12 @@ class Grid:
         check(L.load().gpe_grid_get_stencil(self._h, C.byref(c)))
         return c.value
 
-    def hoc_segments(self) -> np.ndarray:
-        """The 19-point segment table: rows {start, length, flags, off[16], 0}."""
+    def hoc_segments(self, points: int = 19) -> np.ndarray:
+        """The 19- or 27-point segment table: rows {start, length, flags, off[T], 0}."""
         n = C.c_int64()
-        check(L.load().gpe_grid_hoc_segments(self._h, C.byref(n), None))
-        out = np.zeros((n.value, 20), np.int32)
-        check(L.load().gpe_grid_hoc_segments(self._h, C.byref(n), out.ctypes.data))
+        check(L.load().gpe_grid_stencil_segments(self._h, int(points), C.byref(n), None))
+        out = np.zeros((n.value, 4 + (16 if points == 19 else 24)), np.int32)
+        check(L.load().gpe_grid_stencil_segments(self._h, int(points), C.byref(n), out.ctypes.data))
         return out
 
     # ---- work buffers ---------------------------------------------------

@@ -163,11 +163,13 @@ struct Problem {
   std::vector<double> inst_h;          // 3 per instance
   std::vector<SegHead> heads;          // host copy (n_segs + 1)
   std::vector<int64_t> plane_begin;    // first compact site of every non-empty x-plane of every instance
-  // 19-point stencil tables (single grids only, built by enable_hoc)
+  // 19- and 27-point stencil tables (single grids only, built by enable_hoc)
   int stencil = 7;
-  std::vector<SegHead> hoc_heads;      // host copy (n_hoc_segs + 1)
+  std::vector<SegHead> hoc_heads, c27_heads;   // host copies (segments + 1)
   SegHead* d_hoc_heads = nullptr;
   SegHoc* d_hoc_nbs = nullptr;
+  SegHead* d_c27_heads = nullptr;
+  SegC27* d_c27_nbs = nullptr;
   SegHead* d_heads = nullptr;
   SegNb* d_nbs = nullptr;
   std::map<int, ChunkSet> chunksets;
@@ -207,8 +209,12 @@ struct Problem {
     (void)hipFree(d_nbs);
     (void)hipFree(d_hoc_heads);
     (void)hipFree(d_hoc_nbs);
+    (void)hipFree(d_c27_heads);
+    (void)hipFree(d_c27_nbs);
     d_hoc_heads = nullptr;
     d_hoc_nbs = nullptr;
+    d_c27_heads = nullptr;
+    d_c27_nbs = nullptr;
     (void)hipFree(d_inst);
     (void)hipFree(d_out);
     (void)hipFree(d_step);
@@ -302,23 +308,48 @@ struct Problem {
   // Upload the 19-point segment tables of a single grid's layout (built on
   // the host on first use) and make sure the partial-sum scratch covers the
   // larger chunk count.
-  gpe_status enable_hoc(Layout& lay) {
-    if (n_inst != 1) return fail(GPE_ERR_STATE, "the 19-point stencil is available for single grids only");
-    if (d_hoc_heads) return GPE_OK;
-    build_hoc_segments(lay);
-    const int64_t nh = (int64_t)lay.hoc_nbs.size();
-    hoc_heads = lay.hoc_heads;
+  template <typename Desc>
+  gpe_status upload_taps(const std::vector<SegHead>& hh, const std::vector<Desc>& nb, SegHead** dh, Desc** dn) {
+    const int64_t nh = (int64_t)nb.size();
     DeviceGuard g(device);
-    if (dalloc(&d_hoc_heads, nh + 1) != hipSuccess || dalloc(&d_hoc_nbs, nh) != hipSuccess) {
-      (void)hipFree(d_hoc_heads);
-      (void)hipFree(d_hoc_nbs);
-      d_hoc_heads = nullptr;
-      d_hoc_nbs = nullptr;
-      return fail(GPE_ERR_ALLOC, "19-point segment table allocation failed");
+    if (dalloc(dh, nh + 1) != hipSuccess || dalloc(dn, nh) != hipSuccess) {
+      (void)hipFree(*dh);
+      (void)hipFree(*dn);
+      *dh = nullptr;
+      *dn = nullptr;
+      return fail(GPE_ERR_ALLOC, "stencil segment table allocation failed");
     }
-    hipError_t e = hipMemcpy(d_hoc_heads, hoc_heads.data(), sizeof(SegHead) * (nh + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_hoc_nbs, lay.hoc_nbs.data(), sizeof(SegHoc) * nh, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "19-point segment table upload");
+    hipError_t e = hipMemcpy(*dh, hh.data(), sizeof(SegHead) * (nh + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(*dn, nb.data(), sizeof(Desc) * nh, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(*dh);
+      (void)hipFree(*dn);
+      *dh = nullptr;
+      *dn = nullptr;
+      return hip_fail(e, "stencil segment table upload");
+    }
+    return GPE_OK;
+  }
+
+  gpe_status enable_hoc(Layout& lay, int points) {
+    if (n_inst != 1) return fail(GPE_ERR_STATE, "the 19- and 27-point stencils are available for single grids only");
+    int64_t nh = 0;
+    if (points == 19) {
+      if (d_hoc_heads) return GPE_OK;
+      build_hoc_segments(lay);
+      hoc_heads = lay.hoc_heads;
+      nh = (int64_t)lay.hoc_nbs.size();
+      gpe_status st = upload_taps(hoc_heads, lay.hoc_nbs, &d_hoc_heads, &d_hoc_nbs);
+      if (st != GPE_OK) return st;
+    } else {
+      if (d_c27_heads) return GPE_OK;
+      build_c27_segments(lay);
+      c27_heads = lay.c27_heads;
+      nh = (int64_t)lay.c27_nbs.size();
+      gpe_status st = upload_taps(c27_heads, lay.c27_nbs, &d_c27_heads, &d_c27_nbs);
+      if (st != GPE_OK) return st;
+    }
+    DeviceGuard g(device);
     const int64_t need = (lay.n_active + 255) / 256 + nh / MAX_CHUNK_SEGS + 1;
     if (need > max_chunks) {
       for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -335,14 +366,14 @@ struct Problem {
   }
 
   // chunk table for a chunk capacity and stencil (built on first use)
-  gpe_status chunks_for(int capacity, ChunkSet** out, bool hoc = false) {
-    const int key = capacity * 2 + (hoc ? 1 : 0);
+  gpe_status chunks_for(int capacity, ChunkSet** out, int points = 7) {
+    const int key = capacity * 4 + (points == 19 ? 1 : (points == 27 ? 2 : 0));
     auto it = chunksets.find(key);
     if (it != chunksets.end()) {
       *out = &it->second;
       return GPE_OK;
     }
-    const std::vector<SegHead>& heads = hoc ? hoc_heads : this->heads;
+    const std::vector<SegHead>& heads = points == 19 ? hoc_heads : (points == 27 ? c27_heads : this->heads);
     ChunkSet cs;
     cs.capacity = capacity;
     std::vector<Chunk> tab;
@@ -437,11 +468,11 @@ struct Problem {
 
   Plan plan(const ChunkSet& cs, const LaunchConfig& cfg) const {
     Plan p;
-    const bool hoc = stencil == 19;
-    p.heads = hoc ? d_hoc_heads : d_heads;
+    p.heads = stencil == 19 ? d_hoc_heads : (stencil == 27 ? d_c27_heads : d_heads);
     p.nbs = d_nbs;
-    p.hoc = hoc ? 1 : 0;
+    p.hoc = stencil == 7 ? 0 : stencil;
     p.hocnb = d_hoc_nbs;
+    p.c27nb = d_c27_nbs;
     p.chunks = cs.d_chunks;
     p.inst = d_inst;
     p.partials = d_partials;
@@ -485,6 +516,16 @@ struct Problem {
       h_inst[i].qxy = -0.5 * exy;
       h_inst[i].qxz = -0.5 * exz;
       h_inst[i].qyz = -0.5 * eyz;
+      h_inst[i].qc = 0.0;
+      if (stencil == 27) {
+        // cubic 27-point stencil for equal spacings: (1/(30 h^2)) [-128 centre,
+        // 14 faces, 3 edges, 1 corners], as weights of -Lap/2
+        const double u = -0.5 / (30.0 * h2[0]);
+        h_inst[i].qd = -128.0 * u;
+        h_inst[i].qx = h_inst[i].qy = h_inst[i].qz = 14.0 * u;
+        h_inst[i].qxy = h_inst[i].qxz = h_inst[i].qyz = 3.0 * u;
+        h_inst[i].qc = u;
+      }
       h_inst[i].dV = h[0] * h[1] * h[2];
     }
     HIP_TRY(hipMemcpyAsync(d_inst, h_inst, sizeof(InstParams) * n_inst, hipMemcpyHostToDevice, s));
@@ -699,7 +740,9 @@ double kinetic_bound(const Problem& P) {
   for (int i = 0; i < P.n_inst; ++i) {
     const double* h = &P.inst_h[3 * i];
     const double h2[3] = {h[0] * h[0], h[1] * h[1], h[2] * h[2]};
-    if (P.stencil == 19) {
+    if (P.stencil == 27) {
+      m = std::max(m, 128.0 / (30.0 * h2[0]));
+    } else if (P.stencil == 19) {
       const double exy = (h2[0] + h2[1]) / (12.0 * h2[0] * h2[1]);
       const double exz = (h2[0] + h2[2]) / (12.0 * h2[0] * h2[2]);
       const double eyz = (h2[1] + h2[2]) / (12.0 * h2[1] * h2[2]);
@@ -729,9 +772,9 @@ struct Ctx {
 gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
   c.P = P;
   c.cfg = config_get(config);
-  const bool hoc = P->stencil == 19;
+  const bool hoc = P->stencil != 7;
   if ((uint64_t)P->total * 16u >= (uint64_t(1) << 32)) {
-    if (hoc) return fail(GPE_ERR_ARG, "the 19-point stencil needs arrays below 4 GiB");
+    if (hoc) return fail(GPE_ERR_ARG, "the 19- and 27-point stencils need arrays below 4 GiB");
     // 64-bit addressing is compiled for one shape only
     c.cfg.block = 256;
     c.cfg.spt = 2;
@@ -742,7 +785,7 @@ gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
     c.cfg.block = 256;
     c.cfg.spt = 1;
   }
-  gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs, hoc);
+  gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs, P->stencil);
   if (st != GPE_OK) return st;
   if (c.cfg.xcd == 4) {
     st = P->order_for(*c.cs);
@@ -1290,12 +1333,18 @@ gpe_status gpe_remap(gpe_grid src, gpe_grid dst, gpe_dtype dtype, const void* ps
 
 gpe_status gpe_grid_set_stencil(gpe_grid g, int32_t points) {
   if (!g) return fail(GPE_ERR_ARG, "grid is NULL");
-  if (points != 7 && points != 19) return fail(GPE_ERR_ARG, "stencil must have 7 or 19 points");
+  if (points != 7 && points != 19 && points != 27) return fail(GPE_ERR_ARG, "stencil must have 7, 19 or 27 points");
+  if (points == 27) {
+    const double* h = g->lay.h;
+    const double hm = std::max(h[0], std::max(h[1], h[2])), hn = std::min(h[0], std::min(h[1], h[2]));
+    if (hm - hn > 1e-12 * hm) return fail(GPE_ERR_ARG, "the 27-point stencil needs equal spacings");
+  }
   if (points == 19) build_hoc_segments(g->lay);
+  if (points == 27) build_c27_segments(g->lay);
   if (g->device < 0 || !g->prob) return GPE_OK;
-  if (points == 19) {
+  if (points != 7) {
     DeviceGuard dg(g->device);
-    gpe_status st = g->prob->enable_hoc(g->lay);
+    gpe_status st = g->prob->enable_hoc(g->lay, points);
     if (st != GPE_OK) return st;
   }
   g->prob->stencil = points;
@@ -1308,19 +1357,23 @@ gpe_status gpe_grid_get_stencil(gpe_grid g, int32_t* points) {
   return GPE_OK;
 }
 
-gpe_status gpe_grid_hoc_segments(gpe_grid g, int64_t* n_segments, int32_t* out_host) {
+gpe_status gpe_grid_stencil_segments(gpe_grid g, int32_t points, int64_t* n_segments, int32_t* out_host) {
   if (!g || !n_segments) return fail(GPE_ERR_ARG, "grid or n_segments is NULL");
-  build_hoc_segments(g->lay);
-  const int64_t n = (int64_t)g->lay.hoc_nbs.size();
+  if (points != 19 && points != 27) return fail(GPE_ERR_ARG, "tap tables exist for 19 and 27 points");
+  const bool c27 = points == 27;
+  if (c27) build_c27_segments(g->lay); else build_hoc_segments(g->lay);
+  const std::vector<SegHead>& hh = c27 ? g->lay.c27_heads : g->lay.hoc_heads;
+  const int ntaps = c27 ? C27_TAPS : HOC_TAPS;
+  const int64_t n = (int64_t)hh.size() - 1;
   *n_segments = n;
   if (!out_host) return GPE_OK;
   for (int64_t q = 0; q < n; ++q) {
-    int32_t* o = out_host + 20 * q;
-    o[0] = g->lay.hoc_heads[q].start;
-    o[1] = g->lay.hoc_heads[q + 1].start - g->lay.hoc_heads[q].start;
-    o[2] = g->lay.hoc_heads[q].flags;
-    for (int t = 0; t < HOC_TAPS; ++t) o[3 + t] = g->lay.hoc_nbs[q].off[t];
-    o[19] = 0;
+    int32_t* o = out_host + (4 + ntaps) * q;
+    o[0] = hh[q].start;
+    o[1] = hh[q + 1].start - hh[q].start;
+    o[2] = hh[q].flags;
+    for (int t = 0; t < ntaps; ++t) o[3 + t] = c27 ? g->lay.c27_nbs[q].off[t] : g->lay.hoc_nbs[q].off[t];
+    o[3 + ntaps] = 0;
   }
   return GPE_OK;
 }

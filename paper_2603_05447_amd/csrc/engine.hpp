@@ -34,6 +34,7 @@ struct InstParams {
   // 19-point HOC stencil of App. B eq. (B2) as weights of T~ = -1/2 Lap:
   // faces qx, qy, qz, centre qd, edges qxy (i+-1, j+-1), qxz, qyz
   double qx, qy, qz, qd, qxy, qxz, qyz;
+  double qc;            // 27-point stencil: corner weight (the q* above then hold its weights)
   double omega, norm_target;
   int32_t pot_kind, n_knots;
   int32_t chunk_begin, chunk_count;
@@ -71,8 +72,9 @@ struct Plan {
   int32_t pstride;        // stride between partial-sum components (>= n_chunks)
   int32_t off32;          // 1: every per-site array is below 4 GiB (32-bit byte offsets)
   int32_t max_seg;        // largest seg_count of any chunk (sizes the dynamic LDS)
-  int32_t hoc;            // 1: 19-point stencil; heads/chunks are the HOC segments
-  const SegHoc* hocnb;    // HOC lateral taps (hoc = 1)
+  int32_t hoc;            // 0: 7-point stencil; 19 / 27: heads/chunks are that stencil's segments
+  const SegHoc* hocnb;    // 19-point lateral taps
+  const SegC27* c27nb;    // 27-point lateral taps
 };
 
 // Compiled launch variants (workgroup size x sites per lane, chunk capacity

@@ -133,9 +133,10 @@ std::string build_segments(Layout& L) {
 
 }  // namespace
 
-const int8_t kHocTap[HOC_TAPS][3] = {{-1, 0, 0},  {1, 0, 0},   {0, -1, 0},  {0, 1, 0},   {-1, 0, -1}, {-1, 0, 1},
-                                     {1, 0, -1},  {1, 0, 1},   {0, -1, -1}, {0, -1, 1},  {0, 1, -1},  {0, 1, 1},
-                                     {-1, -1, 0}, {-1, 1, 0},  {1, -1, 0},  {1, 1, 0}};
+const int8_t kHocTap[C27_TAPS][3] = {
+    {-1, 0, 0},   {1, 0, 0},   {0, -1, 0},  {0, 1, 0},   {-1, 0, -1}, {-1, 0, 1}, {1, 0, -1},  {1, 0, 1},
+    {0, -1, -1},  {0, -1, 1},  {0, 1, -1},  {0, 1, 1},   {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0},  {1, 1, 0},
+    {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1},  {1, -1, -1}, {1, -1, 1}, {1, 1, -1},  {1, 1, 1}};
 
 void build_hoc_segments(Layout& L) {
   if (!L.hoc_heads.empty()) return;
@@ -150,6 +151,21 @@ void build_hoc_segments(Layout& L) {
     L.hoc_nbs.push_back(s);
   });
   L.hoc_heads.push_back({(int32_t)L.n_active, 0});
+}
+
+void build_c27_segments(Layout& L) {
+  if (!L.c27_heads.empty()) return;
+  ColumnIndex col;
+  col.build(L);
+  L.c27_heads.reserve(L.heads.size() * 2);
+  L.c27_nbs.reserve(L.nbs.size() * 2);
+  cut_runs(L, col, C27_TAPS, kHocTap, [&](const SegHead& hd, const int32_t* off) {
+    L.c27_heads.push_back(hd);
+    SegC27 s;
+    for (int d = 0; d < C27_TAPS; ++d) s.off[d] = off[d];
+    L.c27_nbs.push_back(s);
+  });
+  L.c27_heads.push_back({(int32_t)L.n_active, 0});
 }
 
 std::string layout_from_runs(const int64_t n[3], int64_t nruns, const int64_t* runs, Layout& out) {

@@ -38,7 +38,13 @@ constexpr int HOC_TAPS = 16;
 struct SegHoc {
   int32_t off[HOC_TAPS];
 };
-extern const int8_t kHocTap[HOC_TAPS][3];
+// The 27-point cubic stencil adds the eight corners (taps 16-23):
+//   (-1,-1,-1) (-1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1) (1,-1,1) (1,1,-1) (1,1,1)
+constexpr int C27_TAPS = 24;
+struct SegC27 {
+  int32_t off[C27_TAPS];
+};
+extern const int8_t kHocTap[C27_TAPS][3];
 
 struct Layout {
   int64_t n[3] = {0, 0, 0};
@@ -50,15 +56,18 @@ struct Layout {
   // segments; heads has n_segments + 1 entries, the last = {n_active, 0}
   std::vector<SegHead> heads;
   std::vector<SegNb> nbs;
-  // HOC segments (built on demand by build_hoc_segments)
+  // HOC segments (built on demand by build_hoc_segments / build_c27_segments)
   std::vector<SegHead> hoc_heads;
   std::vector<SegHoc> hoc_nbs;
+  std::vector<SegHead> c27_heads;
+  std::vector<SegC27> c27_nbs;
   int64_t n_runs() const { return (int64_t)run_i.size(); }
   int64_t n_segments() const { return (int64_t)nbs.size(); }
 };
 
-// Fill L.hoc_heads / L.hoc_nbs (no-op when already built).
+// Fill L.hoc_heads / L.hoc_nbs, or L.c27_heads / L.c27_nbs (no-op when built).
 void build_hoc_segments(Layout& L);
+void build_c27_segments(Layout& L);
 
 // Returns an empty string on success, else a description of the problem.
 std::string layout_from_mask(const int64_t n[3], const uint8_t* mask, Layout& out);

@@ -234,13 +234,16 @@ template <typename R> struct PassArgs {
 // REAL: the state is real (imaginary time from a real start, Sec. II.A), one
 // R per site instead of two; only the imaginary-time passes and the
 // observation pass exist in that form.
-// HOC: the 19-point stencil of App. B eq. (B2) instead of the 7-point one;
-// the segment descriptors then hold the sixteen lateral taps of SegHoc.
-template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT, bool REAL, bool HOC>
+// STN: the stencil.  7 is App. B eq. (B1); 19 is the higher-order compact
+// stencil of eq. (B2), whose segment descriptors hold sixteen lateral taps
+// (SegHoc); 27 is the cubic stencil, which adds the eight corners (SegC27).
+template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT, bool REAL, int STN>
 __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
   using C = typename CT<R>::T;
   using S = typename std::conditional<REAL, R, C>::type;   // stencil state type
-  using D = typename std::conditional<HOC, SegHoc, SegNb>::type;   // lateral descriptor
+  constexpr bool HOC = (STN != 7);
+  using D = typename std::conditional<STN == 27, SegC27,
+                                      typename std::conditional<STN == 19, SegHoc, SegNb>::type>::type;
   static_assert(!REAL || OP == OP_ITP1 || OP == OP_ITP2 || OP == OP_OBS, "real state: ITP and OBS only");
   constexpr int CH = BLOCK * SPT;
   constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
@@ -333,7 +336,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // the same LDS slot), so these loads are unconditional and issue first.
   const SegHead* hsrc = pl.heads + ch.seg_begin;
   const D* nsrc;
-  if constexpr (HOC) nsrc = pl.hocnb + ch.seg_begin; else nsrc = pl.nbs + ch.seg_begin;
+  if constexpr (STN == 27) nsrc = pl.c27nb + ch.seg_begin;
+  else if constexpr (STN == 19) nsrc = pl.hocnb + ch.seg_begin;
+  else nsrc = pl.nbs + ch.seg_begin;
   const int t0 = threadIdx.x;
   // a chunk holds at most MAX_CHUNK_SEGS (< 256 <= BLOCK) segments, so one
   // slot per lane covers its table
@@ -406,13 +411,13 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   S xm[SPT], xp[SPT], ym[SPT], yp[SPT];
   R wxm[SPT], wxp[SPT], wym[SPT], wyp[SPT];
   // HOC: value, LDS slot (-1: loaded from global) and weight of every tap
-  constexpr int NT16 = HOC ? HOC_TAPS : 1;
+  constexpr int NT16 = STN == 27 ? C27_TAPS : (STN == 19 ? HOC_TAPS : 1);
   S hv[SPT][NT16];
   int hs[SPT][NT16];
   R hw[SPT][NT16];
   if constexpr (HOC) {
-    // tap weights by class: faces x, y; xz, yz, xy edges (App. B eq. (B2))
-    const R cls[5] = {(R)ip.qx, (R)ip.qy, (R)ip.qxz, (R)ip.qyz, (R)ip.qxy};
+    // tap weights by class: faces x, y; xz, yz, xy edges; corners
+    const R cls[6] = {(R)ip.qx, (R)ip.qy, (R)ip.qxz, (R)ip.qyz, (R)ip.qxy, (R)ip.qc};
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       const int s = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
@@ -433,7 +438,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         hs[m][t] = lds ? win : -1;
         hv[m][t] = zero;
         if (!lds) hv[m][t] = load(s + o);
-        const int c = t < 2 ? 0 : (t < 4 ? 1 : (t < 8 ? 2 : (t < 12 ? 3 : 4)));
+        const int c = t < 2 ? 0 : (t < 4 ? 1 : (t < 8 ? 2 : (t < 12 ? 3 : (t < 16 ? 4 : 5))));
         hw[m][t] = o ? cls[c] : R(0);
       }
     }
@@ -665,33 +670,35 @@ template <int BLOCK, int SPT, typename R, int OP, bool REAL>
 static hipError_t launch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   const size_t dyn = (size_t)p.max_seg * sizeof(SegNb) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
   if (p.off32 && cfg.nt)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s,
-                       p, a);
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL, 7>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p,
+                       a);
   else if (p.off32)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false, REAL, false>), dim3(p.n_chunks), dim3(BLOCK), dyn, s,
-                       p, a);
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false, REAL, 7>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p,
+                       a);
   else
-    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL, false>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL, 7>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
   return hipGetLastError();
 }
 
-// The 19-point stencil holds sixteen lateral values per site in registers, so
-// it is compiled for one site per lane and 32-bit offsets only.
-template <typename R, int OP, bool REAL>
+// The 19- and 27-point stencils hold 16 / 24 lateral values per site in
+// registers, so they are compiled for one site per lane and 32-bit offsets only.
+template <typename R, int OP, bool REAL, int STN>
 static hipError_t launch_pass_hoc(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
+  using D = typename std::conditional<STN == 27, SegC27, SegHoc>::type;
   if (!p.off32 || cfg.block != 256 || cfg.spt != 1) return hipErrorInvalidValue;
-  const size_t dyn = (size_t)p.max_seg * sizeof(SegHoc) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
+  const size_t dyn = (size_t)p.max_seg * sizeof(D) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
   if (cfg.nt)
-    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, true, REAL, true>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, true, REAL, STN>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
   else
-    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, false, REAL, true>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, false, REAL, STN>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
   return hipGetLastError();
 }
 
 template <typename R, int OP, bool REAL = false>
 static hipError_t dispatch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   if (p.n_chunks <= 0) return hipSuccess;
-  if (p.hoc) return launch_pass_hoc<R, OP, REAL>(p, cfg, a, s);
+  if (p.hoc == 19) return launch_pass_hoc<R, OP, REAL, 19>(p, cfg, a, s);
+  if (p.hoc == 27) return launch_pass_hoc<R, OP, REAL, 27>(p, cfg, a, s);
   // arrays of 4 GiB or more use 64-bit addressing with the 256 x 2 shape (the
   // chunk table of a grid that large is built for that shape)
   if (cfg.block == 256 && cfg.spt == 1) return launch_pass<256, 1, R, OP, REAL>(p, cfg, a, s);

@@ -106,22 +106,25 @@ def test_segments_reproduce_brute_force_neighbours(lib, name, make):
 
 
 HOC_TAPS = ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (-1, 0, -1), (-1, 0, 1), (1, 0, -1), (1, 0, 1),
-            (0, -1, -1), (0, -1, 1), (0, 1, -1), (0, 1, 1), (-1, -1, 0), (-1, 1, 0), (1, -1, 0), (1, 1, 0))
+            (0, -1, -1), (0, -1, 1), (0, 1, -1), (0, 1, 1), (-1, -1, 0), (-1, 1, 0), (1, -1, 0), (1, 1, 0),
+            (-1, -1, -1), (-1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1), (1, -1, 1), (1, 1, -1), (1, 1, 1))
 
 
+@pytest.mark.parametrize("points", [19, 27])
 @pytest.mark.parametrize("name,make", CASES)
-def test_hoc_segments_reproduce_brute_force_taps(lib, name, make):
-    """The 19-point tables: every active site's sixteen lateral taps (and
+def test_hoc_segments_reproduce_brute_force_taps(lib, name, make, points):
+    """The 19/27-point tables: every active site's 16/24 lateral taps (and
     the run-end flags for k+-1) match a dense box lookup exactly."""
     w = make()
     g = _host_grid(w.box, runs=w.runs)
-    segs = g.hoc_segments()
+    segs = g.hoc_segments(points)
+    ntap = 16 if points == 19 else 24
     n0, n1, n2 = w.box.n
     idx = -np.ones(w.box.n, np.int64)
     i, j, k = site_ijk(w.runs)
     idx[i, j, k] = np.arange(i.size)
-    want = -np.ones((i.size, 16), np.int64)
-    for t, (di, dj, dk) in enumerate(HOC_TAPS):
+    want = -np.ones((i.size, ntap), np.int64)
+    for t, (di, dj, dk) in enumerate(HOC_TAPS[:ntap]):
         a, b, c = i + di, j + dj, k + dk
         ok = (a >= 0) & (a < n0) & (b >= 0) & (b < n1) & (c >= 0) & (c < n2)
         want[ok, t] = idx[a[ok], b[ok], c[ok]]
@@ -132,7 +135,7 @@ def test_hoc_segments_reproduce_brute_force_taps(lib, name, make):
         start, length, flags = row[0], row[1], row[2]
         s = np.arange(start, start + length)
         covered[s] += 1
-        for t in range(16):
+        for t in range(ntap):
             if row[3 + t] != 0:
                 got[s, t] = s + row[3 + t]
         zm, zp = s - 1, s + 1

@@ -1,7 +1,8 @@
 """GPU parity of the 19-point higher-order compact stencil (App. B eq. (B2))
-through the C ABI against the oracle's 19-point operator, for every path
-that applies T~: imaginary time (complex and real state), real time with
-RK4 / RKHE3 / RKCK, observations, and the fidelity gradient.
+and of the cubic 27-point stencil through the C ABI against the oracle's
+operators, for every path that applies T~: imaginary time (complex and real
+state), real time with RK4 / RKHE3 / RKCK, observations, and the fidelity
+gradient.
 
 Tolerances: relative L2 <= 1e-10 (complex128), <= 1e-5 (complex64)."""
 import numpy as np
@@ -28,12 +29,12 @@ def _need_gpu():
     p.load_library()
 
 
-def _hoc_case(w, dtype):
+def _hoc_case(w, dtype, points=19):
     c = Case(w, dtype)
-    c.grid.set_stencil(19)
-    assert c.grid.get_stencil() == 19
+    c.grid.set_stencil(points)
+    assert c.grid.get_stencil() == points
     lin = site_linear_index(w.box, w.runs)
-    c.T19 = op.kinetic_direct_19(w.box.n, w.box.h, lin)
+    c.T19 = (op.kinetic_direct_19 if points == 19 else op.kinetic_direct_27)(w.box.n, w.box.h, lin)
     return c
 
 
@@ -120,3 +121,49 @@ def test_hoc_switch_back_and_stability_bound():
     c.grid.real_time(psi, c.pot, w.g, 1e-3, 5, observe=False)
     ref = rt.real_time(c.T, w.psi0, c.opot, w.g, 1e-3, 0.0, 5)
     assert rel_l2(psi.cpu().numpy(), ref) <= 1e-10
+
+
+ISO = [lambda: configs.random_mask_problem(n=(12, 11, 13), density=0.5, seed=43, g=40.0, h=(0.42, 0.42, 0.42)),
+       lambda: configs.small_shell(n=24)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("make", ISO, ids=["random-iso", "shell24"])
+def test_27pt_imag_time_matches_oracle(dtype, make):
+    w = make()
+    c = _hoc_case(w, dtype, 27)
+    psi = c.psi()
+    obs = c.grid.imag_time(psi, c.pot, w.g, 2e-3, 20)
+    ref, _ = itp.imaginary_time(c.T19, w.psi0, w.field, w.g, 2e-3, w.box.dV, 20)
+    err = rel_l2(psi.cpu().numpy(), ref)
+    print(f"27pt ITP {w.name} {dtype}: rel L2 {err:.3e}", flush=True)
+    assert err <= TOL[dtype]
+    N, E, mu = ob.energy_mu(c.T19, ref, w.field, w.g, w.box.dV)
+    assert abs(obs["energy"] - E) <= TOL[dtype] * abs(E) * 10
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "rkck"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_27pt_real_time_matches_oracle(integrator, dtype):
+    w = configs.small_rf_ramp(n=24, steps=20)
+    c = _hoc_case(w, dtype, 27)
+    psi = c.psi()
+    c.grid.real_time(psi, c.pot, w.g, 1e-3, 20, t0=0.003, integrator=integrator, observe=False)
+    if integrator == "rk4":
+        ref = rt.real_time(c.T19, w.psi0, c.opot, w.g, 1e-3, 0.003, 20)
+    else:
+        A, b = tableau.cash_karp5()
+        ref = rt.real_time_tableau(c.T19, w.psi0, c.opot, w.g, 1e-3, 0.003, 20, A, b)
+    err = rel_l2(psi.cpu().numpy(), ref)
+    print(f"27pt {integrator} {dtype}: rel L2 {err:.3e}", flush=True)
+    assert err <= TOL[dtype]
+
+
+def test_27pt_needs_equal_spacings():
+    from paper_2603_05447_amd import GPEError, _lib
+    w = MAKERS[0]()             # anisotropic spacings
+    c = Case(w, "c128")
+    with pytest.raises(GPEError) as e:
+        c.grid.set_stencil(27)
+    assert e.value.status == _lib.GPE_ERR_ARG
+    assert c.grid.get_stencil() == 7
