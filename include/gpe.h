@@ -366,6 +366,15 @@ gpe_status gpe_grid_autotune(gpe_grid grid, gpe_dtype dtype, void* psi, const gp
                              const gpe_params* params, int32_t reps, void* work, size_t work_bytes,
                              void* stream, int32_t* best_config, double* times_ms_host);
 
+/* Every gpe_grid_autotune result is also recorded in a process-wide cache
+ * keyed by (dtype, floor(log2 n_active), floor(log2 mean segment length)).
+ * gpe_grid_apply_tuned gives the grid the cached configuration of its class
+ * (*config = that index) or leaves it unchanged (*config = -1 when the class
+ * has not been tuned).  gpe_autotune_cache_clear empties the cache.  The
+ * cache is guarded by a lock. */
+gpe_status gpe_grid_apply_tuned(gpe_grid grid, gpe_dtype dtype, int32_t* config);
+gpe_status gpe_autotune_cache_clear(void);
+
 /* ---- Per-kernel timing -----------------------------------------------
  * When enabled, every kernel launch of the library is bracketed by HIP
  * events on its stream and the elapsed time is accumulated per kernel

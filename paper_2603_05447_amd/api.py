@@ -231,6 +231,13 @@ class Grid:
         check(L.load().gpe_grid_runs(self._h, out.ctypes.data))
         return out
 
+    def apply_tuned(self, dtype: int) -> Optional[int]:
+        """Take the launch configuration autotuned for this grid's size /
+        segment-length class (any grid of the process), if there is one."""
+        c = C.c_int32()
+        check(L.load().gpe_grid_apply_tuned(self._h, int(dtype), C.byref(c)))
+        return None if c.value < 0 else c.value
+
     def set_stencil(self, points: int) -> None:
         """7-point (default), 19-point HOC (App. B eq. (B2)) or 27-point cubic Laplacian."""
         check(L.load().gpe_grid_set_stencil(self._h, int(points)))

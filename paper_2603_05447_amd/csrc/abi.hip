@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <memory>
 #include <new>
 #include <string>
@@ -1884,6 +1886,22 @@ gpe_status gpe_batch_set_config(gpe_batch b, int32_t config) {
   return GPE_OK;
 }
 
+// Autotuning results, shared by every grid of the process: keyed by the
+// element type, the size class floor(log2 n_active) and the class
+// floor(log2 mean segment length), the two properties that decide which
+// launch variant streams a layout best.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
+static std::tuple<int, int, int> tune_key(gpe_grid g, int dtype) {
+  const int64_t n = g->lay.n_active;
+  const double mean_seg = (double)n / (double)std::max<int64_t>(1, g->lay.n_segments());
+  int nb = 0, sb = 0;
+  while ((int64_t(1) << (nb + 1)) <= n) ++nb;
+  while ((double)(int64_t(1) << (sb + 1)) <= mean_seg) ++sb;
+  return std::make_tuple(dtype, nb, sb);
+}
+
 gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
                              int32_t reps, void* work, size_t work_bytes, void* stream, int32_t* best_config,
                              double* times_ms) {
@@ -1951,6 +1969,32 @@ gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_p
   }
   g->prob->config = bi;
   if (best_config) *best_config = bi;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[tune_key(g, dtype)] = bi;
+  }
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_apply_tuned(gpe_grid g, gpe_dtype dtype, int32_t* config) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st != GPE_OK) return st;
+  if (!config) return fail(GPE_ERR_ARG, "config is NULL");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_cache.find(tune_key(g, dtype));
+  if (it == g_tune_cache.end()) {
+    *config = -1;
+    return GPE_OK;
+  }
+  g->prob->config = it->second;
+  *config = it->second;
+  return GPE_OK;
+}
+
+gpe_status gpe_autotune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.clear();
   return GPE_OK;
 }
 

@@ -175,3 +175,21 @@ def test_autotune_selects_a_valid_config():
     assert c.grid.get_config() == best
     assert all(t > 0 for t in times)
     assert times[best] == min(times)
+
+
+def test_autotune_cache_serves_grids_of_the_same_class():
+    from paper_2603_05447_amd import _lib, load_library
+    load_library().gpe_autotune_cache_clear()
+    w = configs.small_rf_ramp(n=28)
+    c = Case(w, "c128")
+    best, _ = c.grid.autotune(c.psi(), c.pot, w.g, w.dt, reps=2)
+    # the same layout again: same size and segment-length class
+    c2 = Case(w, "c128")
+    assert c2.grid.apply_tuned(_lib.GPE_C128) == best
+    assert c2.grid.get_config() == best
+    # another element type, or a much smaller grid, has not been tuned
+    assert Case(w, "c64").grid.apply_tuned(_lib.GPE_C64) is None
+    small = configs.small_shell(n=12)
+    assert Case(small, "c128").grid.apply_tuned(_lib.GPE_C128) is None
+    load_library().gpe_autotune_cache_clear()
+    assert Case(w, "c128").grid.apply_tuned(_lib.GPE_C128) is None
