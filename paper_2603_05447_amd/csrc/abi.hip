@@ -625,6 +625,7 @@ size_t work_bytes_for(int64_t n, int dtype, int mode, int64_t nsteps, int64_t ck
 struct gpe_grid_s {
   Layout lay;
   int device = -1;
+  int stencil = 7;          // selected stencil (also recorded for host-only grids)
   std::unique_ptr<Problem> prob;
   int64_t* d_run_base = nullptr;
   int32_t* d_run_start = nullptr;
@@ -1343,19 +1344,21 @@ gpe_status gpe_grid_set_stencil(gpe_grid g, int32_t points) {
   }
   if (points == 19) build_hoc_segments(g->lay);
   if (points == 27) build_c27_segments(g->lay);
-  if (g->device < 0 || !g->prob) return GPE_OK;
-  if (points != 7) {
-    DeviceGuard dg(g->device);
-    gpe_status st = g->prob->enable_hoc(g->lay, points);
-    if (st != GPE_OK) return st;
+  if (g->device >= 0 && g->prob) {
+    if (points != 7) {
+      DeviceGuard dg(g->device);
+      gpe_status st = g->prob->enable_hoc(g->lay, points);
+      if (st != GPE_OK) return st;
+    }
+    g->prob->stencil = points;
   }
-  g->prob->stencil = points;
+  g->stencil = points;
   return GPE_OK;
 }
 
 gpe_status gpe_grid_get_stencil(gpe_grid g, int32_t* points) {
   if (!g || !points) return fail(GPE_ERR_ARG, "grid or points is NULL");
-  *points = (g->prob ? g->prob->stencil : 7);
+  *points = g->stencil;
   return GPE_OK;
 }
 

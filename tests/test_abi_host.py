@@ -260,3 +260,22 @@ def test_c5_scale_layout_from_analytic_runs(lib):
     segs = g.segments()
     assert segs[:, 1].sum() == g.n_active
     assert np.all(segs[:, 3:7] == 0)       # no lateral neighbours in this sparse set
+
+
+def test_plain_c_client(lib, tmp_path):
+    """The ABI is usable from C alone: a small C program (tests/c/) is built
+    with gcc against include/gpe.h and libgpe.so and runs host-only calls."""
+    import shutil
+    import subprocess
+    from paper_2603_05447_amd import _lib
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = os.path.join(ROOT, "tests", "c", "abi_host_demo.c")
+    exe = str(tmp_path / "abi_host_demo")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-O1", src, "-I", os.path.join(ROOT, "include"), "-L", libdir,
+                    "-lgpe", f"-Wl,-rpath,{libdir}", "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.startswith("ok ")
