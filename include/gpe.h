@@ -301,7 +301,8 @@ gpe_status gpe_fidelity_grad(gpe_grid grid, gpe_dtype dtype, const void* psi0, c
  * A batch concatenates the compact layouts of n grids (instance i occupies
  * compact sites [offsets[i], offsets[i+1])) so one kernel launch advances
  * every instance.  All per-site buffers passed to batch calls (psi, field,
- * psi_target) are concatenated the same way. */
+ * psi_target) are concatenated the same way.  Batches use the 7-point
+ * stencil whatever stencil the member grids have selected. */
 typedef struct {
   double omega;
   int32_t n_knots;
