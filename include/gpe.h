@@ -210,7 +210,8 @@ gpe_status gpe_grid_stencil_segments(gpe_grid grid, int32_t points, int64_t* n_s
 gpe_status gpe_grid_destroy(gpe_grid grid);
 
 /* Size in bytes of the device work buffer a call needs.
- *   mode GPE_MODE_ITP: gpe_imag_time; GPE_MODE_ITP_REAL: gpe_imag_time_real;
+ *   mode GPE_MODE_ITP: gpe_imag_time (two temporaries and P); GPE_MODE_ITP_REAL:
+ *   gpe_imag_time_real (the same in reals);
  *   GPE_MODE_RT / _RT_RKHE3 / _RT_RKCK:
  *   gpe_real_time with that integrator (3, 2 and 5 state vectors);
  *   GPE_MODE_ADJ: gpe_fidelity_grad with nsteps and ckpt_every as given. */

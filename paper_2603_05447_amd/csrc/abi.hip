@@ -606,8 +606,10 @@ size_t work_bytes_for(int64_t n, int dtype, int mode, int64_t nsteps, int64_t ck
   Carver c(nullptr);
   const size_t st = (size_t)n * csize(dtype);
   if (mode == GPE_MODE_ITP || mode == GPE_MODE_ITP_REAL) {
+    // tmp, P and (19/27-point stencils) phi
     c.take(mode == GPE_MODE_ITP ? st : (size_t)n * rsize(dtype));
     c.take((size_t)n * rsize(dtype));
+    c.take(mode == GPE_MODE_ITP ? st : (size_t)n * rsize(dtype));
   } else if (mode == GPE_MODE_RT || mode == GPE_MODE_RT_RKHE3 || mode == GPE_MODE_RT_RKCK) {
     const int integ = mode == GPE_MODE_RT ? GPE_RK4 : (mode == GPE_MODE_RT_RKHE3 ? GPE_RKHE3 : GPE_RKCK);
     for (int i = 0; i < integrator_buffers(integ); ++i) c.take(st);
@@ -862,6 +864,11 @@ gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps,
   Carver cv(work);
   void* tmp = cv.take((size_t)c.P->total * (real ? 1 : 2) * sizeof(R));
   void* prop = cv.take((size_t)c.P->total * sizeof(R));
+  // With the 19/27-point stencils the first pass would apply the diagonal
+  // half-step at every one of 16/24 lateral taps (two gathers each); a
+  // separate site-by-site pass forms phi once instead.
+  const bool split_diag = c.P->stencil != 7;
+  void* phi = split_diag ? cv.take((size_t)c.P->total * (real ? 1 : 2) * sizeof(R)) : nullptr;
   LTRY(run_set_step(c.pl.step, 0, c.s));
   LTRY(run_make_prop<R>(c.pl, c.cfg, field, prop, c.s));
   LTRY(run_set_scale_one(c.pl, c.s));
@@ -872,7 +879,12 @@ gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps,
       LTRY(run_finalize(c.pl, FIN_OBS, hist + k * c.P->n_inst, c.s));
       ++k;
     }
-    LTRY(run_itp_pass1<R>(c.pl, c.cfg, psi, prop, tmp, real, c.s));
+    if (split_diag) {
+      LTRY(run_itp_phi<R>(c.pl, c.cfg, psi, prop, phi, real, c.s));
+      LTRY(run_itp_pass1<R>(c.pl, c.cfg, phi, prop, tmp, real, c.s, true));
+    } else {
+      LTRY(run_itp_pass1<R>(c.pl, c.cfg, psi, prop, tmp, real, c.s));
+    }
     LTRY(run_itp_pass2<R>(c.pl, c.cfg, tmp, prop, psi, real, c.s));
     LTRY(run_finalize(c.pl, FIN_NORM_SCALE, nullptr, c.s));
   }

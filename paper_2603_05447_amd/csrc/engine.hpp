@@ -107,8 +107,14 @@ const char* family_name(int f);
 // All return hipSuccess or the launch error.  `cfg` selects the variant.
 // R = double (complex128) or float (complex64).  `real`: the state is one R
 // per site (real imaginary time) instead of a complex pair.
+// raw_input: psi_raw already holds phi (run_itp_phi applied the diagonal
+// half-step and the scale), so pass 1 applies only the Euler substep
 template <typename R> hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw,
-                                               const void* prop, void* tmp, bool real, hipStream_t s);
+                                               const void* prop, void* tmp, bool real, hipStream_t s,
+                                               bool raw_input = false);
+// phi = s psi P (1 - g |s psi|^2 dt/2) site by site (s = the instance's scale)
+template <typename R> hipError_t run_itp_phi(const Plan& p, const LaunchConfig& cfg, const void* psi,
+                                             const void* prop, void* phi, bool real, hipStream_t s);
 template <typename R> hipError_t run_itp_pass2(const Plan& p, const LaunchConfig& cfg, const void* tmp,
                                                const void* prop, void* psi_raw, bool real, hipStream_t s);
 // stage 1..4 of the memory-optimised RK4 step; Y = stencil input, y0 = step start,

@@ -206,6 +206,7 @@ enum PassOp {
   OP_RK2F,       // as OP_RK2, and out2 = (-y0 + Y + 2 out)/3
   OP_RK4F,       // out = A + Y/3 + dt/6 f(t + dt, Y)    (A read through `a`)
   OP_RKG,        // generic App. A stage: out = ccur Y + sum_j hc_j h_j + cdt dt f(t + c dt, Y)
+  OP_ITP1R,      // as OP_ITP1 with Y already holding phi (diagonal half-step applied by PT_PHI)
 };
 constexpr int RKG_MAX_HIST = 5;
 
@@ -244,7 +245,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   constexpr bool HOC = (STN != 7);
   using D = typename std::conditional<STN == 27, SegC27,
                                       typename std::conditional<STN == 19, SegHoc, SegNb>::type>::type;
-  static_assert(!REAL || OP == OP_ITP1 || OP == OP_ITP2 || OP == OP_OBS, "real state: ITP and OBS only");
+  static_assert(!REAL || OP == OP_ITP1 || OP == OP_ITP1R || OP == OP_ITP2 || OP == OP_OBS,
+                "real state: ITP and OBS only");
   constexpr int CH = BLOCK * SPT;
   constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
   constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4) || OP == OP_RK2F || OP == OP_RK4F || OP == OP_RKG;
@@ -302,16 +304,17 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   auto at1 = [&](auto* base, int i) { return ld<NT>(ptr(base, i)); };         // touched once
   auto put = [&](auto* base, int i, const auto& v) { st<NT>(ptr(base, i), v); };
   // value of the stencil input at compact site s (ITP1 applies the diagonal half-step on load)
+  constexpr bool diag_on_load = (OP == OP_ITP1);
   auto load = [&](int s) -> S {
     S v = at(Yin, s);
     if constexpr (REAL) {
-      if (OP == OP_ITP1) {
+      if (diag_on_load) {
         const R vr = v * scale;
         v = vr * (at(a.prop, s) * (R(1) - hg * vr * vr));
       } else if (OP == OP_OBS) {
         v = v * scale;
       }
-    } else if (OP == OP_ITP1) {
+    } else if (diag_on_load) {
       const R p = at(a.prop, s);
       const R vr = v.x * scale, vi = v.y * scale;
       const R f = p * (R(1) - hg * (vr * vr + vi * vi));
@@ -525,7 +528,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       if constexpr (REAL) {
         // T~ y at s, real state
         const R lt = latr + wzm * zm + wzp * zp + wc * yc;
-        if constexpr (OP == OP_ITP1) {
+        if constexpr (OP == OP_ITP1 || OP == OP_ITP1R) {
           put(Yout, s, yc - R(0.5) * dt * lt);
         } else if constexpr (OP == OP_ITP2) {
           const R q = yc - R(0.5) * dt * lt;
@@ -545,7 +548,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       const R lr = latr + wzm * zm.x + wzp * zp.x + wc * yc.x;
       const R li = lati + wzm * zm.y + wzp * zp.y + wc * yc.y;
 
-      if constexpr (OP == OP_ITP1) {
+      if constexpr (OP == OP_ITP1 || OP == OP_ITP1R) {
         put(a.out, s, cmk<R>(yc.x - R(0.5) * dt * lr, yc.y - R(0.5) * dt * li));
       } else if constexpr (OP == OP_ITP2) {
         const R qr = yc.x - R(0.5) * dt * lr, qi = yc.y - R(0.5) * dt * li;
@@ -731,14 +734,18 @@ static PassArgs<R> pass_args() {
 
 template <typename R>
 hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw, const void* prop, void* tmp,
-                         bool real, hipStream_t s) {
+                         bool real, hipStream_t s, bool raw_input) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
   a.Y = (const C*)psi_raw;
   a.prop = (const R*)prop;
   a.out = (C*)tmp;
   timing_before(FAM_ITP1, s);
-  hipError_t e = real ? dispatch_pass<R, OP_ITP1, true>(p, cfg, a, s) : dispatch_pass<R, OP_ITP1>(p, cfg, a, s);
+  hipError_t e;
+  if (raw_input)
+    e = real ? dispatch_pass<R, OP_ITP1R, true>(p, cfg, a, s) : dispatch_pass<R, OP_ITP1R>(p, cfg, a, s);
+  else
+    e = real ? dispatch_pass<R, OP_ITP1, true>(p, cfg, a, s) : dispatch_pass<R, OP_ITP1>(p, cfg, a, s);
   timing_after(FAM_ITP1, s);
   return e;
 }
@@ -892,13 +899,16 @@ hipError_t run_adj_stage(const Plan& p, const LaunchConfig& cfg, int stage, cons
 // ---------------------------------------------------------------------------
 // pointwise passes (one workgroup of 256 lanes per chunk)
 // ---------------------------------------------------------------------------
-enum PointOp { PT_PROP = 0, PT_SCALE, PT_OVERLAP, PT_SEED, PT_RANGE, PT_SCALE_REAL };
+// PT_PHI / PT_PHI_REAL: the first diagonal half-step of an imaginary-time
+// step on its own, phi = s psi P (1 - g |s psi|^2 dt/2) (P read from `field`)
+enum PointOp { PT_PROP = 0, PT_SCALE, PT_OVERLAP, PT_SEED, PT_RANGE, PT_SCALE_REAL, PT_PHI, PT_PHI_REAL };
 
 template <typename R> struct PointArgs {
   using C = typename CT<R>::T;
   const C* a;
   const C* b;
   const R* field;
+  const R* rin;
   C* out;
   R* rout;
 };
@@ -926,7 +936,8 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   }
   R sc = R(1);
   double cre = 0.0, cim = 0.0;
-  if (OP == PT_SCALE || OP == PT_SCALE_REAL) sc = (R)pl.out[ch.inst].scale;
+  if (OP == PT_SCALE || OP == PT_SCALE_REAL || OP == PT_PHI || OP == PT_PHI_REAL) sc = (R)pl.out[ch.inst].scale;
+  const R hg = (R)ip.g * (R)ip.dt * R(0.5);
   if (OP == PT_SEED) {
     cre = pl.out[ch.inst].ov_re;
     cim = pl.out[ch.inst].ov_im;
@@ -941,6 +952,14 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
       a.out[s] = cmk<R>(v.x * sc, v.y * sc);
     } else if constexpr (OP == PT_SCALE_REAL) {
       a.rout[s] = a.rout[s] * sc;
+    } else if constexpr (OP == PT_PHI) {
+      const C v = a.a[s];
+      const R vr = v.x * sc, vi = v.y * sc;
+      const R f = a.field[s] * (R(1) - hg * (vr * vr + vi * vi));
+      a.out[s] = cmk<R>(vr * f, vi * f);
+    } else if constexpr (OP == PT_PHI_REAL) {
+      const R vr = a.rin[s] * sc;
+      a.rout[s] = vr * (a.field[s] * (R(1) - hg * vr * vr));
     } else if constexpr (OP == PT_OVERLAP) {
       const C x = a.a[s], y = a.b[s];
       acc[0] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
@@ -997,6 +1016,7 @@ template <typename R> static PointArgs<R> point_args() {
   PointArgs<R> a;
   a.a = a.b = nullptr;
   a.field = nullptr;
+  a.rin = nullptr;
   a.out = nullptr;
   a.rout = nullptr;
   return a;
@@ -1019,6 +1039,21 @@ hipError_t run_apply_scale(const Plan& p, const LaunchConfig&, void* psi, bool r
   }
   a.out = (typename CT<R>::T*)psi;
   return launch_point<R, PT_SCALE>(p, a, s);
+}
+
+template <typename R>
+hipError_t run_itp_phi(const Plan& p, const LaunchConfig&, const void* psi, const void* prop, void* phi, bool real,
+                       hipStream_t s) {
+  PointArgs<R> a = point_args<R>();
+  a.field = (const R*)prop;
+  if (real) {
+    a.rin = (const R*)psi;
+    a.rout = (R*)phi;
+    return launch_point<R, PT_PHI_REAL>(p, a, s);
+  }
+  a.a = (const typename CT<R>::T*)psi;
+  a.out = (typename CT<R>::T*)phi;
+  return launch_point<R, PT_PHI>(p, a, s);
 }
 
 template <typename R>
@@ -1310,7 +1345,9 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
 // explicit instantiations
 #define GPE_INST(R)                                                                                            \
   template hipError_t run_itp_pass1<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
-                                       bool, hipStream_t);                                                   \
+                                       bool, hipStream_t, bool);                                             \
+  template hipError_t run_itp_phi<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*, bool,  \
+                                     hipStream_t);                                                           \
   template hipError_t run_itp_pass2<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
                                        bool, hipStream_t);                                                   \
   template hipError_t run_rk_stage<R>(const Plan&, const LaunchConfig&, int, bool, const void*, const void*, \
