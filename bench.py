@@ -344,6 +344,38 @@ def bench_hoc(args, dev, report):
     torch.cuda.empty_cache()
 
 
+def bench_c1(args, dev, report):
+    """C1, the tiny shell (40,600 sites, 500 imaginary-time steps, complex128):
+    it fits in L2 / Infinity Cache, so only the update rate is reported, beside
+    the FP64 oracle running the same 500 steps on one host core."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    from workloads import configs
+    w = configs.c1()
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    V = torch.tensor(w.field, dtype=torch.float64, device=dev)
+    psi = torch.tensor(w.psi0, dtype=torch.complex128, device=dev)
+    pot = Potential.static(V)
+    g.imag_time(psi.clone(), pot, w.g, w.dt, 5, observe=False)      # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    obs = g.imag_time(psi, pot, w.g, w.dt, w.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    out = {"workload": w.name, "n_active": w.n_active, "steps": w.steps, "s": el,
+           "site_updates_per_s": w.n_active * w.steps / el, "energy": obs["energy"]}
+    if not args.no_cpu:
+        from oracle import itp, operator as op
+        from workloads import site_linear_index
+        T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, w.runs))
+        t = time.perf_counter()
+        itp.imaginary_time(T, w.psi0, w.field, w.g, w.dt, w.box.dV, w.steps)
+        ct = time.perf_counter() - t
+        out["oracle_1core_site_updates_per_s"] = w.n_active * w.steps / ct
+    report["c1"] = out
+    log(f"[bench] C1: {out['site_updates_per_s']:.3g} site-updates/s on the GPU")
+
+
 def cpu_baseline(args):
     """The FP64 oracle, single-threaded, on a slab of the headline workload:
     the active sites of x-planes [448, 576) of the 1024 x 1024 x 512 grid
@@ -556,6 +588,7 @@ def main():
         log("[bench] restage done")
         bench_hoc(args, dev, report)
         log("[bench] 19-point stencil done")
+        bench_c1(args, dev, report)
     if args.c5 > 0:
         bench_c5(args, dev, report)
         log("[bench] C5 precision study done")
@@ -599,7 +632,7 @@ def main():
     if "c64" in report:
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
-    for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "restage_c2", "hoc19_c2",
+    for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "restage_c2", "hoc19_c2", "c1",
                 "precision_c5"):
         if key in report:
             line[key] = report[key]
