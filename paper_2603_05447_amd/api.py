@@ -502,6 +502,31 @@ class FidelityGrad(torch.autograd.Function):
         return (grad_out * grad,) + (None,) * 10
 
 
+class BatchFidelityGrad(torch.autograd.Function):
+    """Per-instance losses 1 - |<target_i|psi_i(T)>|^2 of a batch as a
+    differentiable function of a (n_instances, n_knots) tensor of knot values
+    (all instances share one knot count); one ABI call runs the batched
+    forward and adjoint sweeps and the gradients are cached for backward."""
+
+    @staticmethod
+    def forward(ctx, knots: torch.Tensor, batch: "Batch", psi0: torch.Tensor, target: torch.Tensor,
+                field: torch.Tensor, omegas, knot_ts, gs, dts, steps: int, ckpt_every: int = 0,
+                use_graph: bool = False):
+        kd = knots.detach().to("cpu", torch.float64).numpy()
+        if kd.ndim != 2 or kd.shape[0] != len(batch.grids):
+            raise ValueError("knots must be (n_instances, n_knots)")
+        ramps = [(omegas[i], knot_ts[i], kd[i]) for i in range(kd.shape[0])]
+        loss, grads = batch.fidelity_grad(psi0, target, field, ramps, gs, dts, steps, 0.0, ckpt_every,
+                                          use_graph=use_graph)
+        ctx.save_for_backward(torch.as_tensor(np.stack(grads), dtype=knots.dtype, device=knots.device))
+        return torch.as_tensor(loss, dtype=knots.dtype, device=knots.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (grad,) = ctx.saved_tensors
+        return (grad_out[:, None] * grad,) + (None,) * 11
+
+
 def config_count() -> int:
     return int(L.load().gpe_config_count())
 

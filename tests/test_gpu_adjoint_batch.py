@@ -193,3 +193,22 @@ def test_autotune_cache_serves_grids_of_the_same_class():
     assert Case(small, "c128").grid.apply_tuned(_lib.GPE_C128) is None
     load_library().gpe_autotune_cache_clear()
     assert Case(w, "c128").grid.apply_tuned(_lib.GPE_C128) is None
+
+
+def test_batch_autograd_function():
+    import torch
+    from paper_2603_05447_amd import BatchFidelityGrad
+    ws = _instances(3, 8)
+    b, psi, field, ramps = _batch(ws, "c128")
+    tg = [_target(w, 20 + i) for i, w in enumerate(ws)]
+    target = torch.tensor(np.concatenate(tg), dtype=torch.complex128, device="cuda:0")
+    knots = torch.tensor(np.stack([w.knot_delta for w in ws]), dtype=torch.float64, requires_grad=True)
+    loss = BatchFidelityGrad.apply(knots, b, psi, target, field, [w.omega for w in ws], [w.knot_t for w in ws],
+                                   [w.g for w in ws], [w.dt for w in ws], 8)
+    weights = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64)
+    (weights * loss).sum().backward()
+    for i, w in enumerate(ws):
+        c = Case(w, "c128")
+        ol, og, _ = adj.fidelity_grad(c.T, c.opot, w.g, w.dt, 0.0, 8, w.psi0, tg[i], w.box.dV)
+        assert abs(loss[i].item() - ol) <= 1e-10
+        assert np.max(np.abs(knots.grad[i].numpy() - weights[i].item() * og)) <= 1e-9 * np.max(np.abs(og))
