@@ -10,7 +10,8 @@ site updates of both phases per second, inputs resident in HBM.
 
 Also reported: the complex64 form (FP32 stencil, FP64 reductions), the
 adjoint gradient rate on the 256^3 hollowing ramp (grads/s vs plain FP64
-forward runs), the 64-instance batched sweep (hipGraph), per-kernel timing
+forward runs), the 64-instance batched sweep (hipGraph; forward, and forward
+plus adjoint in complex64 against complex128), per-kernel timing
 (HIP events on the launch stream) with the roofline of the dominant kernel,
 and the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
@@ -486,6 +487,42 @@ def bench_batched(args, dev, report):
             "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 4, scheme) for i in range(1, 5)) * b.total * args.batch_steps
             / el / 1e9,
             "norm_min": min(o["norm"] for o in obs), "norm_max": max(o["norm"] for o in obs)}
+    # forward + adjoint of every instance in one batched call (sqrt(N) checkpoints), complex64 storage
+    # against complex128 throughout: loss and 8 knot gradients per instance
+    rng = np.random.default_rng(4242)
+    tg = []
+    for w in ws:
+        t_ = w.psi0 * np.exp(1j * rng.uniform(0.0, 0.3, w.n_active))
+        tg.append(t_ / np.sqrt(np.sum(np.abs(t_) ** 2) * w.box.dV))
+    tg = np.concatenate(tg)
+    psi0 = np.concatenate([w.psi0 for w in ws])
+    adj = {}
+    for name, cdt, rdt in (("c64", torch.complex64, torch.float32), ("c128", torch.complex128, torch.float64)):
+        p0 = torch.tensor(psi0, dtype=cdt, device=dev)
+        tt = torch.tensor(tg, dtype=cdt, device=dev)
+        fd = torch.tensor(np.concatenate([w.field for w in ws]), dtype=rdt, device=dev)
+        b.fidelity_grad(p0, tt, fd, ramps, gs, dts, 10, use_graph=True)      # warmup
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        loss, grads = b.fidelity_grad(p0, tt, fd, ramps, gs, dts, args.batch_steps, use_graph=True)
+        el = time.perf_counter() - t
+        pf = p0.clone()
+        b.real_time(pf, fd, ramps, gs, dts, 5, use_graph=True, observe=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        b.real_time(pf, fd, ramps, gs, dts, args.batch_steps, use_graph=True, observe=False)
+        torch.cuda.synchronize()
+        el_f = time.perf_counter() - t
+        adj[name] = {"s": el, "instance_grads_per_s": len(ws) / el, "forward_s": el_f,
+                     "grad_over_forward_time": el / el_f, "loss": np.asarray(loss), "grads": np.stack(grads)}
+        del p0, tt, fd, pf
+    g64, g128 = adj["c64"].pop("grads"), adj["c128"].pop("grads")
+    l64, l128 = adj["c64"].pop("loss"), adj["c128"].pop("loss")
+    adj["c64_vs_c128"] = {
+        "grad_rel_err_max": float(np.max(np.abs(g64 - g128).max(axis=1) / np.abs(g128).max(axis=1))),
+        "grad_rel_err_median": float(np.median(np.abs(g64 - g128).max(axis=1) / np.abs(g128).max(axis=1))),
+        "loss_abs_err_max": float(np.max(np.abs(l64 - l128)))}
+    out["forward_adjoint"] = adj
     report["batched_c4"] = {"instances": len(ws), "total_sites": b.total, "steps": args.batch_steps, **out}
     del b, grids, psi, field, work
     torch.cuda.empty_cache()
