@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GPE_ABI_VERSION 1
+#define GPE_ABI_VERSION 2
 #define GPE_MAX_KNOTS 32
 
 typedef enum {
@@ -342,20 +342,27 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch batch, gpe_dtype dtype, const void*
 
 /* ---- Launch configuration and autotuning -----------------------------
  * A launch configuration is an index into the table of compiled kernel
- * variants: workgroup size x sites per lane, the order in which chunks are
+ * variants: workgroup size (64 to 1024 lanes) x sites per lane (1 to 8), the
+ * order in which chunks are
  * handed to the XCDs (0 array order, 1 contiguous eighths, 2/3 blocks of
  * 64/256 chunks dealt round-robin, 4 the x-th eighth of every x-plane's
  * chunks to XCD x, plane after plane), and the
  * RK4 storage scheme (0: the App. A form, whose last stage reads y0, y2, y3;
  * 1: the second stage also stores A = (-y0 + y2 + 2 y3)/3 so the last stage
  * reads A alone, 16 fewer bytes per site per complex128 step; both give the
- * RK4 result up to rounding), and whether streams touched once per pass use
- * non-temporal loads/stores.  gpe_config_count/gpe_config_describe list
+ * RK4 result up to rounding), whether streams touched once per pass use
+ * non-temporal loads/stores, and whether the chunk's stencil input is staged
+ * in LDS (1: the k-1 / k+1 and in-window j-1 / j+1 neighbours come from LDS;
+ * 0: every neighbour is loaded from global memory and the pass has one
+ * workgroup barrier fewer).  Every variant computes the same stencil
+ * arithmetic; results differ only by the rounding of the FP64 reductions,
+ * whose grouping follows the chunk size, and of the RK4 storage scheme.
+ * gpe_config_count/gpe_config_describe list
  * them; variant 0 is the default.  The grid's (or batch's) configuration is
  * used by every later call on it. */
 int32_t gpe_config_count(void);
 gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* sites_per_lane, int32_t* xcd_map,
-                               int32_t* rk_scheme, int32_t* nontemporal);
+                               int32_t* rk_scheme, int32_t* nontemporal, int32_t* lds_stage);
 gpe_status gpe_grid_set_config(gpe_grid grid, int32_t config);
 gpe_status gpe_grid_get_config(gpe_grid grid, int32_t* config);
 gpe_status gpe_batch_set_config(gpe_batch batch, int32_t config);

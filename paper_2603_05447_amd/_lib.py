@@ -85,7 +85,7 @@ SIGNATURES = {
     "gpe_batch_fidelity_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, C.POINTER(Ramp), C.POINTER(Params),
                                           C.c_double, _i64, _i64, _i32, _vp, C.c_size_t, _vp, _pd, _pd]),
     "gpe_config_count": (_i32, []),
-    "gpe_config_describe": (C.c_int, [_i32] + [C.POINTER(_i32)] * 5),
+    "gpe_config_describe": (C.c_int, [_i32] + [C.POINTER(_i32)] * 6),
     "gpe_grid_set_config": (C.c_int, [_vp, _i32]),
     "gpe_grid_get_config": (C.c_int, [_vp, C.POINTER(_i32)]),
     "gpe_batch_set_config": (C.c_int, [_vp, _i32]),

@@ -532,10 +532,11 @@ def config_count() -> int:
 
 
 def config_describe(i: int):
-    b, s, x, r, nt = (C.c_int32() for _ in range(5))
-    check(L.load().gpe_config_describe(int(i), C.byref(b), C.byref(s), C.byref(x), C.byref(r), C.byref(nt)))
+    b, s, x, r, nt, st = (C.c_int32() for _ in range(6))
+    check(L.load().gpe_config_describe(int(i), C.byref(b), C.byref(s), C.byref(x), C.byref(r), C.byref(nt),
+                                       C.byref(st)))
     return {"block": b.value, "sites_per_lane": s.value, "xcd_map": x.value, "rk_scheme": r.value,
-            "nontemporal": nt.value}
+            "nontemporal": nt.value, "lds_stage": st.value}
 
 
 class KernelTimer:

@@ -784,11 +784,13 @@ gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
     c.cfg.block = 256;
     c.cfg.spt = 2;
     c.cfg.nt = 0;
+    c.cfg.stage = 1;
   }
   if (hoc) {
     // the 19-point kernels are compiled for 256 lanes x 1 site
     c.cfg.block = 256;
     c.cfg.spt = 1;
+    c.cfg.stage = 1;
   }
   gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs, P->stencil);
   if (st != GPE_OK) return st;
@@ -1867,7 +1869,7 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi
 int32_t gpe_config_count(void) { return config_count(); }
 
 gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* spt, int32_t* xcd, int32_t* rk_scheme,
-                               int32_t* nontemporal) {
+                               int32_t* nontemporal, int32_t* lds_stage) {
   if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
   LaunchConfig c = config_get(config);
   if (block) *block = c.block;
@@ -1875,6 +1877,7 @@ gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* spt, int
   if (xcd) *xcd = c.xcd;
   if (rk_scheme) *rk_scheme = c.scheme;
   if (nontemporal) *nontemporal = c.nt;
+  if (lds_stage) *lds_stage = c.stage;
   return GPE_OK;
 }
 

@@ -85,12 +85,16 @@ struct Plan {
 //             and forms A + y4/3 + dt/6 k4; y4 reuses y2's buffer (224 B/site/step)
 //   nt: streams touched once per pass (own-site inputs, outputs) use
 //       non-temporal loads and stores
+//   stage: the chunk's stencil input is staged in LDS, which supplies the
+//       k-1 / k+1 neighbours and the j-1 / j+1 ones inside the window; 0 loads
+//       every neighbour from global memory (L1/L2 hits) and skips the barrier
 struct LaunchConfig {
   int block;
   int spt;
   int xcd;
   int scheme;
   int nt;
+  int stage;
 };
 int config_count();
 LaunchConfig config_get(int i);

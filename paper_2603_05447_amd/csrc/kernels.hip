@@ -81,12 +81,14 @@ template <bool NT, typename T> __device__ __forceinline__ void st(T* p, const T&
 // plane-eighths order (mode 4) turns the i-1 / i+1 neighbour reads into L2
 // hits and beats array order by about 3 %; the contiguous-eighths order also
 // removes those misses but is slower, and non-temporal single-use streams
-// beat cached ones.
+// beat cached ones.  Every shape holds at least 256 sites per chunk (the
+// grid's partial-sum scratch is sized for that).
 static const LaunchConfig kConfigs[] = {
-    {256, 2, 4, 1, 1}, {512, 1, 0, 1, 1}, {256, 1, 0, 1, 1}, {256, 4, 0, 1, 1}, {512, 2, 0, 1, 1},
-    {1024, 1, 0, 1, 1}, {256, 2, 0, 1, 0}, {512, 1, 0, 1, 0}, {256, 2, 1, 1, 1}, {256, 2, 0, 0, 1},
-    {256, 2, 2, 1, 1}, {256, 2, 3, 1, 1}, {512, 1, 2, 1, 1}, {256, 2, 0, 1, 1}, {512, 1, 4, 1, 1},
-    {256, 4, 4, 1, 1},
+    {256, 2, 4, 1, 1, 1}, {512, 1, 0, 1, 1, 1}, {256, 1, 0, 1, 1, 1}, {256, 4, 0, 1, 1, 1}, {512, 2, 0, 1, 1, 1},
+    {1024, 1, 0, 1, 1, 1}, {256, 2, 0, 1, 0, 1}, {512, 1, 0, 1, 0, 1}, {256, 2, 1, 1, 1, 1}, {256, 2, 0, 0, 1, 1},
+    {256, 2, 2, 1, 1, 1}, {256, 2, 3, 1, 1, 1}, {512, 1, 2, 1, 1, 1}, {256, 2, 0, 1, 1, 1}, {512, 1, 4, 1, 1, 1},
+    {256, 4, 4, 1, 1, 1}, {64, 8, 4, 1, 1, 1},   {128, 4, 4, 1, 1, 1}, {256, 8, 4, 1, 1, 1}, {256, 2, 4, 1, 1, 0},
+    {256, 4, 4, 1, 1, 0},
 };
 int config_count() { return (int)(sizeof(kConfigs) / sizeof(kConfigs[0])); }
 LaunchConfig config_get(int i) { return kConfigs[i]; }
@@ -238,7 +240,7 @@ template <typename R> struct PassArgs {
 // STN: the stencil.  7 is App. B eq. (B1); 19 is the higher-order compact
 // stencil of eq. (B2), whose segment descriptors hold sixteen lateral taps
 // (SegHoc); 27 is the cubic stencil, which adds the eight corners (SegC27).
-template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT, bool REAL, int STN>
+template <typename R, int BLOCK, int SPT, int OP, bool OFF32, bool NT, bool REAL, int STN, bool STG>
 __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R> a) {
   using C = typename CT<R>::T;
   using S = typename std::conditional<REAL, R, C>::type;   // stencil state type
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
                                       typename std::conditional<STN == 19, SegHoc, SegNb>::type>::type;
   static_assert(!REAL || OP == OP_ITP1 || OP == OP_ITP1R || OP == OP_ITP2 || OP == OP_OBS,
                 "real state: ITP and OBS only");
+  static_assert(STG || STN == 7, "the 19- and 27-point passes always stage");
   constexpr int CH = BLOCK * SPT;
   constexpr bool ADJ = (OP >= OP_ADJ4 && OP <= OP_ADJ1);
   constexpr bool RK = (OP >= OP_RK1 && OP <= OP_RK4) || OP == OP_RK2F || OP == OP_RK4F || OP == OP_RKG;
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   constexpr bool NEED_L = (OP == OP_ADJ3 || OP == OP_ADJ2 || OP == OP_ADJ1);
   constexpr bool NEED_F = (RK || OP == OP_OBS || ADJ);
   constexpr bool NEED_P = (OP == OP_ITP2);
-  __shared__ S sy[CH + 2];
+  __shared__ S sy[STG ? CH + 2 : 1];
   __shared__ double red[BLOCK / 64][NR > 0 ? NR : 1];
   const S* const Yin = reinterpret_cast<const S*>(a.Y);
   S* const Yout = reinterpret_cast<S*>(a.out);
@@ -343,10 +346,15 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   else if constexpr (STN == 19) nsrc = pl.hocnb + ch.seg_begin;
   else nsrc = pl.nbs + ch.seg_begin;
   const int t0 = threadIdx.x;
-  // a chunk holds at most MAX_CHUNK_SEGS (< 256 <= BLOCK) segments, so one
-  // slot per lane covers its table
-  sh[min(t0, ch.seg_count)] = hsrc[min(t0, ch.seg_count)];
-  snb[min(t0, ch.seg_count - 1)] = nsrc[min(t0, ch.seg_count - 1)];
+  // a chunk holds at most MAX_CHUNK_SEGS (255) segments: one slot per lane
+  // covers its table for 256 lanes or more, TBL slots for fewer
+  constexpr int TBL = BLOCK > MAX_CHUNK_SEGS ? 1 : (MAX_CHUNK_SEGS + BLOCK) / BLOCK;
+#pragma unroll
+  for (int q = 0; q < TBL; ++q) {
+    const int t = t0 + q * BLOCK;
+    sh[min(t, ch.seg_count)] = hsrc[min(t, ch.seg_count)];
+    snb[min(t, ch.seg_count - 1)] = nsrc[min(t, ch.seg_count - 1)];
+  }
   __builtin_amdgcn_sched_barrier(0);
 
   // Lanes past the end of the chunk load its last site (always valid) and
@@ -384,14 +392,27 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     }
   }
   __builtin_amdgcn_sched_barrier(0);
-  S stg[NSTG];
+  S stg[STG ? NSTG : 1];
+  // without LDS staging: the lane's own sites and their k-1 / k+1 neighbours
+  // (the site itself stands in past the instance ends, where the weight is 0)
+  S own[STG ? 1 : SPT], kmv[STG ? 1 : SPT], kpv[STG ? 1 : SPT];
+  if constexpr (STG) {
 #pragma unroll
-  for (int q = 0; q < NSTG; ++q) {
-    const int t = threadIdx.x + q * BLOCK;
-    const int sidx = ch.site_begin - 1 + t;
-    const bool in = (t < ch.count + 2) && sidx >= ib && sidx < ie;
-    stg[q] = load(in ? sidx : last);
-    if (!in) stg[q] = zero;
+    for (int q = 0; q < NSTG; ++q) {
+      const int t = threadIdx.x + q * BLOCK;
+      const int sidx = ch.site_begin - 1 + t;
+      const bool in = (t < ch.count + 2) && sidx >= ib && sidx < ie;
+      stg[q] = load(in ? sidx : last);
+      if (!in) stg[q] = zero;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < SPT; ++m) {
+      const int sc = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
+      own[m] = load(sc);
+      kmv[m] = load(sc > ib ? sc - 1 : sc);
+      kpv[m] = load(sc + 1 < ie ? sc + 1 : sc);
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
 
@@ -459,8 +480,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     xm[m] = load(s + nb.xm);
     xp[m] = load(s + nb.xp);
     const int tm = s - wbase + nb.ym, tp = s - wbase + nb.yp;
-    tym[m] = (tm >= 0 && tm < ch.count + 2) ? tm : -1;
-    typ[m] = (tp >= 0 && tp < ch.count + 2) ? tp : -1;
+    tym[m] = (STG && tm >= 0 && tm < ch.count + 2) ? tm : -1;
+    typ[m] = (STG && tp >= 0 && tp < ch.count + 2) ? tp : -1;
     ym[m] = zero;
     yp[m] = zero;
     if (tym[m] < 0) ym[m] = load(s + nb.ym);
@@ -474,14 +495,16 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   __builtin_amdgcn_sched_barrier(0);
 
   // the staged stencil input becomes visible to the neighbouring lanes
+  if constexpr (STG) {
 #pragma unroll
-  for (int q = 0; q < NSTG; ++q) {
-    const int t = threadIdx.x + q * BLOCK;
-    if (t < CH + 2) sy[t] = stg[q];
+    for (int q = 0; q < NSTG; ++q) {
+      const int t = threadIdx.x + q * BLOCK;
+      if (t < CH + 2) sy[t] = stg[q];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 
   // ---- phase B2: arithmetic and stores ----
   double acc[NR > 0 ? NR : 1];
@@ -495,8 +518,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       const int s = ch.site_begin + l;
       const SegHead hd = sh[js[m]];
       const int send = sh[js[m] + 1].start;
-      const S yc = sy[l + 1];
-      const S zm = sy[l], zp = sy[l + 2];
+      const S yc = STG ? sy[l + 1] : own[m];
+      const S zm = STG ? sy[l] : kmv[m], zp = STG ? sy[l + 2] : kpv[m];
       // own-column k-1 / k+1 weight and the centre weight of the stencil
       const R wz = HOC ? (R)ip.qz : cz, wc = HOC ? (R)ip.qd : cd;
       const R wzm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? R(0) : wz;
@@ -669,17 +692,35 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   }
 }
 
+// Shapes of 256 or more lanes and up to 4 sites per lane are compiled with and
+// without non-temporal streams; the smaller workgroups and 8 sites per lane
+// only with them, and the variant without LDS staging for 256 x 2 and 256 x 4.
 template <int BLOCK, int SPT, typename R, int OP, bool REAL>
 static hipError_t launch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
+  constexpr bool BOTH_NT = BLOCK >= 256 && SPT <= 4;
+  constexpr bool NO_STAGE = BLOCK == 256 && (SPT == 2 || SPT == 4);
   const size_t dyn = (size_t)p.max_seg * sizeof(SegNb) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
-  if (p.off32 && cfg.nt)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL, 7>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p,
+  if (!p.off32) {
+    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL, 7, true>), dim3(p.n_chunks), dim3(256), dyn, s, p,
                        a);
-  else if (p.off32)
-    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false, REAL, 7>), dim3(p.n_chunks), dim3(BLOCK), dyn, s, p,
-                       a);
-  else
-    hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL, 7>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+  } else if (!cfg.stage) {
+    if constexpr (NO_STAGE) {
+      if (!cfg.nt) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL, 7, false>), dim3(p.n_chunks), dim3(BLOCK), dyn,
+                         s, p, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if (cfg.nt) {
+    hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, true, REAL, 7, true>), dim3(p.n_chunks), dim3(BLOCK), dyn, s,
+                       p, a);
+  } else {
+    if constexpr (BOTH_NT)
+      hipLaunchKernelGGL((k_pass<R, BLOCK, SPT, OP, true, false, REAL, 7, true>), dim3(p.n_chunks), dim3(BLOCK), dyn,
+                         s, p, a);
+    else
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -691,9 +732,11 @@ static hipError_t launch_pass_hoc(const Plan& p, const LaunchConfig& cfg, const 
   if (!p.off32 || cfg.block != 256 || cfg.spt != 1) return hipErrorInvalidValue;
   const size_t dyn = (size_t)p.max_seg * sizeof(D) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
   if (cfg.nt)
-    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, true, REAL, STN>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, true, REAL, STN, true>), dim3(p.n_chunks), dim3(256), dyn, s, p,
+                       a);
   else
-    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, false, REAL, STN>), dim3(p.n_chunks), dim3(256), dyn, s, p, a);
+    hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, false, REAL, STN, true>), dim3(p.n_chunks), dim3(256), dyn, s, p,
+                       a);
   return hipGetLastError();
 }
 
@@ -710,6 +753,9 @@ static hipError_t dispatch_pass(const Plan& p, const LaunchConfig& cfg, const Pa
   if (cfg.block == 512 && cfg.spt == 1) return launch_pass<512, 1, R, OP, REAL>(p, cfg, a, s);
   if (cfg.block == 512 && cfg.spt == 2) return launch_pass<512, 2, R, OP, REAL>(p, cfg, a, s);
   if (cfg.block == 1024 && cfg.spt == 1) return launch_pass<1024, 1, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 256 && cfg.spt == 8) return launch_pass<256, 8, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 128 && cfg.spt == 4) return launch_pass<128, 4, R, OP, REAL>(p, cfg, a, s);
+  if (cfg.block == 64 && cfg.spt == 8) return launch_pass<64, 8, R, OP, REAL>(p, cfg, a, s);
   return hipErrorInvalidValue;
 }
 

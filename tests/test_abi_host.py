@@ -35,8 +35,22 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
         assert n in _lib.SIGNATURES, f"{n} has no ctypes signature"
-    assert lib.gpe_abi_version() == 1
+    assert lib.gpe_abi_version() == 2
     assert lib.gpe_config_count() >= 6
+
+
+def test_launch_variant_table_spans_the_tuning_space(lib):
+    """The tuner's search space: 64 to 1024 lanes, 1 to 8 sites per lane, LDS
+    staging on and off; every shape holds at least 256 sites per chunk."""
+    from paper_2603_05447_amd import config_describe
+    ds = [config_describe(k) for k in range(lib.gpe_config_count())]
+    assert {d["block"] for d in ds} == {64, 128, 256, 512, 1024}
+    assert {d["sites_per_lane"] for d in ds} == {1, 2, 4, 8}
+    assert {d["lds_stage"] for d in ds} == {0, 1}
+    assert all(d["block"] * d["sites_per_lane"] >= 256 for d in ds)
+    assert ds[0] == {"block": 256, "sites_per_lane": 2, "xcd_map": 4, "rk_scheme": 1, "nontemporal": 1,
+                     "lds_stage": 1}
+    assert len({tuple(d.values()) for d in ds}) == len(ds)
 
 
 def _expected_neighbours(box, runs):

@@ -140,6 +140,26 @@ def test_every_launch_config_gives_the_same_result():
             assert rel_l2(out, base) <= 1e-13, k
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_every_launch_config_matches_the_oracle_on_a_fragmented_mask(dtype):
+    """Every launch variant (64 to 1024 lanes, 1 to 8 sites per lane, with and
+    without LDS staging, every chunk order) against the oracle on a random
+    mask whose chunks are cut at the 255-segment limit and end in ragged
+    tails: imaginary time, then real time from its result."""
+    from paper_2603_05447_amd import config_count
+    w = configs.random_mask_problem(n=(18, 20, 22), density=0.5, seed=12)
+    c0 = Case(w, dtype)
+    ref, _ = itp.imaginary_time(c0.T, w.psi0, w.field, w.g, 2e-3, w.box.dV, 4)
+    ref = rt.real_time(c0.T, ref, c0.opot, w.g, 1e-3, 0.0, 4)
+    for k in range(config_count()):
+        c = Case(w, dtype, config=k)
+        psi = c.psi()
+        c.grid.imag_time(psi, c.pot, w.g, 2e-3, 4, observe=False)
+        c.grid.real_time(psi, c.pot, w.g, 1e-3, 4, observe=False)
+        err = rel_l2(psi.cpu().numpy(), ref)
+        assert err <= TOL[dtype], (k, err)
+
+
 def test_runs_are_bitwise_reproducible():
     w = configs.small_rf_ramp(n=28)
     outs = []
