@@ -548,6 +548,7 @@ def bench_c5(args, dev, report):
         pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
         g.real_time(psi, pot, w.g, w.dt, 2, observe=False)
         psi.copy_(torch.tensor(w.psi0, dtype=cdt, device=dev))
+        e0 = g.observe(psi, pot, 0.0, w.g)["energy"]
         torch.cuda.synchronize()
         t = time.perf_counter()
         obs = g.real_time(psi, pot, w.g, w.dt, args.c5)
@@ -557,7 +558,7 @@ def bench_c5(args, dev, report):
                       "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 8 if dtype == "c128" else 4,
                                                  config_describe(g.get_config())["rk_scheme"]) for i in range(1, 5))
                       * w.n_active * args.c5 / el / 1e9,
-                      "norm_drift": obs["norm"] - n0, "energy": obs["energy"]}
+                      "norm_drift": obs["norm"] - n0, "energy_start": e0, "energy": obs["energy"]}
         del U, psi
         g.release_work()
         torch.cuda.empty_cache()
@@ -566,6 +567,40 @@ def bench_c5(args, dev, report):
     ov = np.vdot(b, a)
     out["c64_vs_c128_phase_aligned"] = float(1.0 - abs(ov) / (np.linalg.norm(a) * np.linalg.norm(b)))
     report["precision_c5"] = out
+
+
+def bench_c2_job(args, dev, report):
+    """The headline job end to end, in complex128 and complex64: the ground
+    state by imaginary time at Delta = 60, then RK4 real time after the
+    quench to Delta = 62 (dt = 2e-4 for both), with observables at the phase
+    boundaries and the complex64 final state against the complex128 one."""
+    import torch
+    out, finals = {}, {}
+    for dtype in ("c128", "c64"):
+        w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, dtype)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o_itp = g.imag_time(psi, pot_itp, w.g, w.dt, args.job_itp)
+        t_itp = time.perf_counter() - t
+        o0 = g.observe(psi, pot_rt, 0.0, w.g)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o_rt = g.real_time(psi, pot_rt, w.g, w.dt, args.job_rt)
+        t_rt = time.perf_counter() - t
+        finals[dtype] = psi.to(torch.complex128).cpu().numpy()
+        out[dtype] = {"imag_time_s": t_itp, "real_time_s": t_rt, "total_s": t_itp + t_rt,
+                      "site_updates_per_s": w.n_active * (args.job_itp + args.job_rt) / (t_itp + t_rt),
+                      "ground_state": {"norm": o_itp["norm"], "energy": o_itp["energy"], "mu": o_itp["mu"]},
+                      "real_time": {"energy_start": o0["energy"], "energy_end": o_rt["energy"],
+                                    "norm_end": o_rt["norm"]}}
+        log(f"[bench] job {dtype}: imaginary time {t_itp:.2f} s, real time {t_rt:.2f} s")
+        del g, U, psi
+        torch.cuda.empty_cache()
+    a, b = finals["c64"], finals["c128"]
+    out["c64_vs_c128_rel_l2"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out["c64_vs_c128_phase_aligned"] = float(1.0 - abs(np.vdot(b, a)) / (np.linalg.norm(a) * np.linalg.norm(b)))
+    report["job_c2"] = {"workload": "rf-bubble 1024x1024x512, 16,028,656 active sites, g=2000, dt=2e-4",
+                        "imag_time_steps": args.job_itp, "real_time_steps": args.job_rt, **out}
 
 
 def main():
@@ -584,6 +619,10 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--int-steps", type=int, default=100, help="steps per integrator in the RKHE3/RK4/RKCK leg")
     ap.add_argument("--c5", type=int, default=0, help="run the 60M-site FP32-vs-FP64 study for this many steps")
+    ap.add_argument("--job", action="store_true",
+                    help="also run the headline job end to end (imaginary then real time) in both precisions")
+    ap.add_argument("--job-itp", type=int, default=5000)
+    ap.add_argument("--job-rt", type=int, default=10000)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -629,6 +668,9 @@ def main():
     if args.c5 > 0:
         bench_c5(args, dev, report)
         log("[bench] C5 precision study done")
+    if args.job:
+        bench_c2_job(args, dev, report)
+        log("[bench] headline job done")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args)
@@ -670,7 +712,7 @@ def main():
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
     for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "restage_c2", "hoc19_c2", "c1",
-                "precision_c5"):
+                "precision_c5", "job_c2"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)
