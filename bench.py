@@ -138,6 +138,32 @@ def run_phase_timed(g, psi, pot_itp, pot_rt, w, k_itp, k_rt):
     return e0.elapsed_time(e1), e1.elapsed_time(e2)
 
 
+def achievable_copy_gbps(dev, mib: int = 1024, reps: int = 10) -> float:
+    """Bandwidth of the library's plain streaming copy (1 GiB read + 1 GiB
+    written), HIP events on the launch stream: the achievable ceiling the
+    passes are read against beside the 8 TB/s vendor peak."""
+    import torch
+    from paper_2603_05447_amd import stream_copy
+    src = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        stream_copy(src, dst)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        stream_copy(src, dst)
+    e1.record(s)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    ok = bool(torch.equal(src, dst))
+    del src, dst
+    torch.cuda.empty_cache()
+    if not ok:
+        raise RuntimeError("stream copy produced wrong bytes")
+    return 2.0 * (mib << 20) / (us * 1e-6) / 1e9
+
+
 def bench_c2(args, dev, dtype, report):
     import torch
     from paper_2603_05447_amd import KernelTimer
@@ -649,6 +675,8 @@ def main():
         torch.cuda.empty_cache()
     bench_c2(args, dev, "c128", report)
     log(f"[bench] c128 done: {report['c128']['site_updates_per_s']:.4g} site-updates/s")
+    copy_gbps = achievable_copy_gbps(dev)
+    log(f"[bench] streaming copy: {copy_gbps:.0f} GB/s")
     if not args.no_extras:
         bench_c2(args, dev, "c64", report)
         log(f"[bench] c64 done: {report['c64']['site_updates_per_s']:.4g} site-updates/s")
@@ -683,6 +711,7 @@ def main():
     traffic, tsrc = profiled_traffic(dom) if main_res["config"] == 0 else (None, None)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": traffic, "traffic_unit": "bytes/launch",
+                "achievable_copy_GBps": copy_gbps, "frac_of_copy": k["GBps"] / copy_gbps,
                 "traffic_source": tsrc, "algo_bytes_per_launch": k["algo_bytes_per_launch"],
                 "avg_launch_us": k["avg_us"], "launches": k["launches"]}
     line = {

@@ -394,6 +394,15 @@ int32_t gpe_timing_count(void);
 const char* gpe_timing_name(int32_t family);
 gpe_status gpe_timing_read(int32_t family, int64_t* launches, double* total_ms);
 
+/* A plain streaming copy of `bytes` bytes from src to dst (device buffers,
+ * 16-byte aligned, not overlapping; bytes a multiple of 16): one 16-byte
+ * load and one 16-byte store per lane and nothing else.  It measures the
+ * achievable HBM bandwidth that the passes' roofline is read against (timing
+ * family "stream_copy").  Stream-ordered.  GPE_ERR_ARG for a NULL or
+ * misaligned pointer, a size that is not a multiple of 16 or needs more than
+ * 2^31 - 1 workgroups, or overlapping buffers. */
+gpe_status gpe_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

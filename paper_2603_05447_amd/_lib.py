@@ -98,6 +98,7 @@ SIGNATURES = {
     "gpe_timing_count": (_i32, []),
     "gpe_timing_name": (C.c_char_p, [_i32]),
     "gpe_timing_read": (C.c_int, [_i32, C.POINTER(_i64), _pd]),
+    "gpe_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
 }
 
 _lib = None

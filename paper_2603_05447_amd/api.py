@@ -527,6 +527,15 @@ class BatchFidelityGrad(torch.autograd.Function):
         return (grad_out[:, None] * grad,) + (None,) * 11
 
 
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """Plain streaming copy of src's bytes into dst on the device (the
+    achievable-bandwidth reference kernel)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nb:
+        raise ValueError("dst is smaller than src")
+    check(L.load().gpe_stream_copy(src.data_ptr(), dst.data_ptr(), nb, _stream(stream)))
+
+
 def config_count() -> int:
     return int(L.load().gpe_config_count())
 

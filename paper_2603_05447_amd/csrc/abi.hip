@@ -2018,6 +2018,20 @@ gpe_status gpe_autotune_cache_clear(void) {
 
 // ---- timing ---------------------------------------------------------------
 
+gpe_status gpe_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  gpe_status st = check_ptr(src, "src");
+  if (st == GPE_OK) st = check_ptr(dst, "dst");
+  if (st != GPE_OK) return st;
+  if (bytes % 16 != 0) return fail(GPE_ERR_ARG, "bytes (%zu) is not a multiple of 16", bytes);
+  const size_t n16 = bytes / 16;
+  if ((n16 + 255) / 256 > (size_t)INT32_MAX) return fail(GPE_ERR_ARG, "copy of %zu bytes is too large", bytes);
+  const char* a = (const char*)src;
+  char* b = (char*)dst;
+  if (a < b + bytes && b < a + bytes) return fail(GPE_ERR_ARG, "src and dst overlap");
+  LTRY(run_stream_copy(src, dst, n16, (hipStream_t)stream));
+  return GPE_OK;
+}
+
 gpe_status gpe_timing_enable(int32_t enable) {
   g_tim.enabled = enable != 0;
   return GPE_OK;

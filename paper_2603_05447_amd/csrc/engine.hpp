@@ -103,7 +103,7 @@ inline int chunk_capacity(const LaunchConfig& c) { return c.block * c.spt; }
 // Kernel families (for per-kernel timing).
 enum Family {
   FAM_ITP1 = 0, FAM_ITP2, FAM_RK1, FAM_RK2, FAM_RK3, FAM_RK4, FAM_OBSERVE,
-  FAM_ADJ1, FAM_ADJ2, FAM_ADJ3, FAM_ADJ4, FAM_FINALIZE, FAM_POINTWISE, FAM_RKG, FAM_COUNT
+  FAM_ADJ1, FAM_ADJ2, FAM_ADJ3, FAM_ADJ4, FAM_FINALIZE, FAM_POINTWISE, FAM_RKG, FAM_COPY, FAM_COUNT
 };
 const char* family_name(int f);
 
@@ -172,6 +172,8 @@ template <typename R> hipError_t run_fill_zero(void* dst, int64_t n_complex, hip
 template <typename R> hipError_t run_threshold(const void* va, const void* vb, int64_t n, double cutoff,
                                                uint8_t* mask, hipStream_t s);
 // destination site i <- src[iv_src[q] + i - iv_dst[q]] for its interval q, or 0 when iv_src[q] < 0
+// plain streaming copy of n16 16-byte elements (the achievable-bandwidth reference)
+hipError_t run_stream_copy(const void* src, void* dst, size_t n16, hipStream_t s);
 template <typename R> hipError_t run_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv,
                                            int64_t n_dst, const void* src, void* dst, hipStream_t s);
 

@@ -96,7 +96,7 @@ LaunchConfig config_get(int i) { return kConfigs[i]; }
 const char* family_name(int f) {
   static const char* names[FAM_COUNT] = {"itp_pass1",  "itp_pass2",  "rk_stage1",  "rk_stage2", "rk_stage3",
                                          "rk_stage4",  "observe",    "adj_stage1", "adj_stage2", "adj_stage3",
-                                         "adj_stage4", "finalize",   "pointwise",  "rk_generic"};
+                                         "adj_stage4", "finalize",   "pointwise",  "rk_generic", "stream_copy"};
   return (f >= 0 && f < FAM_COUNT) ? names[f] : "?";
 }
 
@@ -1357,6 +1357,23 @@ __global__ void k_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_
     const int64_t o = iv_src[lo];
     dst[i] = o >= 0 ? src[o + (i - iv_dst[lo])] : cmk<R>(R(0), R(0));
   }
+}
+
+// one 16-byte load and one 16-byte store per lane, nothing else
+__global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                     size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t run_stream_copy(const void* src, void* dst, size_t n16, hipStream_t s) {
+  if (n16 == 0) return hipSuccess;
+  timing_before(FAM_COPY, s);
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s, (const double2*)src,
+                     (double2*)dst, n16);
+  hipError_t e = hipGetLastError();
+  timing_after(FAM_COPY, s);
+  return e;
 }
 
 template <typename R>

@@ -160,6 +160,19 @@ def test_every_launch_config_matches_the_oracle_on_a_fragmented_mask(dtype):
         assert err <= TOL[dtype], (k, err)
 
 
+def test_stream_copy_reference_kernel():
+    import torch
+    from paper_2603_05447_amd import GPEError, _lib, stream_copy
+    x = torch.randint(0, 256, (16 * 100_003,), dtype=torch.uint8, device="cuda:0")
+    y = torch.zeros_like(x)
+    stream_copy(x, y)
+    assert torch.equal(x, y)
+    for src, dst in ((x[:20], y), (x[1:17], y), (x[:64], x[32:96])):   # size, alignment, overlap
+        with pytest.raises(GPEError) as e:
+            stream_copy(src, dst)
+        assert e.value.status == _lib.GPE_ERR_ARG
+
+
 def test_runs_are_bitwise_reproducible():
     w = configs.small_rf_ramp(n=28)
     outs = []
