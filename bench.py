@@ -412,11 +412,7 @@ def cpu_baseline(args):
     from oracle.potential import RFRamp
     from workloads import configs, site_linear_index
     w = configs.c2()
-    sel = (w.runs[:, 0] >= 448) & (w.runs[:, 0] < 576)
-    runs = w.runs[sel]
-    lens = runs[:, 3] - runs[:, 2]
-    starts = np.concatenate([[0], np.cumsum(w.runs[:, 3] - w.runs[:, 2])[:-1]])[sel]
-    idx = np.concatenate([np.arange(s, s + l) for s, l in zip(starts, lens)])
+    runs, idx = _slab(w, 448, 576)
     U = w.field[idx]
     psi = w.psi0[idx]
     lin = site_linear_index(w.box, runs)
@@ -443,6 +439,76 @@ def cpu_baseline(args):
                       f"({idx.size} active sites); median of {reps} repeats of 1 imaginary-time + 2 RK4 steps "
                       f"(operator build {t_build:.1f}s not counted)",
             "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+
+
+def _slab(w, i_lo, i_hi):
+    """Active sites of x-planes [i_lo, i_hi) of a workload: (runs, compact indices)."""
+    sel = (w.runs[:, 0] >= i_lo) & (w.runs[:, 0] < i_hi)
+    runs = w.runs[sel]
+    lens = runs[:, 3] - runs[:, 2]
+    starts = np.concatenate([[0], np.cumsum(w.runs[:, 3] - w.runs[:, 2])[:-1]])[sel]
+    return runs, np.concatenate([np.arange(s, s + l) for s, l in zip(starts, lens)])
+
+
+def cpu_per_config(report):
+    """The FP64 oracle (one thread) on the other workloads, each on a bounded
+    sample, beside the GPU rate of the same work where the report has it:
+    C3 loss + gradient over a 4-step prefix of the ramp on the whole grid,
+    C4 10 RK4 steps of four sampled instances, C5 two RK4 steps on the active
+    sites of x-planes [960, 1088) (Dirichlet at the slab faces)."""
+    from oracle import operator as op, realtime as rt, adjoint as adj
+    from oracle.potential import RFRamp
+    from workloads import configs, site_linear_index
+    out = {}
+    # C3: forward + adjoint, 10 steps, whole grid
+    w = configs.c3()
+    T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, w.runs))
+    ramp = RFRamp(w.field, w.omega, w.knot_t, w.knot_delta)
+    rng = np.random.default_rng(7)
+    tgt = w.psi0 * np.exp(1j * rng.uniform(0.0, 0.3, w.n_active))
+    tgt /= np.sqrt(np.sum(np.abs(tgt) ** 2) * w.box.dV)
+    k = 4
+    t = time.perf_counter()
+    adj.fidelity_grad(T, ramp, w.g, w.dt, 0.0, k, w.psi0, tgt, w.box.dV)
+    el = time.perf_counter() - t
+    c3 = {"sample": f"loss + 8-knot gradient over the first {k} of {w.steps} steps, {w.n_active} sites",
+          "s_per_step": el / k}
+    if "adjoint_c3" in report:
+        gpu = report["adjoint_c3"]["s_per_grad"] / report["adjoint_c3"]["steps"]
+        c3["gpu_s_per_step"] = gpu
+        c3["gpu_speedup"] = (el / k) / gpu
+    out["c3_forward_adjoint"] = c3
+    del T, ramp, tgt, w
+    # C4: four sampled instances, complex128, 10 RK4 steps each
+    sites, el = 0, 0.0
+    for i in (0, 21, 42, 63):
+        w = configs.c4_instance(i)
+        T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, w.runs))
+        ramp = RFRamp(w.field, w.omega, w.knot_t, w.knot_delta)
+        t = time.perf_counter()
+        rt.real_time(T, w.psi0, ramp, w.g, w.dt, 0.0, 10)
+        el += time.perf_counter() - t
+        sites += w.n_active
+    c4 = {"sample": f"instances 0, 21, 42, 63 ({sites} sites), 10 RK4 steps each", "site_updates_per_s": sites * 10 / el}
+    if "batched_c4" in report:
+        c4["gpu_site_updates_per_s_c64_batched"] = report["batched_c4"]["graph"]["site_updates_per_s"]
+    out["c4_sampled"] = c4
+    # C5: slab of x-planes, two RK4 steps
+    w = configs.c5()
+    runs, idx = _slab(w, 960, 1088)
+    T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, runs))
+    ramp = RFRamp(w.field[idx], w.omega, w.knot_t, w.knot_delta)
+    psi = w.psi0[idx]
+    t = time.perf_counter()
+    rt.real_time(T, psi, ramp, w.g, w.dt, 0.0, 2)
+    el = time.perf_counter() - t
+    c5 = {"sample": f"x-planes [960, 1088) of the 2048 x 2048 x 1024 shell ({idx.size} sites), 2 RK4 steps",
+          "site_updates_per_s": idx.size * 2 / el}
+    if "precision_c5" in report:
+        c5["gpu_site_updates_per_s_c128"] = report["precision_c5"]["c128"]["site_updates_per_s"]
+    out["c5_slab"] = c5
+    out["cores"] = 1
+    return out
 
 
 def bench_adjoint(args, dev, report):
@@ -638,6 +704,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="time every launch variant and use the fastest")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-all", action="store_true",
+                    help="also time the oracle on samples of the 256^3 ramp, the batch and the 60M-site shell")
     ap.add_argument("--no-extras", action="store_true", help="skip complex64, adjoint and batched legs")
     ap.add_argument("--adj-steps", type=int, default=2000,
                     help="steps of the 2-time-unit adjoint ramp (dt = 2/steps; RK4 needs steps >= 1100)")
@@ -703,6 +771,9 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(args)
         log(f"[bench] cpu baseline: {cpu['value']:.4g} site-updates/s")
+    if args.cpu_all:
+        report["cpu_oracle_per_config"] = cpu_per_config(report)
+        log("[bench] oracle on the other workloads done")
 
     main_res = report["c128"]
     kern = main_res["kernels"]
@@ -741,7 +812,7 @@ def main():
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
     for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "restage_c2", "hoc19_c2", "c1",
-                "precision_c5", "job_c2"):
+                "precision_c5", "job_c2", "cpu_oracle_per_config"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)
