@@ -148,9 +148,11 @@ gpe_status gpe_grid_create_runs(const gpe_geometry* geom, int64_t nruns, const i
  * NULL: va_box alone).  va_box/vb_box are device arrays of n0*n1*n2 reals in
  * box linear order (double for GPE_C128, float for GPE_C64) on `device`
  * (>= 0).  For a stage between potentials V_i and V_{i+1} the paper's cutoff
- * is 5 max(mu_i, mu_{i+1}).  The mask is built by a device kernel, copied to
- * the host and compacted as in gpe_grid_create; the call synchronises the
- * device.  Errors as gpe_grid_create (an empty selection is GPE_ERR_ARG). */
+ * is 5 max(mu_i, mu_{i+1}).  The z-runs of the selection are found on the
+ * device (one wave per (i, j) column; no box mask is formed) and only the run
+ * table is copied to the host, where the segments are built as in
+ * gpe_grid_create_runs; the call runs on the null stream and synchronises.
+ * Errors as gpe_grid_create (an empty selection is GPE_ERR_ARG). */
 gpe_status gpe_grid_create_threshold(const gpe_geometry* geom, gpe_dtype dtype, const void* va_box,
                                      const void* vb_box, double cutoff, int device, gpe_grid* out);
 

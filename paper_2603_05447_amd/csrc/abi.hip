@@ -1275,20 +1275,50 @@ gpe_status gpe_grid_create_threshold(const gpe_geometry* geom, gpe_dtype dtype, 
   if (device < 0) return fail(GPE_ERR_ARG, "the potentials live on a device: device must be >= 0");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return fail(GPE_ERR_DEVICE, "device %d not available", device);
-  const int64_t npts = geom->n[0] * geom->n[1] * geom->n[2];
-  std::vector<uint8_t> mask((size_t)npts);
+  // the z-runs of the selection are found on the device (a count pass, the
+  // column offsets, an emit pass); only the run table comes to the host
+  const int64_t n0 = geom->n[0], n1 = geom->n[1], n2 = geom->n[2], n01 = n0 * n1;
+  std::vector<int64_t> runs;
   {
     DeviceGuard dg(device);
-    uint8_t* d_mask = nullptr;
-    HIP_TRY(hipMalloc((void**)&d_mask, (size_t)npts));
-    hipError_t e = dtype == GPE_C128 ? run_threshold<double>(va_box, vb_box, npts, cutoff, d_mask, nullptr)
-                                     : run_threshold<float>(va_box, vb_box, npts, cutoff, d_mask, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(mask.data(), d_mask, (size_t)npts, hipMemcpyDeviceToHost);
-    (void)hipFree(d_mask);
-    if (e != hipSuccess) return hip_fail(e, "post-selection mask");
+    if (!dg.ok) return fail(GPE_ERR_DEVICE, "hipSetDevice(%d) failed", device);
+    auto column_runs = [&](int32_t* cnt, const int64_t* off, int64_t* rr) {
+      return dtype == GPE_C128 ? run_column_runs<double>(va_box, vb_box, n0, n1, n2, cutoff, cnt, off, rr, nullptr)
+                               : run_column_runs<float>(va_box, vb_box, n0, n1, n2, cutoff, cnt, off, rr, nullptr);
+    };
+    int32_t* d_cnt = nullptr;
+    int64_t* d_off = nullptr;
+    int64_t* d_runs = nullptr;
+    std::vector<int32_t> cnt((size_t)n01);
+    std::vector<int64_t> off((size_t)n01);
+    hipError_t e = hipMalloc((void**)&d_cnt, sizeof(int32_t) * (size_t)n01);
+    if (e == hipSuccess) e = column_runs(d_cnt, nullptr, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(cnt.data(), d_cnt, sizeof(int32_t) * (size_t)n01, hipMemcpyDeviceToHost);
+    int64_t total = 0;
+    if (e == hipSuccess) {
+      for (int64_t c = 0; c < n01; ++c) {
+        off[(size_t)c] = total;
+        total += cnt[(size_t)c];
+      }
+    }
+    if (e == hipSuccess && total > 0) {
+      e = hipMalloc((void**)&d_off, sizeof(int64_t) * (size_t)n01);
+      if (e == hipSuccess) e = hipMalloc((void**)&d_runs, sizeof(int64_t) * 4 * (size_t)total);
+      if (e == hipSuccess) e = hipMemcpy(d_off, off.data(), sizeof(int64_t) * (size_t)n01, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = column_runs(nullptr, d_off, d_runs);
+      if (e == hipSuccess) {
+        runs.resize(4 * (size_t)total);
+        e = hipMemcpy(runs.data(), d_runs, sizeof(int64_t) * 4 * (size_t)total, hipMemcpyDeviceToHost);
+      }
+    }
+    (void)hipFree(d_cnt);
+    (void)hipFree(d_off);
+    (void)hipFree(d_runs);
+    if (e != hipSuccess) return hip_fail(e, "post-selection");
+    if (total == 0) return fail(GPE_ERR_ARG, "geometry: the active set is empty");
   }
   Layout lay;
-  std::string err = layout_from_mask(geom->n, mask.data(), lay);
+  std::string err = layout_from_runs(geom->n, (int64_t)(runs.size() / 4), runs.data(), lay);
   if (!err.empty()) return fail(GPE_ERR_ARG, "%s", err.c_str());
   return finish_grid(geom, std::move(lay), device, out);
 }

@@ -168,12 +168,16 @@ template <typename R> hipError_t run_pack(const int64_t* run_base, const int32_t
                                           int64_t n_active, const void* src, void* dst, bool to_box,
                                           hipStream_t s, bool real = false);
 template <typename R> hipError_t run_fill_zero(void* dst, int64_t n_complex, hipStream_t s);
-// box mask of min(va, vb) < cutoff (vb may be null), n box points
-template <typename R> hipError_t run_threshold(const void* va, const void* vb, int64_t n, double cutoff,
-                                               uint8_t* mask, hipStream_t s);
-// destination site i <- src[iv_src[q] + i - iv_dst[q]] for its interval q, or 0 when iv_src[q] < 0
+// z-runs of the post-selection min(va, vb) < cutoff (vb may be null) over a
+// box of n0 x n1 x n2 points, column by column: with offsets == nullptr the
+// number of runs of every (i, j) column goes to counts[i n1 + j]; otherwise
+// the runs {i, j, k0, k1} of column c are written from row offsets[c] of runs
+template <typename R> hipError_t run_column_runs(const void* va, const void* vb, int64_t n0, int64_t n1, int64_t n2,
+                                                 double cutoff, int32_t* counts, const int64_t* offsets,
+                                                 int64_t* runs, hipStream_t s);
 // plain streaming copy of n16 16-byte elements (the achievable-bandwidth reference)
 hipError_t run_stream_copy(const void* src, void* dst, size_t n16, hipStream_t s);
+// destination site i <- src[iv_src[q] + i - iv_dst[q]] for its interval q, or 0 when iv_src[q] < 0
 template <typename R> hipError_t run_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv,
                                            int64_t n_dst, const void* src, void* dst, hipStream_t s);
 

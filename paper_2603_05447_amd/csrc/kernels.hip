@@ -1317,26 +1317,78 @@ hipError_t run_pack(const int64_t* run_base, const int32_t* run_start, int64_t n
   return e;
 }
 
-// Post-selection (Sec. II.A, repeated per ramp stage in Sec. V): mask[x] =
-// min(Va[x], Vb[x]) < cutoff over the whole box (Vb may be null).
+// Post-selection (Sec. II.A, repeated per ramp stage in Sec. V): the active
+// set is min(Va, Vb) < cutoff over the whole box (Vb may be null), found
+// directly as z-runs.  One wave per (i, j) column reads the column 64 points
+// at a time; the ballot of the selection is compared with itself shifted by
+// one point, and every change (a run's first point or the first point after
+// it) is taken in order.  The count pass writes the number of runs per
+// column; the emit pass writes the runs from the column's offset.
 template <typename R>
-__global__ void k_threshold(const R* va, const R* vb, int64_t n, R cutoff, uint8_t* mask) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    R v = va[i];
-    if (vb) {
-      const R w = vb[i];
-      v = w < v ? w : v;
+__global__ __launch_bounds__(256) void k_column_runs(const R* va, const R* vb, int64_t n1, int64_t n01, int64_t n2,
+                                                     R cutoff, int32_t* counts, const int64_t* offsets,
+                                                     int64_t* runs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n01; c += nwaves) {
+    const int64_t base = c * n2;
+    unsigned long long prev = 0;     // selection at k = kk - 1
+    bool in_run = false;
+    int64_t k0 = 0, nr = 0, pos = offsets ? offsets[c] : 0;
+    for (int64_t kk = 0; kk < n2; kk += 64) {
+      const int64_t k = kk + lane;
+      bool on = false;
+      if (k < n2) {
+        R v = va[base + k];
+        if (vb) {
+          const R w = vb[base + k];
+          v = w < v ? w : v;
+        }
+        on = v < cutoff;
+      }
+      const unsigned long long m = __ballot(on);
+      unsigned long long t = m ^ ((m << 1) | prev);
+      prev = m >> 63;
+      if (!offsets) {
+        nr += __popcll(t & m);
+        continue;
+      }
+      while (t) {
+        const int64_t kt = kk + (__ffsll((long long)t) - 1);
+        t &= t - 1;
+        if (!in_run) {
+          k0 = kt;
+        } else if (lane == 0) {
+          int64_t* r = runs + 4 * pos;
+          r[0] = c / n1;
+          r[1] = c % n1;
+          r[2] = k0;
+          r[3] = kt;
+        }
+        if (in_run) ++pos;
+        in_run = !in_run;
+      }
     }
-    mask[i] = (v < cutoff) ? 1 : 0;
+    if (!offsets) {
+      if (lane == 0) counts[c] = (int32_t)nr;
+    } else if (in_run && lane == 0) {
+      int64_t* r = runs + 4 * pos;
+      r[0] = c / n1;
+      r[1] = c % n1;
+      r[2] = k0;
+      r[3] = n2;
+    }
   }
 }
 
 template <typename R>
-hipError_t run_threshold(const void* va, const void* vb, int64_t n, double cutoff, uint8_t* mask, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_threshold<R>), dim3((unsigned)blocks), dim3(256), 0, s, (const R*)va, (const R*)vb, n,
-                     (R)cutoff, mask);
+hipError_t run_column_runs(const void* va, const void* vb, int64_t n0, int64_t n1, int64_t n2, double cutoff,
+                           int32_t* counts, const int64_t* offsets, int64_t* runs, hipStream_t s) {
+  const int64_t n01 = n0 * n1;
+  if (n01 <= 0 || n2 <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n01 + 3) / 4, 65536);
+  hipLaunchKernelGGL((k_column_runs<R>), dim3((unsigned)blocks), dim3(256), 0, s, (const R*)va, (const R*)vb, n1,
+                     n01, n2, (R)cutoff, counts, offsets, runs);
   return hipGetLastError();
 }
 
@@ -1434,7 +1486,8 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
   template hipError_t run_pack<R>(const int64_t*, const int32_t*, int64_t, int64_t, const void*, void*, bool, \
                                   hipStream_t, bool);                                                        \
   template hipError_t run_fill_zero<R>(void*, int64_t, hipStream_t);                                         \
-  template hipError_t run_threshold<R>(const void*, const void*, int64_t, double, uint8_t*, hipStream_t);     \
+  template hipError_t run_column_runs<R>(const void*, const void*, int64_t, int64_t, int64_t, double, int32_t*, \
+                                         const int64_t*, int64_t*, hipStream_t);                             \
   template hipError_t run_remap<R>(const int64_t*, const int64_t*, int64_t, int64_t, const void*, void*,      \
                                    hipStream_t);
 

@@ -77,6 +77,30 @@ def test_threshold_grid_matches_oracle_mask(rdt):
     assert np.array_equal(site_linear_index(s.box, g1.runs()[:, :4]), np.flatnonzero((Va < cut).ravel()))
 
 
+@pytest.mark.parametrize("n2", [1, 63, 64, 128, 150, 300])
+def test_threshold_runs_cross_the_64_point_steps(n2):
+    """Runs that start at k = 0, end at k = n2, cross multiples of 64, and
+    single-point runs: the device-built run table equals the runs of the
+    dense selection."""
+    import torch
+    from paper_2603_05447_amd import Grid
+    rng = np.random.default_rng(n2)
+    n = (5, 6, n2)
+    va = rng.uniform(0.0, 1.0, n)
+    vb = rng.uniform(0.0, 1.0, n)
+    # long stretches in some columns, isolated points in others
+    va[0, :, :] = 0.0
+    va[1, 2, ::2] = 2.0
+    va[2, :, n2 // 2:] = 0.1
+    vb[2, :, :] = 5.0
+    cut = 0.3
+    box = Box(n, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0))
+    g = Grid.from_threshold(n, box.h, box.x0, torch.tensor(va, device="cuda:0"), torch.tensor(vb, device="cuda:0"),
+                            cut, device=0)
+    want = runs_from_mask(np.minimum(va, vb) < cut)
+    assert np.array_equal(g.runs()[:, :4], want)
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_remap_is_exact(dtype):
     import torch
