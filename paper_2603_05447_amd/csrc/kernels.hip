@@ -1395,19 +1395,17 @@ hipError_t run_column_runs(const void* va, const void* vb, int64_t n0, int64_t n
 // Carry psi between two compact layouts of one box: the destination array is
 // cut into intervals (iv_dst[q] = first destination site, sorted, iv_dst[0]
 // = 0), each copied from consecutive source sites starting at iv_src[q] or
-// zero-filled when iv_src[q] < 0.  One lane per destination site finds its
-// interval by binary search.
+// zero-filled when iv_src[q] < 0.  One wave per interval (grid-stride over
+// the intervals) copies it with consecutive lanes on consecutive sites.
 template <typename R>
-__global__ void k_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv, int64_t n_dst,
-                        const typename CT<R>::T* src, typename CT<R>::T* dst) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_dst; i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lo = 0, hi = n_iv - 1;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (iv_dst[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    const int64_t o = iv_src[lo];
-    dst[i] = o >= 0 ? src[o + (i - iv_dst[lo])] : cmk<R>(R(0), R(0));
+__global__ __launch_bounds__(256) void k_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv,
+                                               int64_t n_dst, const typename CT<R>::T* src,
+                                               typename CT<R>::T* dst) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < n_iv; q += nwaves) {
+    const int64_t d0 = iv_dst[q], d1 = q + 1 < n_iv ? iv_dst[q + 1] : n_dst, o = iv_src[q];
+    for (int64_t i = d0 + lane; i < d1; i += 64) dst[i] = o >= 0 ? src[o + (i - d0)] : cmk<R>(R(0), R(0));
   }
 }
 
@@ -1432,8 +1430,8 @@ template <typename R>
 hipError_t run_remap(const int64_t* iv_dst, const int64_t* iv_src, int64_t n_iv, int64_t n_dst, const void* src,
                      void* dst, hipStream_t s) {
   using C = typename CT<R>::T;
-  if (n_dst <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((n_dst + 255) / 256, 65536);
+  if (n_dst <= 0 || n_iv <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n_iv + 3) / 4, 65536);
   timing_before(FAM_POINTWISE, s);
   hipLaunchKernelGGL((k_remap<R>), dim3((unsigned)blocks), dim3(256), 0, s, iv_dst, iv_src, n_iv, n_dst,
                      (const C*)src, (C*)dst);
