@@ -209,6 +209,8 @@ gpe_status gpe_grid_get_stencil(gpe_grid grid, int32_t* points);
  * count only. */
 gpe_status gpe_grid_stencil_segments(gpe_grid grid, int32_t points, int64_t* n_segments, int32_t* out_host);
 
+/* Frees the grid's host and device tables and its captured graphs, after
+ * waiting for the device's outstanding work.  NULL is accepted. */
 gpe_status gpe_grid_destroy(gpe_grid grid);
 
 /* Size in bytes of the device work buffer a call needs.
@@ -316,6 +318,7 @@ typedef struct {
 
 gpe_status gpe_batch_create(int32_t n, const gpe_grid* grids, int device, gpe_batch* out);
 gpe_status gpe_batch_offsets(gpe_batch batch, int64_t* offsets_host /* n+1 */);
+/* As gpe_grid_destroy, for a batch (its grids are not affected). */
 gpe_status gpe_batch_destroy(gpe_batch batch);
 gpe_status gpe_batch_work_bytes(gpe_batch batch, gpe_dtype dtype, int32_t mode, int64_t nsteps,
                                 int64_t ckpt_every, size_t* bytes);

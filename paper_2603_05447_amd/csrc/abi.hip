@@ -200,6 +200,7 @@ struct Problem {
   void release() {
     if (device < 0) return;
     DeviceGuard g(device);
+    (void)hipDeviceSynchronize();     // launches and graphs in flight use these tables
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     graphs.clear();
     for (auto& kv : chunksets) {
@@ -354,6 +355,8 @@ struct Problem {
     DeviceGuard g(device);
     const int64_t need = (lay.n_active + 255) / 256 + nh / MAX_CHUNK_SEGS + 1;
     if (need > max_chunks) {
+      // the graphs and launches in flight hold the old scratch
+      if (hipDeviceSynchronize() != hipSuccess) return fail(GPE_ERR_DEVICE, "hipDeviceSynchronize failed");
       for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
       graphs.clear();
       (void)hipFree(d_partials);
@@ -952,6 +955,8 @@ gpe_status read_obs(Problem& P, gpe_obs* out_host, hipStream_t s) {
 }
 
 // adjoint: loss and knot gradients, fully on the device
+constexpr size_t kMaxGraphs = 16;
+
 // Captured graph of one in-place RK4 step of psi (scratch y2, y3, y4); the
 // step index comes from the device counter, so one graph serves every step.
 template <typename R>
@@ -988,6 +993,13 @@ static gpe_status step_graph(const Ctx& c, int dtype, void* psi, const void* fie
   if (graph) (void)hipGraphDestroy(graph);
   (void)hipStreamDestroy(cap);
   if (r != GPE_OK) return r;
+  // a caller that cycles through many buffers would otherwise keep one
+  // instantiated graph per buffer set for the life of the grid
+  if (P.graphs.size() >= kMaxGraphs) {
+    HIP_TRY(hipDeviceSynchronize());     // none of them may still be running
+    for (auto& kv : P.graphs) (void)hipGraphExecDestroy(kv.second);
+    P.graphs.clear();
+  }
   P.graphs[key] = exec;
   *out = exec;
   return GPE_OK;
