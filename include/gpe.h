@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GPE_ABI_VERSION 2
+#define GPE_ABI_VERSION 3
 #define GPE_MAX_KNOTS 32
 
 typedef enum {
@@ -372,21 +372,24 @@ gpe_status gpe_grid_set_config(gpe_grid grid, int32_t config);
 gpe_status gpe_grid_get_config(gpe_grid grid, int32_t* config);
 gpe_status gpe_batch_set_config(gpe_batch batch, int32_t config);
 
-/* Time every configuration on `reps` real-time RK4 steps of psi (contents
+/* Time every configuration on `reps` steps of psi of one phase (contents
  * are advanced; pass a scratch copy), in three interleaved rounds keeping
  * each variant's fastest, select the fastest and store it on the grid.
- * times_ms_host: optional gpe_config_count() doubles (ms per step). */
-gpe_status gpe_grid_autotune(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+ *   mode: GPE_MODE_RT (real time with params.integrator; work sized for it),
+ *         GPE_MODE_ITP or GPE_MODE_ITP_REAL (imaginary time on a complex /
+ *         real state; params.integrator must be 0).
+ *   times_ms_host: optional gpe_config_count() doubles (ms per step). */
+gpe_status gpe_grid_autotune(gpe_grid grid, gpe_dtype dtype, int32_t mode, void* psi, const gpe_potential* pot,
                              const gpe_params* params, int32_t reps, void* work, size_t work_bytes,
                              void* stream, int32_t* best_config, double* times_ms_host);
 
 /* Every gpe_grid_autotune result is also recorded in a process-wide cache
- * keyed by (dtype, floor(log2 n_active), floor(log2 mean segment length)).
- * gpe_grid_apply_tuned gives the grid the cached configuration of its class
- * (*config = that index) or leaves it unchanged (*config = -1 when the class
- * has not been tuned).  gpe_autotune_cache_clear empties the cache.  The
- * cache is guarded by a lock. */
-gpe_status gpe_grid_apply_tuned(gpe_grid grid, gpe_dtype dtype, int32_t* config);
+ * keyed by (dtype, mode, floor(log2 n_active), floor(log2 mean segment
+ * length)).  gpe_grid_apply_tuned gives the grid the cached configuration of
+ * its class for that phase (*config = that index) or leaves it unchanged
+ * (*config = -1 when the class has not been tuned).  gpe_autotune_cache_clear
+ * empties the cache.  The cache is guarded by a lock. */
+gpe_status gpe_grid_apply_tuned(gpe_grid grid, gpe_dtype dtype, int32_t mode, int32_t* config);
 gpe_status gpe_autotune_cache_clear(void);
 
 /* ---- Per-kernel timing -----------------------------------------------

@@ -89,9 +89,9 @@ SIGNATURES = {
     "gpe_grid_set_config": (C.c_int, [_vp, _i32]),
     "gpe_grid_get_config": (C.c_int, [_vp, C.POINTER(_i32)]),
     "gpe_batch_set_config": (C.c_int, [_vp, _i32]),
-    "gpe_grid_autotune": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), _i32, _vp,
+    "gpe_grid_autotune": (C.c_int, [_vp, C.c_int, _i32, _vp, C.POINTER(Potential), C.POINTER(Params), _i32, _vp,
                                     C.c_size_t, _vp, C.POINTER(_i32), _pd]),
-    "gpe_grid_apply_tuned": (C.c_int, [_vp, C.c_int, C.POINTER(_i32)]),
+    "gpe_grid_apply_tuned": (C.c_int, [_vp, C.c_int, _i32, C.POINTER(_i32)]),
     "gpe_autotune_cache_clear": (C.c_int, []),
     "gpe_timing_enable": (C.c_int, [_i32]),
     "gpe_timing_reset": (C.c_int, []),

@@ -104,6 +104,7 @@ class Potential:
 
 INTEGRATORS = {"rk4": L.GPE_RK4, "rkhe3": L.GPE_RKHE3, "rkck": L.GPE_RKCK}
 _RT_MODE = {L.GPE_RK4: L.GPE_MODE_RT, L.GPE_RKHE3: L.GPE_MODE_RT_RKHE3, L.GPE_RKCK: L.GPE_MODE_RT_RKCK}
+_TUNE_MODE = {"rt": L.GPE_MODE_RT, "itp": L.GPE_MODE_ITP, "itp_real": L.GPE_MODE_ITP_REAL}
 
 
 def _integrator(name: str) -> int:
@@ -231,11 +232,12 @@ class Grid:
         check(L.load().gpe_grid_runs(self._h, out.ctypes.data))
         return out
 
-    def apply_tuned(self, dtype: int) -> Optional[int]:
+    def apply_tuned(self, dtype: int, phase: str = "rt") -> Optional[int]:
         """Take the launch configuration autotuned for this grid's size /
-        segment-length class (any grid of the process), if there is one."""
+        segment-length class and phase (any grid of the process), if there
+        is one."""
         c = C.c_int32()
-        check(L.load().gpe_grid_apply_tuned(self._h, int(dtype), C.byref(c)))
+        check(L.load().gpe_grid_apply_tuned(self._h, int(dtype), _TUNE_MODE[phase], C.byref(c)))
         return None if c.value < 0 else c.value
 
     def set_stencil(self, points: int) -> None:
@@ -381,15 +383,34 @@ class Grid:
         return c.value
 
     def autotune(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, reps: int = 5, stream=None,
-                 integrator: str = "rk4"):
-        dt_ = _dtype_of(psi)
+                 integrator: str = "rk4", phase: str = "rt"):
+        """Time every launch variant on `reps` steps of one phase ("rt": real
+        time with `integrator`; "itp": imaginary time, on a real state when
+        psi is real) and keep the fastest.  psi is advanced."""
+        real = psi.dtype in _RSTATE
+        if real and phase != "itp":
+            raise ValueError("a real state tunes imaginary time only (phase='itp')")
+        if real:
+            if not psi.is_cuda or not psi.is_contiguous():
+                raise ValueError("psi must be a contiguous CUDA/HIP tensor")
+            dt_ = _RSTATE[psi.dtype]
+        else:
+            dt_ = _dtype_of(psi)
         cp, keep = pot.as_c(dt_)
-        prm = make_params(g, dt, integrator=integrator)
-        w = self.work(dt_, _RT_MODE[prm.integrator], reps)
+        if phase == "itp":
+            mode = L.GPE_MODE_ITP_REAL if real else L.GPE_MODE_ITP
+            prm = make_params(g, dt)
+            w = self.work(dt_, mode, reps)
+        elif phase == "rt":
+            prm = make_params(g, dt, integrator=integrator)
+            mode = L.GPE_MODE_RT
+            w = self.work(dt_, _RT_MODE[prm.integrator], reps)
+        else:
+            raise ValueError("phase must be 'rt' or 'itp'")
         n = config_count()
         times = (C.c_double * n)(*([-1.0] * n))
         best = C.c_int32()
-        check(L.load().gpe_grid_autotune(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), int(reps),
+        check(L.load().gpe_grid_autotune(self._h, dt_, mode, psi.data_ptr(), C.byref(cp), C.byref(prm), int(reps),
                                          w.data_ptr(), w.numel(), _stream(stream), C.byref(best), times))
         return best.value, list(times)
 

@@ -1951,29 +1951,47 @@ gpe_status gpe_batch_set_config(gpe_batch b, int32_t config) {
 // floor(log2 mean segment length), the two properties that decide which
 // launch variant streams a layout best.
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int>, int> g_tune_cache;
+static std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
 
-static std::tuple<int, int, int> tune_key(gpe_grid g, int dtype) {
+static std::tuple<int, int, int, int> tune_key(gpe_grid g, int dtype, int mode) {
   const int64_t n = g->lay.n_active;
   const double mean_seg = (double)n / (double)std::max<int64_t>(1, g->lay.n_segments());
   int nb = 0, sb = 0;
   while ((int64_t(1) << (nb + 1)) <= n) ++nb;
   while ((double)(int64_t(1) << (sb + 1)) <= mean_seg) ++sb;
-  return std::make_tuple(dtype, nb, sb);
+  return std::make_tuple(dtype, mode, nb, sb);
 }
 
-gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot, const gpe_params* prm,
-                             int32_t reps, void* work, size_t work_bytes, void* stream, int32_t* best_config,
-                             double* times_ms) {
+static gpe_status check_tune_mode(int mode) {
+  if (mode != GPE_MODE_RT && mode != GPE_MODE_ITP && mode != GPE_MODE_ITP_REAL)
+    return fail(GPE_ERR_ARG, "mode must be GPE_MODE_RT, GPE_MODE_ITP or GPE_MODE_ITP_REAL");
+  return GPE_OK;
+}
+
+gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, int32_t mode, void* psi, const gpe_potential* pot,
+                             const gpe_params* prm, int32_t reps, void* work, size_t work_bytes, void* stream,
+                             int32_t* best_config, double* times_ms) {
   gpe_status st = check_grid(g);
   if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_tune_mode(mode);
   if (st == GPE_OK) st = check_ptr(psi, "psi");
   if (st == GPE_OK) st = check_pot(pot);
   if (st == GPE_OK) st = check_params(prm);
   if (st != GPE_OK) return st;
   if (reps < 1) return fail(GPE_ERR_ARG, "reps must be >= 1");
-  st = check_work(work, work_bytes, work_bytes_for(g->lay.n_active, dtype, rt_work_mode(prm->integrator), reps, 0));
+  const bool itp = mode != GPE_MODE_RT, real = mode == GPE_MODE_ITP_REAL;
+  if (itp && prm->integrator != GPE_RK4) return fail(GPE_ERR_ARG, "params.integrator must be 0 for imaginary time");
+  st = check_work(work, work_bytes,
+                  work_bytes_for(g->lay.n_active, dtype, itp ? mode : rt_work_mode(prm->integrator), reps, 0));
   if (st != GPE_OK) return st;
+  // `steps` steps of the tuned phase with the context's launch variant
+  auto run = [&](const Ctx& c, int64_t steps) {
+    if (itp)
+      return dtype == GPE_C128 ? drive_itp<double>(c, psi, pot->field, steps, work, 0, nullptr, real)
+                               : drive_itp<float>(c, psi, pot->field, steps, work, 0, nullptr, real);
+    return dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, steps, work, 0, nullptr, prm->integrator)
+                             : drive_rt<float>(c, psi, pot->field, steps, work, 0, nullptr, prm->integrator);
+  };
   DeviceGuard dg(g->device);
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1993,15 +2011,13 @@ gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_p
       st = g->prob->upload(*c.cs, ps, s);
       if (st != GPE_OK) break;
       // one untimed step, then `reps` timed steps
-      st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, 1, work, 0, nullptr, prm->integrator)
-                             : drive_rt<float>(c, psi, pot->field, 1, work, 0, nullptr, prm->integrator);
+      st = run(c, 1);
       if (st != GPE_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) {
         st = fail(GPE_ERR_DEVICE, "hipEventRecord");
         break;
       }
-      st = dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, reps, work, 0, nullptr, prm->integrator)
-                             : drive_rt<float>(c, psi, pot->field, reps, work, 0, nullptr, prm->integrator);
+      st = run(c, reps);
       if (st != GPE_OK) break;
       float ms = 0.f;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -2031,18 +2047,19 @@ gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_p
   if (best_config) *best_config = bi;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[tune_key(g, dtype)] = bi;
+    g_tune_cache[tune_key(g, dtype, mode)] = bi;
   }
   return GPE_OK;
 }
 
-gpe_status gpe_grid_apply_tuned(gpe_grid g, gpe_dtype dtype, int32_t* config) {
+gpe_status gpe_grid_apply_tuned(gpe_grid g, gpe_dtype dtype, int32_t mode, int32_t* config) {
   gpe_status st = check_grid(g);
   if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_tune_mode(mode);
   if (st != GPE_OK) return st;
   if (!config) return fail(GPE_ERR_ARG, "config is NULL");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune_cache.find(tune_key(g, dtype));
+  auto it = g_tune_cache.find(tune_key(g, dtype, mode));
   if (it == g_tune_cache.end()) {
     *config = -1;
     return GPE_OK;

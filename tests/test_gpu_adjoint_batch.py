@@ -4,7 +4,7 @@ replay)."""
 import numpy as np
 import pytest
 
-from oracle import adjoint as adj, realtime as rt
+from oracle import adjoint as adj, itp, realtime as rt
 from workloads import configs
 
 from gpu_cases import Case, rel_l2
@@ -193,6 +193,33 @@ def test_autotune_cache_serves_grids_of_the_same_class():
     assert Case(small, "c128").grid.apply_tuned(_lib.GPE_C128) is None
     load_library().gpe_autotune_cache_clear()
     assert Case(w, "c128").grid.apply_tuned(_lib.GPE_C128) is None
+
+
+@pytest.mark.parametrize("real", [False, True])
+def test_autotune_on_imaginary_time(real):
+    """Tuning on imaginary-time steps (complex or real state) keeps the
+    fastest variant for that phase, caches it under that phase only, and the
+    tuned grid still matches the oracle."""
+    import torch
+    from paper_2603_05447_amd import _lib, load_library, config_count
+    load_library().gpe_autotune_cache_clear()
+    w = configs.small_shell(n=24)
+    c = Case(w, "c128")
+    scratch = c.psi()
+    if real:
+        scratch = scratch.real.contiguous()
+    best, times = c.grid.autotune(scratch, c.pot, w.g, 2e-3, reps=2, phase="itp")
+    assert 0 <= best < config_count() and c.grid.get_config() == best
+    assert times[best] == min(times)
+    phase = "itp_real" if real else "itp"
+    c2 = Case(w, "c128")
+    assert c2.grid.apply_tuned(_lib.GPE_C128, phase) == best
+    assert c2.grid.apply_tuned(_lib.GPE_C128, "rt") is None
+    psi = c2.psi()
+    c2.grid.imag_time(psi, c2.pot, w.g, 2e-3, 10, observe=False)
+    ref, _ = itp.imaginary_time(c2.T, w.psi0, w.field, w.g, 2e-3, w.box.dV, 10)
+    assert rel_l2(psi.cpu().numpy(), ref) <= 1e-10
+    load_library().gpe_autotune_cache_clear()
 
 
 def test_batch_autograd_function():
