@@ -863,6 +863,10 @@ gpe_status rk_generic_step(const Ctx& c, const MemOptTableau& tb, void* y0, cons
   return GPE_OK;
 }
 
+// instances of at most this many chunks form the imaginary-time scale inside
+// the next pass instead of a finalize launch
+constexpr int kFuseScaleChunks = 1024;
+
 template <typename R>
 gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps, void* work, int64_t obs_every,
                      gpe_obs* hist, bool real = false) {
@@ -877,6 +881,13 @@ gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps,
   LTRY(run_set_step(c.pl.step, 0, c.s));
   LTRY(run_make_prop<R>(c.pl, c.cfg, field, prop, c.s));
   LTRY(run_set_scale_one(c.pl, c.s));
+  // On small grids, where launches rather than bytes set the pace, pass 1
+  // forms the scale from pass 2's norm partials itself and the finalize runs
+  // after the last step only (the observations read the stored scale, so a
+  // run with a history keeps the finalize).
+  int max_chunks = 0;
+  for (int q : c.cs->inst_count) max_chunks = std::max(max_chunks, q);
+  const bool fuse = !split_diag && !(hist && obs_every > 0) && max_chunks <= kFuseScaleChunks;
   int64_t k = 0;
   for (int64_t n = 0; n < nsteps; ++n) {
     if (hist && obs_every > 0 && n % obs_every == 0) {
@@ -888,10 +899,10 @@ gpe_status drive_itp(const Ctx& c, void* psi, const void* field, int64_t nsteps,
       LTRY(run_itp_phi<R>(c.pl, c.cfg, psi, prop, phi, real, c.s));
       LTRY(run_itp_pass1<R>(c.pl, c.cfg, phi, prop, tmp, real, c.s, true));
     } else {
-      LTRY(run_itp_pass1<R>(c.pl, c.cfg, psi, prop, tmp, real, c.s));
+      LTRY(run_itp_pass1<R>(c.pl, c.cfg, psi, prop, tmp, real, c.s, false, fuse && n > 0));
     }
     LTRY(run_itp_pass2<R>(c.pl, c.cfg, tmp, prop, psi, real, c.s));
-    LTRY(run_finalize(c.pl, FIN_NORM_SCALE, nullptr, c.s));
+    if (!fuse || n == nsteps - 1) LTRY(run_finalize(c.pl, FIN_NORM_SCALE, nullptr, c.s));
   }
   if (nsteps > 0) LTRY(run_apply_scale<R>(c.pl, c.cfg, psi, real, c.s));
   return GPE_OK;

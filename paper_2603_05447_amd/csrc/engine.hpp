@@ -112,10 +112,12 @@ const char* family_name(int f);
 // R = double (complex128) or float (complex64).  `real`: the state is one R
 // per site (real imaginary time) instead of a complex pair.
 // raw_input: psi_raw already holds phi (run_itp_phi applied the diagonal
-// half-step and the scale), so pass 1 applies only the Euler substep
+// half-step and the scale), so pass 1 applies only the Euler substep.
+// scale_from_partials: the scale is formed from the norm partials of the
+// previous pass 2 (which then needs no finalize), not read from the instance
 template <typename R> hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw,
                                                const void* prop, void* tmp, bool real, hipStream_t s,
-                                               bool raw_input = false);
+                                               bool raw_input = false, bool scale_from_partials = false);
 // phi = s psi P (1 - g |s psi|^2 dt/2) site by site (s = the instance's scale)
 template <typename R> hipError_t run_itp_phi(const Plan& p, const LaunchConfig& cfg, const void* psi,
                                              const void* prop, void* phi, bool real, hipStream_t s);

@@ -225,6 +225,7 @@ template <typename R> struct PassArgs {
   double c_stage;   // stage time offset in units of dt
   int64_t step;     // step index; < 0: read the device step counter (graph replay)
   int use_scale;    // OBS: multiply Y by the instance's scale
+  int scale_from_partials;  // ITP1: form the scale from the norm partials of the last pass 2
   // OP_RKG: earlier stage states read at the site, their coefficients, the
   // coefficient of the stencil input itself and the k coefficient (in units of dt)
   int nh;
@@ -286,6 +287,22 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const R* const field2 = reinterpret_cast<const R*>(ip.field2);
   R scale = R(1);
   if (OP == OP_ITP1 || (OP == OP_OBS && a.use_scale)) scale = (R)pl.out[ch.inst].scale;
+  if constexpr (OP == OP_ITP1) {
+    if (a.scale_from_partials) {
+      // every workgroup sums the instance's norm partials in one fixed order
+      // (the grid is small: a few partials per lane) instead of a finalize launch
+      __shared__ double s_norm[BLOCK / 64];
+      double v = 0.0;
+      for (int c = ip.chunk_begin + (int)threadIdx.x; c < ip.chunk_begin + ip.chunk_count; c += BLOCK)
+        v += pl.partials[c];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if ((threadIdx.x & 63) == 0) s_norm[threadIdx.x >> 6] = v;
+      __syncthreads();
+      double n = 0.0;
+      for (int w = 0; w < BLOCK / 64; ++w) n += s_norm[w];
+      scale = (R)sqrt(ip.norm_target / (ip.dV * n));
+    }
+  }
   const R hg = g * dt * R(0.5);
   S zero;
   if constexpr (REAL) zero = R(0); else zero = cmk<R>(R(0), R(0));
@@ -768,6 +785,7 @@ static PassArgs<R> pass_args() {
   a.c_stage = 0.0;
   a.step = -1;
   a.use_scale = 0;
+  a.scale_from_partials = 0;
   a.nh = 0;
   for (int j = 0; j < RKG_MAX_HIST; ++j) {
     a.h[j] = nullptr;
@@ -780,9 +798,10 @@ static PassArgs<R> pass_args() {
 
 template <typename R>
 hipError_t run_itp_pass1(const Plan& p, const LaunchConfig& cfg, const void* psi_raw, const void* prop, void* tmp,
-                         bool real, hipStream_t s, bool raw_input) {
+                         bool real, hipStream_t s, bool raw_input, bool scale_from_partials) {
   using C = typename CT<R>::T;
   PassArgs<R> a = pass_args<R>();
+  a.scale_from_partials = scale_from_partials ? 1 : 0;
   a.Y = (const C*)psi_raw;
   a.prop = (const R*)prop;
   a.out = (C*)tmp;
@@ -1458,7 +1477,7 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
 // explicit instantiations
 #define GPE_INST(R)                                                                                            \
   template hipError_t run_itp_pass1<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \
-                                       bool, hipStream_t, bool);                                             \
+                                       bool, hipStream_t, bool, bool);                                       \
   template hipError_t run_itp_phi<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*, bool,  \
                                      hipStream_t);                                                           \
   template hipError_t run_itp_pass2<R>(const Plan&, const LaunchConfig&, const void*, const void*, void*,    \

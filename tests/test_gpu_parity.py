@@ -160,6 +160,23 @@ def test_every_launch_config_matches_the_oracle_on_a_fragmented_mask(dtype):
         assert err <= TOL[dtype], (k, err)
 
 
+@pytest.mark.parametrize("real", [False, True])
+def test_small_grid_scale_formed_in_pass1_equals_the_finalize_path(real):
+    """On small grids pass 1 forms the renormalisation scale from pass 2's
+    norm partials (no finalize launch); a run with an observation history
+    keeps the finalize.  Both give the same state to rounding."""
+    import torch
+    w = configs.small_shell(n=24)
+    c = Case(w, "c128")
+    a, b = c.psi(), c.psi()
+    if real:
+        a, b = a.real.contiguous(), b.real.contiguous()
+    c.grid.imag_time(a, c.pot, w.g, 2e-3, 30, observe=False)
+    hist = torch.zeros((1, 3), dtype=torch.float64, device="cuda:0")
+    c.grid.imag_time(b, c.pot, w.g, 2e-3, 30, obs_every=30, history=hist, observe=False)
+    assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-13
+
+
 def test_stream_copy_reference_kernel():
     import torch
     from paper_2603_05447_amd import GPEError, _lib, stream_copy
