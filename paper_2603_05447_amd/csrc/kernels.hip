@@ -300,7 +300,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       __syncthreads();
       double n = 0.0;
       for (int w = 0; w < BLOCK / 64; ++w) n += s_norm[w];
-      scale = (R)sqrt(ip.norm_target / (ip.dV * n));
+      // the same value in every lane: move it to scalar registers, where the
+      // stored scale lives, so the stencil code keeps its vector registers
+      const unsigned long long b = (unsigned long long)__double_as_longlong(sqrt(ip.norm_target / (ip.dV * n)));
+      const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+      const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+      scale = (R)__longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
     }
   }
   const R hg = g * dt * R(0.5);
