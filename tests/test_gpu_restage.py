@@ -101,6 +101,19 @@ def test_threshold_runs_cross_the_64_point_steps(n2):
     assert np.array_equal(g.runs()[:, :4], want)
 
 
+def test_threshold_with_nothing_selected_is_an_argument_error():
+    import torch
+    from paper_2603_05447_amd import Grid, GPEError, _lib
+    n = (4, 5, 70)
+    va = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(GPEError) as e:
+        Grid.from_threshold(n, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), va, None, 0.5, device=0)
+    assert e.value.status == _lib.GPE_ERR_ARG
+    with pytest.raises(GPEError) as e:       # NaN never passes the cut
+        Grid.from_threshold(n, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0), va * float("nan"), None, 2.0, device=0)
+    assert e.value.status == _lib.GPE_ERR_ARG
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_remap_is_exact(dtype):
     import torch
