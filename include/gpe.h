@@ -151,8 +151,9 @@ gpe_status gpe_grid_create_runs(const gpe_geometry* geom, int64_t nruns, const i
  * is 5 max(mu_i, mu_{i+1}).  The z-runs of the selection are found on the
  * device (one wave per (i, j) column; no box mask is formed) and only the run
  * table is copied to the host, where the segments are built as in
- * gpe_grid_create_runs; the call runs on the null stream and synchronises.
- * Errors as gpe_grid_create (an empty selection is GPE_ERR_ARG). */
+ * gpe_grid_create_runs; the call runs on the null stream and synchronises
+ * (potentials written on a non-blocking stream must be complete before the
+ * call).  Errors as gpe_grid_create (an empty selection is GPE_ERR_ARG). */
 gpe_status gpe_grid_create_threshold(const gpe_geometry* geom, gpe_dtype dtype, const void* va_box,
                                      const void* vb_box, double cutoff, int device, gpe_grid* out);
 
