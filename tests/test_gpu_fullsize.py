@@ -90,16 +90,17 @@ def test_c2_rk4_step_sampled(c2, dtype, tol):
     assert abs(o["norm"] - n0) <= bound + (0 if dtype == "c128" else 1e-5)
 
 
-def test_c2_imag_time_step_sampled(c2):
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-5)])
+def test_c2_imag_time_step_sampled(c2, dtype, tol):
     import torch
     from paper_2603_05447_amd import Grid, Potential
     w, ijk = c2
     g = Grid.from_box(w.box, runs=w.runs, device=0)
-    U = torch.tensor(w.field, dtype=torch.float64, device="cuda:0")
-    psi = torch.tensor(w.psi0, dtype=torch.complex128, device="cuda:0")
+    U = torch.tensor(w.field, dtype=torch.float64 if dtype == "c128" else torch.float32, device="cuda:0")
+    psi = torch.tensor(w.psi0, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda:0")
     d = w.extra["delta_itp"]
     obs = g.imag_time(psi, Potential.rf(U, w.omega, [0.0], [d]), w.g, w.dt, 1)
-    assert abs(obs["norm"] - 1.0) < 1e-12
+    assert abs(obs["norm"] - 1.0) < (1e-12 if dtype == "c128" else 1e-6)
     out = psi.cpu().numpy()
     got, ref = [], []
     for s in _samples(w, ijk, seed=1):
@@ -112,5 +113,5 @@ def test_c2_imag_time_step_sampled(c2):
     scale = np.real(np.vdot(ref, got)) / np.real(np.vdot(ref, ref))   # the global 1/sqrt(norm)
     assert scale > 0
     err = np.linalg.norm(got - scale * ref) / np.linalg.norm(scale * ref)
-    print(f"C2 ITP sampled rel L2 (up to the global scale) = {err:.3e}", flush=True)
-    assert err <= 1e-10
+    print(f"C2 ITP {dtype} sampled rel L2 (up to the global scale) = {err:.3e}", flush=True)
+    assert err <= tol
