@@ -12,7 +12,7 @@ conservation) are checked on the whole array."""
 import numpy as np
 import pytest
 
-from oracle import operator as op, itp, realtime as rt
+from oracle import operator as op, itp, realtime as rt, tableau
 from oracle.potential import RFRamp
 from workloads import configs, site_ijk
 
@@ -88,6 +88,33 @@ def test_c2_rk4_step_sampled(c2, dtype, tol):
     bound = 20 * (lam * w.dt) ** 6 / 72 * n0
     print(f"  norm change over 20 steps {o['norm'] - n0:.3e} (bound {bound:.3e})", flush=True)
     assert abs(o["norm"] - n0) <= bound + (0 if dtype == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("integrator", ["rkhe3", "rkck"])
+def test_c2_rkhe3_rkck_step_sampled(c2, integrator):
+    """One step of each of the other integrators on the whole headline grid
+    (complex128) against the oracle's Butcher-form step on patches (RKCK has
+    six stages, so its patches reach 7 sites)."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    w, ijk = c2
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    U = torch.tensor(w.field, dtype=torch.float64, device="cuda:0")
+    psi = torch.tensor(w.psi0, dtype=torch.complex128, device="cuda:0")
+    d = w.extra["delta_rt"]
+    g.real_time(psi, Potential.rf(U, w.omega, [0.0], [d]), w.g, w.dt, 1, observe=False, integrator=integrator)
+    out = psi.cpu().numpy()
+    A, b = tableau.heun3() if integrator == "rkhe3" else tableau.cash_karp5()
+    got, ref = [], []
+    for s in _samples(w, ijk, count=24, seed=2):
+        idx, T, c = _patch(w, ijk, s, R=7)
+        ramp = RFRamp(w.field[idx], w.omega, [0.0], [d])
+        ref.append(rt.rk_step_tableau(T, w.psi0[idx], 0.0, w.dt, ramp, w.g, A, b)[c])
+        got.append(out[s])
+    got, ref = np.array(got), np.array(ref)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"C2 {integrator} sampled rel L2 = {err:.3e}", flush=True)
+    assert err <= 1e-10
 
 
 @pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-5)])
