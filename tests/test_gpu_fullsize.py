@@ -41,6 +41,17 @@ def _patch(w, ijk, s, R=R_PATCH):
     return idx, T, centre
 
 
+def _patch_op(w, ijk, s, R=R_PATCH, points=7):
+    """The active sites within R of site s, the chosen operator on them, and
+    the position of s among them."""
+    i, j, k = ijk
+    sel = (np.abs(i - i[s]) <= R) & (np.abs(j - j[s]) <= R) & (np.abs(k - k[s]) <= R)
+    idx = np.nonzero(sel)[0]
+    lin = (i[idx] * w.box.n[1] + j[idx]) * w.box.n[2] + k[idx]
+    build = {7: op.kinetic_direct, 19: op.kinetic_direct_19, 27: op.kinetic_direct_27}[points]
+    return idx, build(w.box.n, w.box.h, lin), int(np.searchsorted(idx, s))
+
+
 def _samples(w, ijk, count=40, seed=0):
     rng = np.random.default_rng(seed)
     n = w.n_active
@@ -115,6 +126,42 @@ def test_c2_rkhe3_rkck_step_sampled(c2, integrator):
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"C2 {integrator} sampled rel L2 = {err:.3e}", flush=True)
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("points", [19, 27])
+def test_c2_hoc_rk4_and_imag_time_steps_sampled(c2, points):
+    """The 19- and 27-point stencils on the whole headline grid (complex128):
+    one RK4 step and one imaginary-time step against the oracle's operator of
+    the same stencil on patches (the imaginary-time result up to its global
+    renormalisation factor)."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    w, ijk = c2
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    g.set_stencil(points)
+    U = torch.tensor(w.field, dtype=torch.float64, device="cuda:0")
+    d_rt, d_itp = w.extra["delta_rt"], w.extra["delta_itp"]
+    p_rt = torch.tensor(w.psi0, dtype=torch.complex128, device="cuda:0")
+    g.real_time(p_rt, Potential.rf(U, w.omega, [0.0], [d_rt]), w.g, w.dt, 1, observe=False)
+    p_itp = torch.tensor(w.psi0, dtype=torch.complex128, device="cuda:0")
+    g.imag_time(p_itp, Potential.rf(U, w.omega, [0.0], [d_itp]), w.g, w.dt, 1, observe=False)
+    o_rt, o_itp = p_rt.cpu().numpy(), p_itp.cpu().numpy()
+    got_rt, ref_rt, got_itp, ref_itp = [], [], [], []
+    for s in _samples(w, ijk, count=16, seed=3):
+        idx, T, c = _patch_op(w, ijk, s, points=points)
+        ref_rt.append(rt.rk4_step(T, w.psi0[idx], 0.0, w.dt, RFRamp(w.field[idx], w.omega, [0.0], [d_rt]), w.g)[c])
+        V = np.sqrt((w.field[idx] - d_itp) ** 2 + w.omega ** 2)
+        y, nrm = itp.itp_step(T, w.psi0[idx], itp.propagator(V, w.dt), w.g, w.dt, w.box.dV)
+        ref_itp.append(y[c] * np.sqrt(nrm))
+        got_rt.append(o_rt[s])
+        got_itp.append(o_itp[s])
+    got_rt, ref_rt = np.array(got_rt), np.array(ref_rt)
+    err_rt = np.linalg.norm(got_rt - ref_rt) / np.linalg.norm(ref_rt)
+    got_itp, ref_itp = np.array(got_itp), np.array(ref_itp)
+    scale = np.real(np.vdot(ref_itp, got_itp)) / np.real(np.vdot(ref_itp, ref_itp))
+    err_itp = np.linalg.norm(got_itp - scale * ref_itp) / np.linalg.norm(scale * ref_itp)
+    print(f"C2 {points}-point: RK4 sampled rel L2 {err_rt:.3e}, ITP {err_itp:.3e}", flush=True)
+    assert err_rt <= 1e-10 and scale > 0 and err_itp <= 1e-10
 
 
 @pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-5)])
