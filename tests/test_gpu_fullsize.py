@@ -12,9 +12,9 @@ conservation) are checked on the whole array."""
 import numpy as np
 import pytest
 
-from oracle import operator as op, itp, realtime as rt, tableau
+from oracle import operator as op, itp, realtime as rt, restage, tableau
 from oracle.potential import RFRamp
-from workloads import configs, site_ijk
+from workloads import configs, runs_from_mask, site_ijk, site_linear_index
 
 pytestmark = pytest.mark.gpu
 R_PATCH = 6
@@ -189,3 +189,31 @@ def test_c2_imag_time_step_sampled(c2, dtype, tol):
     err = np.linalg.norm(got - scale * ref) / np.linalg.norm(scale * ref)
     print(f"C2 ITP {dtype} sampled rel L2 (up to the global scale) = {err:.3e}", flush=True)
     assert err <= tol
+
+
+def test_c2_post_selection_and_remap_on_the_full_box(c2):
+    """A staged-ramp stage at full size: the device post-selection of the
+    537M-point box (min(V_a, V_b) < 27, Delta 60 -> 62) equals the runs of the
+    same selection made on the host, bit for bit, and psi carried over to the
+    new grid equals the oracle's remap."""
+    import torch
+    from paper_2603_05447_amd import Grid
+    w, ijk = c2
+    box = w.box
+    ax = [torch.tensor(box.axis(d), dtype=torch.float64, device="cuda:0") for d in range(3)]
+    U = 0.5 * (ax[0][:, None, None] ** 2 + ax[1][None, :, None] ** 2 + 4.0 * ax[2][None, None, :] ** 2)
+    Va = torch.sqrt((U - 60.0) ** 2 + 4.0).contiguous()
+    Vb = torch.sqrt((U - 62.0) ** 2 + 4.0).contiguous()
+    del U
+    g2 = Grid.from_threshold(box.n, box.h, box.x0, Va, Vb, 27.0, device=0)
+    mask = (torch.minimum(Va, Vb) < 27.0).cpu().numpy()
+    del Va, Vb
+    want = runs_from_mask(mask)
+    del mask
+    print(f"full-box post-selection: {g2.n_active} sites in {want.shape[0]} runs", flush=True)
+    assert np.array_equal(g2.runs()[:, :4], want)
+    g1 = Grid.from_box(box, runs=w.runs, device=0)
+    psi = torch.tensor(w.psi0, dtype=torch.complex128, device="cuda:0")
+    out = g2.remap_from(g1, psi).cpu().numpy()
+    ref = restage.remap(w.psi0, site_linear_index(box, w.runs), site_linear_index(box, want))
+    assert np.array_equal(out, ref)
