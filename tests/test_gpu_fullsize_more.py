@@ -6,8 +6,9 @@ configuration:
   2000-step loss against central differences of the GPU forward loss (a
   property that holds at any size).
 * C4 (64 instances, 34.7M sites): the batched launches equal single-grid
-  runs of sampled instances, and one instance's three RK4 steps equal the
-  oracle run on the whole instance.
+  runs of sampled instances, one instance's three RK4 steps equal the
+  oracle run on the whole instance, and the batched forward + adjoint gives
+  sampled instances their single-grid loss and gradient.
 * C5 (thin shell, 2048 x 2048 x 1024 box, 59.7M sites): one RK4 step in
   complex128 and complex64 against the oracle on patches.
 
@@ -162,6 +163,38 @@ def test_c4_batch_equals_single_grids_and_oracle():
     err = rel_l2(p.cpu().numpy(), ref)
     print(f"C4 instance 5 ({w.n_active} sites): rel L2 {err:.3e}", flush=True)
     assert err <= 1e-10
+
+
+def test_c4_batched_forward_adjoint_equals_single_grids():
+    """The batched forward + adjoint (one call for all 64 instances, complex64
+    storage, hipGraph forward) gives each sampled instance the loss and knot
+    gradient of its own single-grid call."""
+    import torch
+    from paper_2603_05447_amd import Grid, Batch, Potential
+    ws = [configs.c4_instance(i) for i in range(64)]
+    grids = [Grid.from_box(w.box, runs=w.runs, device=0) for w in ws]
+    b = Batch(grids, device=0)
+    rng = np.random.default_rng(8)
+    tg = []
+    for w in ws:
+        t = w.psi0 * np.exp(1j * rng.uniform(0.0, 0.3, w.n_active))
+        tg.append(t / np.sqrt(np.sum(np.abs(t) ** 2) * w.box.dV))
+    psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=torch.complex64, device="cuda:0")
+    target = torch.tensor(np.concatenate(tg), dtype=torch.complex64, device="cuda:0")
+    field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=torch.float32, device="cuda:0")
+    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    steps = 60
+    loss, grads = b.fidelity_grad(psi, target, field, ramps, [w.g for w in ws], [w.dt for w in ws], steps,
+                                  use_graph=True)
+    print(f"C4 full size batched adjoint: {b.total} sites, {steps} steps", flush=True)
+    for i in (0, 31, 63):
+        w = ws[i]
+        U = torch.tensor(w.field, dtype=torch.float32, device="cuda:0")
+        p0 = torch.tensor(w.psi0, dtype=torch.complex64, device="cuda:0")
+        t0 = torch.tensor(tg[i], dtype=torch.complex64, device="cuda:0")
+        l1, g1 = grids[i].fidelity_grad(p0, t0, Potential.rf(U, w.omega, w.knot_t, w.knot_delta), w.g, w.dt, steps)
+        assert abs(loss[i] - l1) <= 1e-6, i
+        assert np.max(np.abs(grads[i] - g1)) <= 1e-5 * np.max(np.abs(g1)), i
 
 
 @pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-5)])
