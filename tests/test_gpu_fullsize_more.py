@@ -10,7 +10,8 @@ configuration:
   oracle run on the whole instance, and the batched forward + adjoint gives
   sampled instances their single-grid loss and gradient.
 * C5 (thin shell, 2048 x 2048 x 1024 box, 59.7M sites): one RK4 step in
-  complex128 and complex64 against the oracle on patches.
+  complex128 and complex64 against the oracle on patches, and a 20-step
+  prefix against the oracle on subdomains of radius 88.
 
 Patches: the active sites within 6 sites of a sampled site (one RK4 step
 moves information 4 sites), found through the run table."""
@@ -201,3 +202,38 @@ def test_c4_batched_forward_adjoint_equals_single_grids():
 def test_c5_rk4_step_sampled(dtype, tol):
     w = configs.c5()
     _sampled_rk4(w, dtype, 0.0, tol, 5)
+
+
+def test_c5_twenty_step_prefix_against_the_oracle_on_subdomains():
+    """The precision study's oracle check: 20 RK4 steps of the 59.7M-site
+    shell in complex128 and complex64, against the FP64 oracle run on
+    subdomains of radius 88 around sampled sites.  Information moves at most
+    4 sites per step, so every site within 8 of the centre is exact in the
+    subdomain run; those sites are compared."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    w = configs.c5()
+    steps, R, inner = 20, 88, 8
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    out = {}
+    for dtype, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
+        U = torch.tensor(w.field, dtype=rdt, device="cuda:0")
+        psi = torch.tensor(w.psi0, dtype=cdt, device="cuda:0")
+        g.real_time(psi, Potential.rf(U, w.omega, w.knot_t, w.knot_delta), w.g, w.dt, steps, observe=False)
+        out[dtype] = psi.cpu().numpy()
+        del U, psi
+    ri = RunIndex(w)
+    rng = np.random.default_rng(6)
+    for s in (int(v) for v in rng.integers(0, w.n_active, 2)):
+        idx, T, c = ri.patch(s, R)
+        ramp = RFRamp(w.field[idx], w.omega, w.knot_t, w.knot_delta)
+        ref = rt.real_time(T, w.psi0[idx], ramp, w.g, w.dt, 0.0, steps)
+        q = np.searchsorted(ri.start, idx, side="right") - 1
+        ii, jj = w.runs[q, 0], w.runs[q, 1]
+        kk = w.runs[q, 2] + (idx - ri.start[q])
+        ci, cj, ck = ri.site(s)
+        near = (np.abs(ii - ci) <= inner) & (np.abs(jj - cj) <= inner) & (np.abs(kk - ck) <= inner)
+        for dtype, tol in (("c128", 1e-10), ("c64", 1e-5)):
+            err = rel_l2(out[dtype][idx[near]], ref[near])
+            print(f"C5 20-step prefix, site {s}, {near.sum()} sites near it, {dtype}: rel L2 {err:.3e}", flush=True)
+            assert err <= tol
