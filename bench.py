@@ -13,7 +13,9 @@ adjoint gradient rate on the 256^3 hollowing ramp (grads/s vs plain FP64
 forward runs), the 64-instance batched sweep (hipGraph; forward, and forward
 plus adjoint in complex64 against complex128), per-kernel timing
 (HIP events on the launch stream) with the roofline of the dominant kernel,
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+the FP64 CPU oracle timed on a bounded sample of the same workload, the
+headline job end to end (5k imaginary-time + 10k RK4 steps, both
+precisions) and 200 steps of the 60M-site precision study.
 """
 from __future__ import annotations
 
@@ -712,14 +714,21 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--int-steps", type=int, default=100, help="steps per integrator in the RKHE3/RK4/RKCK leg")
-    ap.add_argument("--c5", type=int, default=0, help="run the 60M-site FP32-vs-FP64 study for this many steps")
-    ap.add_argument("--job", action="store_true",
-                    help="also run the headline job end to end (imaginary then real time) in both precisions")
+    ap.add_argument("--c5", type=int, default=None,
+                    help="steps of the 60M-site FP32-vs-FP64 study (default 200, 0 with --no-extras; "
+                         "the full study is 20000)")
+    ap.add_argument("--job", action=argparse.BooleanOptionalAction, default=None,
+                    help="run the headline job end to end (imaginary then real time) in both precisions "
+                         "(default: on, off with --no-extras)")
     ap.add_argument("--job-itp", type=int, default=5000)
     ap.add_argument("--job-rt", type=int, default=10000)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.c5 is None:
+        args.c5 = 0 if args.no_extras else 200
+    if args.job is None:
+        args.job = not args.no_extras
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
