@@ -150,6 +150,25 @@ def test_graph_replay_equals_eager_repeatedly():
         assert torch.equal(psi, ref), rep
 
 
+def test_graph_cache_eviction_keeps_results():
+    """More distinct buffer sets than the per-grid graph cache holds: the
+    cache is emptied (after the device is idle) and rebuilt, and every
+    replayed run still equals the eager one."""
+    import torch
+    ws = _instances(3, 4)
+    b, psi, field, ramps = _batch(ws, "c128")
+    gs, dts = [w.g for w in ws], [w.dt for w in ws]
+    kept = []                          # live buffers: every run has its own addresses
+    for rep in range(20):
+        p = psi.clone()
+        q = psi.clone()
+        kept += [p, q]
+        b.real_time(p, field, ramps, gs, dts, 3, use_graph=True, observe=False)
+        b.real_time(q, field, ramps, gs, dts, 3, use_graph=False, observe=False)
+        assert torch.equal(p, q), rep
+    assert len({t.data_ptr() for t in kept}) == len(kept)
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_batch_fidelity_grad_matches_single(use_graph):
     ws = _instances(3, 8)
