@@ -143,3 +143,33 @@ def test_real_start_stays_real_and_phase_is_carried():
     ph = np.exp(0.7j)
     rot, _ = itp.imaginary_time(T, ph * x, w.field, w.g, dt, w.box.dV, 12)
     assert np.max(np.abs(rot - ph * out.real)) <= 1e-13 * np.max(np.abs(out))
+
+
+def test_virial_theorem_of_the_interacting_harmonic_ground_state():
+    """For V = r^2/2 the ground state of the GP energy satisfies the virial
+    identity 2 E_kin - 2 E_pot + 3 E_int = 0 (scaling psi(x) -> l^{3/2}
+    psi(l x) keeps the norm and leaves E stationary at l = 1).  E_kin and
+    E_pot are computed here from their definitions; E_int is mu - E of the
+    oracle's observables, so a wrong weight of the |psi|^4 term in E or mu,
+    or of the kinetic term, breaks the identity by O(E).  The imaginary-time
+    fixed point carries a residual linear in dt and the grid one of O(h^2)
+    (measured: about 1.24 dt + 0.08 h^2), so the test halves dt, checks the
+    residual falls, and bounds its dt -> 0 extrapolation."""
+    box, runs, lin = _full_box(32, 4.8)
+    T = op.kinetic_direct(box.n, box.h, lin)
+    x, y, z = site_coords(box, runs)
+    V = 0.5 * (x * x + y * y + z * z)
+    g = 30.0
+    psi0 = normalise_input(np.exp(-0.4 * (x * x + y * y + z * z)).astype(complex), box.dV)
+    res = []
+    for dt, steps in ((0.01, 1500), (0.005, 3000)):
+        psi, _ = itp.imaginary_time(T, psi0, V, g, dt, box.dV, steps)
+        N, E, mu = ob.energy_mu(T, psi, V, g, box.dV)
+        e_kin = float(np.real(np.vdot(psi, op.apply(T, psi)))) * box.dV / N
+        e_pot = float(np.sum(V * np.abs(psi) ** 2)) * box.dV / N
+        e_int = mu - E
+        assert abs(E - (e_kin + e_pot + e_int)) <= 1e-12 * E
+        assert e_int > 0.1 * E                    # the interaction matters at this g
+        res.append(2 * e_kin - 2 * e_pot + 3 * e_int)
+    assert 0 < res[1] < res[0] < 0.01 * E
+    assert abs(2 * res[1] - res[0]) <= 5e-3 * E   # the O(h^2) part, h = 0.3
