@@ -29,6 +29,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The CPU baseline is the oracle on one core: BLAS/OpenMP pools are pinned to
+# one thread before NumPy/SciPy load (the GPU legs do not use them).
+for _v in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS", "BLIS_NUM_THREADS",
+           "NUMEXPR_NUM_THREADS", "VECLIB_MAXIMUM_THREADS"):
+    os.environ[_v] = "1"
+
 import numpy as np  # noqa: E402
 
 METRIC = "active-site GPE updates/s + % HBM roofline; adjoint grads/s vs plain FP64"
@@ -75,11 +81,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(family: str):
-    """Calibrated HBM bytes per launch of `family` from the committed
-    rocprofv3 summary (profiles/*.txt, FETCH_SIZE + WRITE_SIZE scaled by a
-    copy kernel of known size), or None when no summary was taken on the
-    current kernel source."""
+_WORKLOADS = {}
+
+
+def workload(name: str, *args):
+    """Seeded workload, built once per run (the 60M-site shell takes a while)."""
+    key = (name,) + args
+    if key not in _WORKLOADS:
+        from workloads import configs
+        t = time.time()
+        _WORKLOADS[key] = getattr(configs, name)(*args)
+        log(f"[bench] {name}{args}: {_WORKLOADS[key].n_active} sites ({time.time() - t:.1f}s)")
+    return _WORKLOADS[key]
+
+
+# Algorithmic bytes per active site per time step of the whole step (each
+# stencil input read once per stage, each stored state written once), the
+# figures the roofline targets are stated in: imaginary time 2 passes, RK4
+# the four memory-optimised stages in the App. A storage scheme.
+STEP_BYTES = {"itp": {"c128": 80, "c64": 40}, "rk4": {"c128": 240, "c64": 120}}
+
+
+def step_roofline(n: int, ms_per_step: float, phase: str, dtype: str) -> dict:
+    b = STEP_BYTES[phase][dtype]
+    gbps = b * n / (ms_per_step * 1e-3) / 1e9
+    return {"bytes_per_site_step": b, "ms_per_step": ms_per_step, "site_updates_per_s": n / (ms_per_step * 1e-3),
+            "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS}
+
+
+def profiled_traffic(family: str, workload: str = "c2_c128"):
+    """Calibrated HBM bytes per launch of `family` on `workload` from the
+    committed rocprofv3 summaries (profiles/*.txt, FETCH_SIZE + WRITE_SIZE
+    scaled by a copy kernel of known size), or None when no summary was taken
+    on the current kernel source."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2603_05447_amd", "csrc", "kernels.hip")
@@ -89,20 +123,45 @@ def profiled_traffic(family: str):
             if not line.startswith("TRAFFIC "):
                 continue
             kv = dict(item.split("=", 1) for item in line.split()[1:])
-            if kv.get("family") == family and kv.get("sha256") == sha:
+            if kv.get("family") == family and kv.get("sha256") == sha and kv.get("workload", "c2_c128") == workload:
                 return int(kv["fetch_bytes"]) + int(kv["write_bytes"]), os.path.basename(f)
     return None, None
 
 
 def cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it: model name, family/model/stepping,
+    clock and the number of logical CPUs the kernel reports."""
+    info = {}
+    n = 0
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k == "processor":
+                    n += 1
+                if k in ("model name", "cpu family", "model", "stepping", "cpu MHz", "cache size") and k not in info:
+                    info[k] = v
     except OSError:
         pass
-    return platform.processor() or "unknown"
+    if not info:
+        return platform.processor() or "unknown"
+    return (f"{info.get('model name', '?')} (family {info.get('cpu family', '?')}, model {info.get('model', '?')}, "
+            f"stepping {info.get('stepping', '?')}, {info.get('cpu MHz', '?')} MHz, cache {info.get('cache size', '?')}, "
+            f"{n} logical CPUs in /proc/cpuinfo)")
+
+
+def cpu_threads() -> dict:
+    """Threads the oracle's numeric libraries may use (all pinned to one)."""
+    out = {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "MKL_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    try:
+        from threadpoolctl import threadpool_info
+        out["threadpools"] = [{"api": d.get("internal_api"), "num_threads": d.get("num_threads")}
+                              for d in threadpool_info()]
+    except Exception as e:   # threadpoolctl is optional
+        out["threadpools"] = f"unavailable: {e}"
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -166,6 +225,35 @@ def achievable_copy_gbps(dev, mib: int = 1024, reps: int = 10) -> float:
     return 2.0 * (mib << 20) / (us * 1e-6) / 1e9
 
 
+def kernel_table(kern: dict, R: int, scheme: int, n: int) -> dict:
+    """Per kernel family: launches, average duration (HIP events on the launch
+    stream) and algorithmic GB/s."""
+    kernels = {}
+    for fam, v in kern.items():
+        if v["launches"] == 0:
+            continue
+        avg_us = 1e3 * v["total_ms"] / v["launches"]
+        b = algo_bytes(fam, R, scheme) * n
+        kernels[fam] = {"launches": v["launches"], "avg_us": avg_us, "total_ms": v["total_ms"],
+                        "algo_bytes_per_launch": b, "GBps": (b / (avg_us * 1e-6) / 1e9) if b else None}
+    return kernels
+
+
+def dominant_roofline(kern: dict, workload: str, copy_gbps=None, use_profile: bool = True) -> dict:
+    """Roofline of the kernel family that takes the most time."""
+    dom = max((f for f in kern if kern[f]["GBps"] is not None), key=lambda f: kern[f]["total_ms"])
+    k = kern[dom]
+    traffic, tsrc = profiled_traffic(dom, workload) if use_profile else (None, None)
+    r = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+         "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": traffic, "traffic_unit": "bytes/launch",
+         "traffic_source": tsrc, "algo_bytes_per_launch": k["algo_bytes_per_launch"],
+         "avg_launch_us": k["avg_us"], "launches": k["launches"]}
+    if copy_gbps:
+        r["achievable_copy_GBps"] = copy_gbps
+        r["frac_of_copy"] = k["GBps"] / copy_gbps
+    return r
+
+
 def bench_c2(args, dev, dtype, report):
     import torch
     from paper_2603_05447_amd import KernelTimer
@@ -213,16 +301,10 @@ def bench_c2(args, dev, dtype, report):
         "final_norm": obs["norm"],
         "config": g.get_config(),
         "autotune": tune,
+        "step_roofline": {"itp": step_roofline(n, ms_itp / args.steps, "itp", dtype),
+                          "rk4": step_roofline(n, ms_rt / (2 * args.steps), "rk4", dtype)},
     }
-    kernels = {}
-    for fam, v in kern.items():
-        if v["launches"] == 0:
-            continue
-        avg_us = 1e3 * v["total_ms"] / v["launches"]
-        b = algo_bytes(fam, R, scheme) * n
-        kernels[fam] = {"launches": v["launches"], "avg_us": avg_us, "total_ms": v["total_ms"],
-                        "algo_bytes_per_launch": b, "GBps": (b / (avg_us * 1e-6) / 1e9) if b else None}
-    res["kernels"] = kernels
+    res["kernels"] = kernel_table(kern, R, scheme, n)
     report[dtype] = res
     del psi, U, g
     torch.cuda.empty_cache()
@@ -440,7 +522,7 @@ def cpu_baseline(args):
             "sample": f"FP64 NumPy/SciPy oracle, single thread, on x-planes [448,576) of the headline grid "
                       f"({idx.size} active sites); median of {reps} repeats of 1 imaginary-time + 2 RK4 steps "
                       f"(operator build {t_build:.1f}s not counted)",
-            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count()}
+            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count(), "threads": cpu_threads()}
 
 
 def _slab(w, i_lo, i_hi):
@@ -496,7 +578,7 @@ def cpu_per_config(report):
         c4["gpu_site_updates_per_s_c64_batched"] = report["batched_c4"]["graph"]["site_updates_per_s"]
     out["c4_sampled"] = c4
     # C5: slab of x-planes, two RK4 steps
-    w = configs.c5()
+    w = workload("c5")
     runs, idx = _slab(w, 960, 1088)
     T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, runs))
     ramp = RFRamp(w.field[idx], w.omega, w.knot_t, w.knot_delta)
@@ -509,7 +591,21 @@ def cpu_per_config(report):
     if "precision_c5" in report:
         c5["gpu_site_updates_per_s_c128"] = report["precision_c5"]["c128"]["site_updates_per_s"]
     out["c5_slab"] = c5
+    # C5 subdomain (the shell shrunk 8x per axis, same thickness in grid
+    # units): a 20-step prefix of the 20,000-step study
+    w = workload("c5_subdomain", 8)
+    T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, w.runs))
+    ramp = RFRamp(w.field, w.omega, w.knot_t, w.knot_delta)
+    t = time.perf_counter()
+    rt.real_time(T, w.psi0, ramp, w.g, w.dt, 0.0, 20)
+    el = time.perf_counter() - t
+    sub = {"sample": f"{w.name} ({w.n_active} sites), the first 20 of 20,000 RK4 steps",
+           "site_updates_per_s": w.n_active * 20 / el}
+    if "c5_subdomain" in report:
+        sub["gpu_site_updates_per_s_c128"] = report["c5_subdomain"]["c128"]["site_updates_per_s"]
+    out["c5_subdomain_prefix"] = sub
     out["cores"] = 1
+    out["threads"] = cpu_threads()
     return out
 
 
@@ -568,8 +664,17 @@ def bench_batched(args, dev, report):
     gs, dts = [w.g for w in ws], [w.dt for w in ws]
     work = torch.empty(b.work_bytes(GPE_C64, GPE_MODE_RT, 1), dtype=torch.uint8, device=dev)
     from paper_2603_05447_amd import config_describe
-    scheme = config_describe(0)["rk_scheme"]     # batches use launch variant 0 unless set
-    out = {}
+    # the batch's own launch variant: timed over every variant on replayed steps of this batch
+    scratch = psi.clone()
+    t = time.perf_counter()
+    best, times = b.autotune(scratch, field, ramps, gs, dts, reps=3, use_graph=True)
+    t_tune = time.perf_counter() - t
+    del scratch
+    log(f"[bench] C4 batch autotune: variant {best} ({config_describe(best)}), "
+        f"{times[best]:.3f} ms/step vs variant 0 {times[0]:.3f} ms/step ({t_tune:.1f} s)")
+    scheme = config_describe(best)["rk_scheme"]
+    out = {"autotune": {"best": best, "ms_per_step": {str(k): v for k, v in enumerate(times)},
+                        "variant": config_describe(best), "tune_s": t_tune}}
     for use_graph in (False, True):
         b.real_time(psi, field, ramps, gs, dts, 5, use_graph=use_graph, work=work, observe=False)
         torch.cuda.synchronize()
@@ -580,6 +685,7 @@ def bench_batched(args, dev, report):
             "s": el, "site_updates_per_s": b.total * args.batch_steps / el,
             "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 4, scheme) for i in range(1, 5)) * b.total * args.batch_steps
             / el / 1e9,
+            "step_roofline": step_roofline(b.total, 1e3 * el / args.batch_steps, "rk4", "c64"),
             "norm_min": min(o["norm"] for o in obs), "norm_max": max(o["norm"] for o in obs)}
     # forward + adjoint of every instance in one batched call (sqrt(N) checkpoints), complex64 storage
     # against complex128 throughout: loss and 8 knot gradients per instance
@@ -629,29 +735,42 @@ def bench_c5(args, dev, report):
     import torch
     from paper_2603_05447_amd import Grid, Potential, config_describe
     from workloads import configs
-    t = time.time()
-    w = configs.c5()
-    log(f"[bench] C5 inputs: {w.n_active} sites ({time.time() - t:.1f}s)")
+    w = workload("c5")
     g = Grid.from_box(w.box, runs=w.runs, device=0)
     out = {"workload": w.name, "n_active": w.n_active, "steps": args.c5}
     n0 = float(np.sum(np.abs(w.psi0) ** 2)) * w.box.dV
     res = {}
+    from paper_2603_05447_amd import KernelTimer
+    scheme = config_describe(g.get_config())["rk_scheme"]
     for dtype, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
+        R = 8 if dtype == "c128" else 4
         U = torch.tensor(w.field, dtype=rdt, device=dev)
         psi = torch.tensor(w.psi0, dtype=cdt, device=dev)
         pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
         g.real_time(psi, pot, w.g, w.dt, 2, observe=False)
+        # a short leg with per-kernel HIP-event timing on the launch stream
+        with KernelTimer() as kt:
+            g.real_time(psi, pot, w.g, w.dt, 20, observe=False, check_stability=False)
+            kern = kernel_table(kt.read(), R, scheme, w.n_active)
         psi.copy_(torch.tensor(w.psi0, dtype=cdt, device=dev))
         e0 = g.observe(psi, pot, 0.0, w.g)["energy"]
         torch.cuda.synchronize()
+        s_ = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t = time.perf_counter()
+        ev0.record(s_)
         obs = g.real_time(psi, pot, w.g, w.dt, args.c5)
+        ev1.record(s_)
+        torch.cuda.synchronize()
         el = time.perf_counter() - t
+        ms_step = ev0.elapsed_time(ev1) / args.c5
         res[dtype] = psi.to(torch.complex128).cpu().numpy()
         out[dtype] = {"s": el, "site_updates_per_s": w.n_active * args.c5 / el,
-                      "eff_GBps": sum(algo_bytes(f"rk_stage{i}", 8 if dtype == "c128" else 4,
-                                                 config_describe(g.get_config())["rk_scheme"]) for i in range(1, 5))
+                      "eff_GBps": sum(algo_bytes(f"rk_stage{i}", R, scheme) for i in range(1, 5))
                       * w.n_active * args.c5 / el / 1e9,
+                      "step_roofline": step_roofline(w.n_active, ms_step, "rk4", dtype),
+                      "kernels": kern,
+                      "roofline": dominant_roofline(kern, f"c5_{dtype}", use_profile=g.get_config() == 0),
                       "norm_drift": obs["norm"] - n0, "energy_start": e0, "energy": obs["energy"]}
         del U, psi
         g.release_work()
@@ -661,6 +780,62 @@ def bench_c5(args, dev, report):
     ov = np.vdot(b, a)
     out["c64_vs_c128_phase_aligned"] = float(1.0 - abs(ov) / (np.linalg.norm(a) * np.linalg.norm(b)))
     report["precision_c5"] = out
+
+
+def bench_c5_subdomain(args, dev, report):
+    """The precision study over its full horizon on the downscaled shell
+    (2048 x 2048 x 1024 shrunk 8x per axis, 931,864 sites, the same thickness
+    in grid units): 20,000 RK4 steps in complex128 and complex64 against the
+    FP64 oracle's stored run (sampled sites after 20 / 200 / 2,000 / 20,000
+    steps, norm and energy), when the stored run is present."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    w = workload("c5_subdomain", 8)
+    ref = None
+    path = os.path.join(ROOT, "tests", "golden", "c5_subdomain_s8.npz")
+    if os.path.exists(path):
+        ref = np.load(path)
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    out = {"workload": w.name, "n_active": w.n_active, "steps": w.steps, "oracle_reference": ref is not None}
+    n0 = float(np.sum(np.abs(w.psi0) ** 2)) * w.box.dV
+    for dtype, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
+        U = torch.tensor(w.field, dtype=rdt, device=dev)
+        psi = torch.tensor(w.psi0, dtype=cdt, device=dev)
+        pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
+        res = {"errors_vs_oracle": {}}
+        done, t_run = 0, 0.0
+        for stop in (20, 200, 2000, w.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            obs = g.real_time(psi, pot, w.g, w.dt, stop - done, t0=done * w.dt)
+            t_run += time.perf_counter() - t
+            done = stop
+            if ref is not None:
+                k = list(ref["sample_steps"]).index(stop)
+                idx = torch.as_tensor(ref["sample_index"], device=dev)
+                got = psi[idx].to(torch.complex128).cpu().numpy()
+                want = ref["samples"][k]
+                ov = np.vdot(want, got)
+                res["errors_vs_oracle"][str(stop)] = {
+                    "rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+                    "phase_aligned": float(1.0 - abs(ov) / (np.linalg.norm(got) * np.linalg.norm(want))),
+                    "max_abs_over_max": float(np.max(np.abs(got - want)) / np.max(np.abs(want)))}
+        res["s"] = t_run
+        res["site_updates_per_s"] = w.n_active * w.steps / t_run
+        res["norm_drift"] = obs["norm"] - n0
+        res["energy"] = obs["energy"]
+        if ref is not None:
+            ro = ref["obs"][list(ref["obs_steps"]).index(w.steps)]
+            res["oracle_norm"], res["oracle_energy"] = float(ro[0]), float(ro[1])
+            res["norm_rel_err"] = abs(obs["norm"] - ro[0]) / ro[0]
+            res["energy_rel_err"] = abs(obs["energy"] - ro[1]) / abs(ro[1])
+        out[dtype] = res
+        log(f"[bench] C5 subdomain {dtype}: {w.steps} steps in {t_run:.2f} s; "
+            f"{res['errors_vs_oracle'].get(str(w.steps), {})}")
+        del U, psi
+    g.release_work()
+    torch.cuda.empty_cache()
+    report["c5_subdomain"] = out
 
 
 def bench_c2_job(args, dev, report):
@@ -706,8 +881,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="time every launch variant and use the fastest")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-all", action="store_true",
-                    help="also time the oracle on samples of the 256^3 ramp, the batch and the 60M-site shell")
+    ap.add_argument("--no-cpu-all", action="store_true",
+                    help="skip the oracle on samples of the 256^3 ramp, the batch and the 60M-site shell")
     ap.add_argument("--no-extras", action="store_true", help="skip complex64, adjoint and batched legs")
     ap.add_argument("--adj-steps", type=int, default=2000,
                     help="steps of the 2-time-unit adjoint ramp (dt = 2/steps; RK4 needs steps >= 1100)")
@@ -722,6 +897,10 @@ def main():
                          "(default: on, off with --no-extras)")
     ap.add_argument("--job-itp", type=int, default=5000)
     ap.add_argument("--job-rt", type=int, default=10000)
+    ap.add_argument("--legs", default="all",
+                    help="comma list of legs to run (for profiling one workload): c2, c64, adjoint, batched, "
+                         "integrators, itp_real, restage, hoc, c1, c5, c5_subdomain, job; 'all' runs every leg. "
+                         "Without c2 no headline line is printed, only the legs' report")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -750,50 +929,63 @@ def main():
         torch.cuda.synchronize()
         del x, y
         torch.cuda.empty_cache()
-    bench_c2(args, dev, "c128", report)
-    log(f"[bench] c128 done: {report['c128']['site_updates_per_s']:.4g} site-updates/s")
-    copy_gbps = achievable_copy_gbps(dev)
-    log(f"[bench] streaming copy: {copy_gbps:.0f} GB/s")
+    legs = None if args.legs == "all" else set(args.legs.split(","))
+
+    def leg(name: str) -> bool:
+        return legs is None or name in legs
+
+    copy_gbps = None
+    if leg("c2"):
+        bench_c2(args, dev, "c128", report)
+        log(f"[bench] c128 done: {report['c128']['site_updates_per_s']:.4g} site-updates/s")
+        copy_gbps = achievable_copy_gbps(dev)
+        log(f"[bench] streaming copy: {copy_gbps:.0f} GB/s")
     if not args.no_extras:
-        bench_c2(args, dev, "c64", report)
-        log(f"[bench] c64 done: {report['c64']['site_updates_per_s']:.4g} site-updates/s")
-        bench_adjoint(args, dev, report)
-        log(f"[bench] adjoint done: {report['adjoint_c3']['grads_per_s']:.3g} grads/s")
-        bench_batched(args, dev, report)
-        log("[bench] batched done")
-        bench_integrators(args, dev, report)
-        log("[bench] integrators done")
-        bench_itp_real(args, dev, report)
-        log("[bench] real imaginary time done")
-        bench_restage(args, dev, report)
-        log("[bench] restage done")
-        bench_hoc(args, dev, report)
-        log("[bench] 19-point stencil done")
-        bench_c1(args, dev, report)
-    if args.c5 > 0:
+        if leg("c64"):
+            bench_c2(args, dev, "c64", report)
+            log(f"[bench] c64 done: {report['c64']['site_updates_per_s']:.4g} site-updates/s")
+        if leg("adjoint"):
+            bench_adjoint(args, dev, report)
+            log(f"[bench] adjoint done: {report['adjoint_c3']['grads_per_s']:.3g} grads/s")
+        if leg("batched"):
+            bench_batched(args, dev, report)
+            log("[bench] batched done")
+        if leg("integrators"):
+            bench_integrators(args, dev, report)
+            log("[bench] integrators done")
+        if leg("itp_real"):
+            bench_itp_real(args, dev, report)
+            log("[bench] real imaginary time done")
+        if leg("restage"):
+            bench_restage(args, dev, report)
+            log("[bench] restage done")
+        if leg("hoc"):
+            bench_hoc(args, dev, report)
+            log("[bench] 19-point stencil done")
+        if leg("c1"):
+            bench_c1(args, dev, report)
+    if args.c5 > 0 and leg("c5"):
         bench_c5(args, dev, report)
         log("[bench] C5 precision study done")
-    if args.job:
+    if args.c5 > 0 and leg("c5_subdomain"):
+        bench_c5_subdomain(args, dev, report)
+    if args.job and leg("job"):
         bench_c2_job(args, dev, report)
         log("[bench] headline job done")
+    if not leg("c2"):
+        print(json.dumps({"legs": sorted(legs), "report": report}, default=float), flush=True)
+        return
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args)
         log(f"[bench] cpu baseline: {cpu['value']:.4g} site-updates/s")
-    if args.cpu_all:
+    if not args.no_cpu and not args.no_cpu_all and not args.no_extras:
         report["cpu_oracle_per_config"] = cpu_per_config(report)
         log("[bench] oracle on the other workloads done")
 
     main_res = report["c128"]
     kern = main_res["kernels"]
-    dom = max((f for f in kern if kern[f]["GBps"] is not None), key=lambda f: kern[f]["total_ms"])
-    k = kern[dom]
-    traffic, tsrc = profiled_traffic(dom) if main_res["config"] == 0 else (None, None)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": traffic, "traffic_unit": "bytes/launch",
-                "achievable_copy_GBps": copy_gbps, "frac_of_copy": k["GBps"] / copy_gbps,
-                "traffic_source": tsrc, "algo_bytes_per_launch": k["algo_bytes_per_launch"],
-                "avg_launch_us": k["avg_us"], "launches": k["launches"]}
+    roofline = dominant_roofline(kern, "c2_c128", copy_gbps, use_profile=main_res["config"] == 0)
     line = {
         "metric": METRIC,
         "value": main_res["site_updates_per_s"],
@@ -812,6 +1004,8 @@ def main():
                                "one step = 1 imaginary-time step + 2 RK4 steps",
                    "n_active": main_res["n_active"], "launch_config": main_res["config"]},
         "roofline": roofline,
+        "roofline_steps": {f"{ph}_{dt}": report[dt]["step_roofline"][ph]
+                           for dt in ("c128", "c64") if dt in report for ph in ("itp", "rk4")},
         "cpu_baseline": cpu,
         "phases": {"c128": {k2: v for k2, v in main_res.items() if k2 != "kernels"}},
         "kernels_c128": kern,
@@ -820,8 +1014,12 @@ def main():
     if "c64" in report:
         line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
         line["kernels_c64"] = report["c64"]["kernels"]
+    if "precision_c5" in report:
+        c5 = report["precision_c5"]
+        line["roofline_c5"] = {dt: {"kernel": c5[dt]["roofline"], "rk4_step": c5[dt]["step_roofline"]}
+                               for dt in ("c128", "c64") if dt in c5}
     for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "restage_c2", "hoc19_c2", "c1",
-                "precision_c5", "job_c2", "cpu_oracle_per_config"):
+                "precision_c5", "c5_subdomain", "job_c2", "cpu_oracle_per_config"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)

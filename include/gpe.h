@@ -25,7 +25,13 @@
  *     library never frees them;
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls
  *     are stream-ordered and asynchronous, except that a call writing to a
- *     *_host output synchronises `stream` before returning.
+ *     *_host output synchronises `stream` before returning.  A grid or batch
+ *     keeps per-handle device state (instance table, reduction partials,
+ *     results, step counter), so the work of a call on a handle starts after
+ *     the work of the previous call on the same handle, whichever stream that
+ *     one used (the library makes the new stream wait for the old one's last
+ *     event; not applied while `stream` is being captured into a graph).
+ *     Caller-owned buffers (psi, fields, work) are the caller's to order.
  *
  * Errors: every call returns a gpe_status.  Arguments are validated before
  * anything is launched, so a call that fails validation has no effect.  A
@@ -43,7 +49,7 @@
 extern "C" {
 #endif
 
-#define GPE_ABI_VERSION 3
+#define GPE_ABI_VERSION 4
 #define GPE_MAX_KNOTS 32
 
 typedef enum {
@@ -52,7 +58,7 @@ typedef enum {
   GPE_ERR_ALLOC = 2,      /* host or device allocation failed */
   GPE_ERR_DEVICE = 3,     /* a HIP call failed (including a device fault surfacing at a sync) */
   GPE_ERR_STATE = 4,      /* handle not usable for this call (e.g. a host-only grid) */
-  GPE_ERR_UNSTABLE = 5,   /* dt above the explicit-scheme stability bound (when checking is on) */
+  GPE_ERR_UNSTABLE = 5,   /* dt above the explicit-scheme stability bound (checked unless skipped) */
   GPE_ERR_NONFINITE = 6   /* a norm observed during the run was NaN/Inf */
 } gpe_status;
 
@@ -114,7 +120,8 @@ typedef struct {
   double dt;              /* time step, > 0 */
   double norm_target;     /* N of eq. (3) for imaginary time; <= 0 means 1 */
   int64_t obs_every;      /* > 0: record an observation every obs_every steps */
-  int32_t check_stability;/* nonzero: fail with GPE_ERR_UNSTABLE above the bound */
+  int32_t skip_stability_check; /* 0 (default): check dt before any step is launched and fail
+                                   with GPE_ERR_UNSTABLE above the bound; nonzero: skip the check */
   int32_t integrator;     /* gpe_integrator for real time (0 = GPE_RK4); other calls need 0 */
 } gpe_params;
 
@@ -244,7 +251,12 @@ gpe_status gpe_pack_real(gpe_grid grid, gpe_dtype dtype, const void* box_dev, vo
  *   final_host: optional (may be NULL) observation of the returned psi.
  *   history_dev: optional device array of ceil(nsteps/obs_every) gpe_obs,
  *               observation before steps 0, obs_every, ...
- * check_stability: dt/2 * lambda_max(T) <= 2 for the Euler substeps. */
+ * Stability (unless params->skip_stability_check): dt/2 * lambda_max(T) <= 2
+ * for the Euler substeps (lambda_max(T) the Gershgorin bound of the grid's
+ * stencil), and g max|psi|^2 dt/2 < 1 at the start state so that the
+ * linearised interaction factor stays positive; a violation returns
+ * GPE_ERR_UNSTABLE before any step runs.  The check reads psi and the field
+ * once on the device and synchronises `stream`. */
 gpe_status gpe_imag_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
                          const gpe_params* params, int64_t nsteps, void* work, size_t work_bytes,
                          void* stream, gpe_obs* final_host, gpe_obs* history_dev);
@@ -271,9 +283,14 @@ gpe_status gpe_imag_time_real(gpe_grid grid, gpe_dtype dtype, void* psi, const g
  *   GPE_RKHE3: stored y2, y3; stage times t + (0, 1/3, 2/3) dt.
  *   GPE_RKCK : stored y2..y6; stage times t + (0, 1/5, 3/10, 3/5, 1, 7/8) dt.
  * Step n starts at t0 + n dt.  work: gpe_work_bytes of the matching mode.
- * check_stability: dt * (lambda_max(T) + max V) <= 2 sqrt(2) (RK4), sqrt(3)
- * (RKHE3) or 1 (RKCK, whose stability function exceeds 1 in modulus on the
- * whole imaginary axis; at 1 the growth per step is below 2.3e-4). */
+ * Stability (unless params->skip_stability_check; Gershgorin bound of the
+ * frozen-coefficient operator of eq. (8)): dt * lambda <= 2 sqrt(2) (RK4),
+ * sqrt(3) (RKHE3) or 1 (RKCK, whose stability function exceeds 1 in modulus
+ * on the whole imaginary axis; at 1 the growth per step is below 2.3e-4), with
+ * lambda = lambda_max(T) + max|V| + |g| max|psi|^2 (max|V| over the ramp's
+ * knots, max|psi|^2 of the start state); a violation returns
+ * GPE_ERR_UNSTABLE before any step runs.  The check reads psi and the field
+ * once on the device and synchronises `stream`. */
 gpe_status gpe_real_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
                          const gpe_params* params, double t0, int64_t nsteps, void* work, size_t work_bytes,
                          void* stream, gpe_obs* final_host, gpe_obs* history_dev);
@@ -296,12 +313,52 @@ gpe_status gpe_overlap(gpe_grid grid, gpe_dtype dtype, const void* a, const void
  * the reverse sweep recomputes one segment at a time from its checkpoint,
  * keeping the segment's stage states, so the work buffer holds
  * ceil(nsteps/K) + 4K + 8 state vectors (K = the checkpoint interval).
+ * Stability as gpe_real_time, with 3 |g| max|psi0|^2 in lambda (Gershgorin
+ * bound of the linearised operator the adjoint stages apply).
  *   psi_final: optional device output of psi(T) (may be NULL).
  *   grad_host: n_knots doubles. */
 gpe_status gpe_fidelity_grad(gpe_grid grid, gpe_dtype dtype, const void* psi0, const void* psi_target,
                              const gpe_potential* pot, const gpe_params* params, double t0, int64_t nsteps,
                              int64_t ckpt_every, void* work, size_t work_bytes, void* stream,
                              double* loss_host, double* grad_host, void* psi_final);
+
+/* ---- Staged ramps (Sec. V) ------------------------------------------
+ * A ramp given as stage potentials V_0 .. V_S on the whole box (device box
+ * arrays, double for GPE_C128, float for GPE_C64) and the chemical potentials
+ * mu_0 .. mu_S of their ground states.  Stage i (i = 0 .. S-1) runs on its own
+ * grid, the post-selection of Sec. II.A repeated at the stage boundary: the
+ * points where min(V_i, V_{i+1}) < cutoff_factor max(mu_i, mu_{i+1}) (the
+ * paper's factor is 5), so every potential met during the stage is covered.
+ *
+ * gpe_staged_ramp_grids builds the S grids (as gpe_grid_create_threshold;
+ * fields_box holds n_fields = S + 1 pointers, mus_host S + 1 values,
+ * cutoff_factor <= 0 selects 5).  grids_out receives S handles owned by the
+ * caller (gpe_grid_destroy each); cutoffs_host (optional) the S cutoffs.  On
+ * failure no grid is left allocated and every grids_out entry is NULL. */
+gpe_status gpe_staged_ramp_grids(const gpe_geometry* geom, gpe_dtype dtype, int32_t n_fields,
+                                 const void* const* fields_box, const double* mus_host, double cutoff_factor,
+                                 int device, gpe_grid* grids_out, double* cutoffs_host);
+
+/* Work buffer of gpe_staged_ramp_run: the largest stage's two compact stage
+ * potentials plus its real-time work for `integrator`. */
+gpe_status gpe_staged_ramp_work_bytes(int32_t n_stages, const gpe_grid* grids, gpe_dtype dtype, int32_t integrator,
+                                      size_t* bytes);
+
+/* Runs the S stages in order.  Stage i carries psi over from the previous
+ * grid (stage 0: `src` with psi_src) to grids[i] as gpe_remap does (a plain
+ * copy when the selection did not change; no renormalisation), packs V_i and
+ * V_{i+1} onto grids[i], observes the carried-over state, and takes
+ * steps_per_stage real-time steps (params: g, dt, integrator, stability
+ * check) from t_i = t0 + i steps_per_stage dt with the LERP potential from V_i
+ * at t_i to V_{i+1} at t_{i+1}.  psi_stage[i] (caller-owned, grids[i]'s
+ * n_active complex values) receives the state on stage i's grid; the ramp's
+ * result is psi_stage[S-1].  records_host: S x 4 doubles per stage {norm
+ * after the carry-over, norm, energy and mu at the stage end}.  Synchronises
+ * `stream` (every stage reads its observations on the host). */
+gpe_status gpe_staged_ramp_run(gpe_grid src, const void* psi_src, int32_t n_stages, const gpe_grid* grids,
+                               void* const* psi_stage, gpe_dtype dtype, const void* const* fields_box,
+                               const gpe_params* params, double t0, int64_t steps_per_stage, void* work,
+                               size_t work_bytes, void* stream, double* records_host);
 
 /* ---- Batched instances ----------------------------------------------
  * A batch concatenates the compact layouts of n grids (instance i occupies
@@ -372,6 +429,7 @@ gpe_status gpe_config_describe(int32_t config, int32_t* block, int32_t* sites_pe
 gpe_status gpe_grid_set_config(gpe_grid grid, int32_t config);
 gpe_status gpe_grid_get_config(gpe_grid grid, int32_t* config);
 gpe_status gpe_batch_set_config(gpe_batch batch, int32_t config);
+gpe_status gpe_batch_get_config(gpe_batch batch, int32_t* config);
 
 /* Time every configuration on `reps` steps of psi of one phase (contents
  * are advanced; pass a scratch copy), in three interleaved rounds keeping
@@ -392,6 +450,24 @@ gpe_status gpe_grid_autotune(gpe_grid grid, gpe_dtype dtype, int32_t mode, void*
  * empties the cache.  The cache is guarded by a lock. */
 gpe_status gpe_grid_apply_tuned(gpe_grid grid, gpe_dtype dtype, int32_t mode, int32_t* config);
 gpe_status gpe_autotune_cache_clear(void);
+
+/* Batched ramp sweeps (the Sec. V ramp-optimisation workload, many ramps per
+ * launch): time every configuration on `reps` real-time steps of the whole
+ * batch (the launches of gpe_batch_real_time with the same ramps, params and
+ * use_graph; psi is advanced, pass a scratch copy), three interleaved rounds
+ * keeping each variant's fastest, select the fastest and store it on the
+ * batch.  With use_graph each variant's step graph is captured in an untimed
+ * first step, so replays are what is timed.  The result is cached like
+ * gpe_grid_autotune's, keyed by (dtype, floor(log2 total active sites),
+ * floor(log2 mean segment length), floor(log2 instance count));
+ * gpe_batch_apply_tuned gives a batch of the same class the cached
+ * configuration (*config = -1 when none).
+ *   work: >= gpe_batch_work_bytes(.., GPE_MODE_RT (or the integrator's mode), ..).
+ *   times_ms_host: optional gpe_config_count() doubles (ms per step). */
+gpe_status gpe_batch_autotune(gpe_batch batch, gpe_dtype dtype, void* psi, const void* field, const gpe_ramp* ramps,
+                              const gpe_params* params, int32_t reps, int32_t use_graph, void* work,
+                              size_t work_bytes, void* stream, int32_t* best_config, double* times_ms_host);
+gpe_status gpe_batch_apply_tuned(gpe_batch batch, gpe_dtype dtype, int32_t* config);
 
 /* ---- Per-kernel timing -----------------------------------------------
  * When enabled, every kernel launch of the library is bracketed by HIP

@@ -28,7 +28,7 @@ class Potential(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("dt", C.c_double), ("norm_target", C.c_double), ("obs_every", C.c_int64),
-                ("check_stability", C.c_int32), ("integrator", C.c_int32)]
+                ("skip_stability_check", C.c_int32), ("integrator", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -76,6 +76,11 @@ SIGNATURES = {
     "gpe_overlap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _pd]),
     "gpe_fidelity_grad": (C.c_int, [_vp, C.c_int, _vp, _vp, C.POINTER(Potential), C.POINTER(Params), C.c_double,
                                     _i64, _i64, _vp, C.c_size_t, _vp, _pd, _pd, _vp]),
+    "gpe_staged_ramp_grids": (C.c_int, [C.POINTER(Geometry), C.c_int, _i32, C.POINTER(_vp), _pd, C.c_double,
+                                        C.c_int, C.POINTER(_vp), _pd]),
+    "gpe_staged_ramp_work_bytes": (C.c_int, [_i32, C.POINTER(_vp), C.c_int, _i32, C.POINTER(C.c_size_t)]),
+    "gpe_staged_ramp_run": (C.c_int, [_vp, _vp, _i32, C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.POINTER(_vp),
+                                      C.POINTER(Params), C.c_double, _i64, _vp, C.c_size_t, _vp, _pd]),
     "gpe_batch_create": (C.c_int, [_i32, C.POINTER(_vp), C.c_int, C.POINTER(_vp)]),
     "gpe_batch_offsets": (C.c_int, [_vp, C.POINTER(_i64)]),
     "gpe_batch_destroy": (C.c_int, [_vp]),
@@ -89,6 +94,10 @@ SIGNATURES = {
     "gpe_grid_set_config": (C.c_int, [_vp, _i32]),
     "gpe_grid_get_config": (C.c_int, [_vp, C.POINTER(_i32)]),
     "gpe_batch_set_config": (C.c_int, [_vp, _i32]),
+    "gpe_batch_get_config": (C.c_int, [_vp, C.POINTER(_i32)]),
+    "gpe_batch_autotune": (C.c_int, [_vp, C.c_int, _vp, _vp, C.POINTER(Ramp), C.POINTER(Params), _i32, _i32, _vp,
+                                     C.c_size_t, _vp, C.POINTER(_i32), _pd]),
+    "gpe_batch_apply_tuned": (C.c_int, [_vp, C.c_int, C.POINTER(_i32)]),
     "gpe_grid_autotune": (C.c_int, [_vp, C.c_int, _i32, _vp, C.POINTER(Potential), C.POINTER(Params), _i32, _vp,
                                     C.c_size_t, _vp, C.POINTER(_i32), _pd]),
     "gpe_grid_apply_tuned": (C.c_int, [_vp, C.c_int, _i32, C.POINTER(_i32)]),

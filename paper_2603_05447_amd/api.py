@@ -27,6 +27,15 @@ def _stream(stream) -> C.c_void_p:
     return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
+def _used_on(t: torch.Tensor, stream) -> torch.Tensor:
+    """Tell torch's caching allocator that `t` is used on `stream` (a torch
+    stream other than the current one), so its memory is not handed out again
+    before the work queued there has finished."""
+    if stream is not None and isinstance(stream, torch.cuda.Stream) and stream != torch.cuda.current_stream():
+        t.record_stream(stream)
+    return t
+
+
 def _dtype_of(psi: torch.Tensor) -> int:
     if psi.dtype not in _CDT:
         raise TypeError("psi must be complex128 or complex64")
@@ -113,12 +122,12 @@ def _integrator(name: str) -> int:
     return INTEGRATORS[name]
 
 
-def make_params(g: float, dt: float, norm_target: float = 1.0, obs_every: int = 0, check_stability: bool = False,
+def make_params(g: float, dt: float, norm_target: float = 1.0, obs_every: int = 0, check_stability: bool = True,
                 integrator: str = "rk4"):
     p = L.Params()
     p.g, p.dt, p.norm_target = float(g), float(dt), float(norm_target)
     p.obs_every = int(obs_every)
-    p.check_stability = 1 if check_stability else 0
+    p.skip_stability_check = 0 if check_stability else 1
     p.integrator = _integrator(integrator)
     return p
 
@@ -278,7 +287,7 @@ class Grid:
     # ---- solver calls ---------------------------------------------------
     def imag_time(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, steps: int,
                   norm_target: float = 1.0, obs_every: int = 0, history: Optional[torch.Tensor] = None,
-                  stream=None, observe: bool = True, check_stability: bool = False) -> Optional[dict]:
+                  stream=None, observe: bool = True, check_stability: bool = True) -> Optional[dict]:
         """Imaginary time in place.  A complex psi (complex128/complex64) runs
         gpe_imag_time; a real psi (float64/float32) runs gpe_imag_time_real."""
         real = psi.dtype in _RSTATE
@@ -290,7 +299,7 @@ class Grid:
             dt_ = _dtype_of(psi)
         cp, keep = pot.as_c(dt_)
         prm = make_params(g, dt, norm_target, obs_every, check_stability)
-        w = self.work(dt_, L.GPE_MODE_ITP_REAL if real else L.GPE_MODE_ITP, steps)
+        w = _used_on(self.work(dt_, L.GPE_MODE_ITP_REAL if real else L.GPE_MODE_ITP, steps), stream)
         o = L.Obs()
         fn = L.load().gpe_imag_time_real if real else L.load().gpe_imag_time
         check(fn(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), int(steps), w.data_ptr(), w.numel(),
@@ -299,11 +308,11 @@ class Grid:
 
     def real_time(self, psi: torch.Tensor, pot: Potential, g: float, dt: float, steps: int, t0: float = 0.0,
                   obs_every: int = 0, history: Optional[torch.Tensor] = None, stream=None, observe: bool = True,
-                  check_stability: bool = False, integrator: str = "rk4") -> Optional[dict]:
+                  check_stability: bool = True, integrator: str = "rk4") -> Optional[dict]:
         dt_ = _dtype_of(psi)
         cp, keep = pot.as_c(dt_)
         prm = make_params(g, dt, 1.0, obs_every, check_stability, integrator)
-        w = self.work(dt_, _RT_MODE[prm.integrator], steps)
+        w = _used_on(self.work(dt_, _RT_MODE[prm.integrator], steps), stream)
         o = L.Obs()
         check(L.load().gpe_real_time(self._h, dt_, psi.data_ptr(), C.byref(cp), C.byref(prm), float(t0),
                                      int(steps), w.data_ptr(), w.numel(), _stream(stream),
@@ -328,12 +337,12 @@ class Grid:
 
     def fidelity_grad(self, psi0: torch.Tensor, target: torch.Tensor, pot: Potential, g: float, dt: float,
                       steps: int, t0: float = 0.0, ckpt_every: int = 0, psi_final: Optional[torch.Tensor] = None,
-                      stream=None, check_stability: bool = False):
+                      stream=None, check_stability: bool = True):
         dt_ = _dtype_of(psi0)
         cp, keep = pot.as_c(dt_)
         prm = make_params(g, dt, 1.0, 0, check_stability)
         nb = self.work_bytes(dt_, L.GPE_MODE_ADJ, steps, ckpt_every)
-        w = torch.empty(max(nb, 256), dtype=torch.uint8, device=psi0.device)
+        w = _used_on(torch.empty(max(nb, 256), dtype=torch.uint8, device=psi0.device), stream)
         loss = C.c_double()
         grad = (C.c_double * L.GPE_MAX_KNOTS)()
         check(L.load().gpe_fidelity_grad(self._h, dt_, psi0.data_ptr(), target.data_ptr(), C.byref(cp),
@@ -400,11 +409,11 @@ class Grid:
         if phase == "itp":
             mode = L.GPE_MODE_ITP_REAL if real else L.GPE_MODE_ITP
             prm = make_params(g, dt)
-            w = self.work(dt_, mode, reps)
+            w = _used_on(self.work(dt_, mode, reps), stream)
         elif phase == "rt":
             prm = make_params(g, dt, integrator=integrator)
             mode = L.GPE_MODE_RT
-            w = self.work(dt_, _RT_MODE[prm.integrator], reps)
+            w = _used_on(self.work(dt_, _RT_MODE[prm.integrator], reps), stream)
         else:
             raise ValueError("phase must be 'rt' or 'itp'")
         n = config_count()
@@ -448,6 +457,35 @@ class Batch:
     def set_config(self, config: int) -> None:
         check(L.load().gpe_batch_set_config(self._h, int(config)))
 
+    def get_config(self) -> int:
+        c = C.c_int32()
+        check(L.load().gpe_batch_get_config(self._h, C.byref(c)))
+        return c.value
+
+    def autotune(self, psi: torch.Tensor, field: torch.Tensor, ramps, gs, dts, reps: int = 3,
+                 use_graph: bool = True, stream=None, integrator: str = "rk4"):
+        """Time every launch variant on `reps` real-time steps of the whole
+        batch (gpe_batch_autotune) and keep the fastest; psi is advanced.
+        Returns (best variant, ms per step of every variant)."""
+        dt_ = _dtype_of(psi)
+        ra, keep = self._ramps(ramps)
+        pa = self._params(gs, dts, integrator)
+        nb = self.work_bytes(dt_, _RT_MODE[pa[0].integrator], reps)
+        w = _used_on(torch.empty(max(nb, 256), dtype=torch.uint8, device=psi.device), stream)
+        n = config_count()
+        times = (C.c_double * n)(*([-1.0] * n))
+        best = C.c_int32()
+        check(L.load().gpe_batch_autotune(self._h, dt_, psi.data_ptr(), field.data_ptr(), ra, pa, int(reps),
+                                          1 if use_graph else 0, w.data_ptr(), w.numel(), _stream(stream),
+                                          C.byref(best), times))
+        return best.value, list(times)
+
+    def apply_tuned(self, dtype: int) -> Optional[int]:
+        """Take the launch configuration autotuned for this batch's class, if any."""
+        c = C.c_int32()
+        check(L.load().gpe_batch_apply_tuned(self._h, int(dtype), C.byref(c)))
+        return None if c.value < 0 else c.value
+
     @staticmethod
     def _ramps(ramps):
         n = len(ramps)
@@ -464,21 +502,22 @@ class Batch:
         return arr, keep
 
     @staticmethod
-    def _params(gs, dts, integrator: str = "rk4"):
+    def _params(gs, dts, integrator: str = "rk4", check_stability: bool = True):
         arr = (L.Params * len(gs))()
         for i, (g, dt) in enumerate(zip(gs, dts)):
-            arr[i] = make_params(g, dt, integrator=integrator)
+            arr[i] = make_params(g, dt, integrator=integrator, check_stability=check_stability)
         return arr
 
     def real_time(self, psi: torch.Tensor, field: torch.Tensor, ramps, gs, dts, steps: int, t0: float = 0.0,
                   use_graph: bool = True, work: Optional[torch.Tensor] = None, stream=None, observe: bool = True,
-                  integrator: str = "rk4"):
+                  integrator: str = "rk4", check_stability: bool = True):
         dt_ = _dtype_of(psi)
         ra, keep = self._ramps(ramps)
-        pa = self._params(gs, dts, integrator)
+        pa = self._params(gs, dts, integrator, check_stability)
         nb = self.work_bytes(dt_, _RT_MODE[pa[0].integrator], steps)
         if work is None or work.numel() < nb:
             work = torch.empty(max(nb, 256), dtype=torch.uint8, device=psi.device)
+        _used_on(work, stream)
         obs = (L.Obs * len(self.grids))()
         check(L.load().gpe_batch_real_time(self._h, dt_, psi.data_ptr(), field.data_ptr(), ra, pa, float(t0),
                                            int(steps), 1 if use_graph else 0, work.data_ptr(), work.numel(),
@@ -486,12 +525,13 @@ class Batch:
         return [_obs_dict(o) for o in obs] if observe else None
 
     def fidelity_grad(self, psi0: torch.Tensor, target: torch.Tensor, field: torch.Tensor, ramps, gs, dts,
-                      steps: int, t0: float = 0.0, ckpt_every: int = 0, use_graph: bool = False, stream=None):
+                      steps: int, t0: float = 0.0, ckpt_every: int = 0, use_graph: bool = False, stream=None,
+                      check_stability: bool = True):
         dt_ = _dtype_of(psi0)
         ra, keep = self._ramps(ramps)
-        pa = self._params(gs, dts)
+        pa = self._params(gs, dts, check_stability=check_stability)
         nb = self.work_bytes(dt_, L.GPE_MODE_ADJ, steps, ckpt_every)
-        w = torch.empty(max(nb, 256), dtype=torch.uint8, device=psi0.device)
+        w = _used_on(torch.empty(max(nb, 256), dtype=torch.uint8, device=psi0.device), stream)
         n = len(self.grids)
         loss = (C.c_double * n)()
         grad = (C.c_double * (n * L.GPE_MAX_KNOTS))()
@@ -592,32 +632,47 @@ class KernelTimer:
 
 
 def staged_ramp(grid: Grid, psi: torch.Tensor, stage_fields: Sequence[torch.Tensor], mus: Sequence[float], g: float,
-                dt: float, steps_per_stage: int, t0: float = 0.0, integrator: str = "rk4", stream=None):
-    """The staged ramp of Sec. V.  stage_fields[i] is the potential V_i on the
-    whole box (device, real, box order); mus[i] the chemical potential of the
-    ground state in V_i.  Stage i (i = 0 .. S-1) first re-post-selects the
-    grid, keeping min(V_i, V_{i+1}) < 5 max(mu_i, mu_{i+1}), carries psi over,
-    then runs `steps_per_stage` real-time steps with V interpolated linearly
-    from V_i to V_{i+1} over the stage.  Returns the final grid, psi on it
-    and per-stage records (active sites, norm kept by the carry-over, norm at
-    the stage end)."""
+                dt: float, steps_per_stage: int, t0: float = 0.0, integrator: str = "rk4", stream=None,
+                cutoff_factor: float = 0.0, check_stability: bool = True):
+    """The staged ramp of Sec. V (gpe_staged_ramp_grids + gpe_staged_ramp_run).
+    stage_fields[i] is the potential V_i on the whole box (device, real, box
+    order); mus[i] the chemical potential of the ground state in V_i; psi
+    lives on `grid`.  The library re-post-selects every stage's grid,
+    carries psi over, and runs `steps_per_stage` real-time steps per stage
+    with V interpolated linearly in time.  Returns the last stage's grid,
+    psi on it and per-stage records."""
+    lib = L.load()
+    dt_ = _dtype_of(psi)
     if len(mus) != len(stage_fields):
         raise ValueError("one chemical potential per stage potential")
-    records = []
-    n, h, x0 = grid.n, grid.h, grid.x0
-    for i in range(len(stage_fields) - 1):
-        cut = 5.0 * max(float(mus[i]), float(mus[i + 1]))
-        new = Grid.from_threshold(n, h, x0, stage_fields[i], stage_fields[i + 1], cut, device=grid.device)
-        if new.n_active == grid.n_active and np.array_equal(new.runs(), grid.runs()):
-            new = grid
-        else:
-            psi = new.remap_from(grid, psi, stream=stream)
-        ta = t0 + i * steps_per_stage * dt
-        tb = ta + steps_per_stage * dt
-        pot = Potential.lerp(new.pack(stage_fields[i]), new.pack(stage_fields[i + 1]), ta, tb)
-        kept = new.observe(psi, pot, ta, g, stream=stream)["norm"]
-        obs = new.real_time(psi, pot, g, dt, steps_per_stage, t0=ta, stream=stream, integrator=integrator)
-        records.append({"stage": i, "cutoff": cut, "n_active": new.n_active, "norm_after_remap": kept,
-                        "norm_end": obs["norm"], "energy_end": obs["energy"]})
-        grid = new
-    return grid, psi, records
+    if psi.numel() != grid.n_active:
+        raise ValueError("psi must hold the grid's n_active values")
+    want = _RDT[dt_]
+    for f in stage_fields:
+        if f.dtype != want or not f.is_cuda or not f.is_contiguous():
+            raise TypeError(f"stage potentials must be contiguous CUDA tensors of {want}")
+    S = len(stage_fields) - 1
+    geom = L.Geometry()
+    for d in range(3):
+        geom.n[d], geom.h[d], geom.x0[d] = grid.n[d], grid.h[d], grid.x0[d]
+    fields = (C.c_void_p * (S + 1))(*[f.data_ptr() for f in stage_fields])
+    mu = _dbl(mus)
+    handles = (C.c_void_p * S)()
+    cuts = (C.c_double * S)()
+    check(lib.gpe_staged_ramp_grids(C.byref(geom), dt_, S + 1, fields, mu, float(cutoff_factor), grid.device,
+                                    handles, cuts))
+    grids = [Grid._wrap(C.c_void_p(handles[i]), grid.n, grid.h, grid.x0, grid.device) for i in range(S)]
+    psis = [_used_on(torch.empty(gr.n_active, dtype=psi.dtype, device=psi.device), stream) for gr in grids]
+    prm = make_params(g, dt, integrator=integrator, check_stability=check_stability)
+    nb = C.c_size_t()
+    gh = (C.c_void_p * S)(*[gr.handle.value for gr in grids])
+    check(lib.gpe_staged_ramp_work_bytes(S, gh, dt_, prm.integrator, C.byref(nb)))
+    w = _used_on(torch.empty(max(nb.value, 256), dtype=torch.uint8, device=psi.device), stream)
+    ps = (C.c_void_p * S)(*[p.data_ptr() for p in psis])
+    rec = (C.c_double * (4 * S))()
+    check(lib.gpe_staged_ramp_run(grid.handle, psi.data_ptr(), S, gh, ps, dt_, fields, C.byref(prm), float(t0),
+                                  int(steps_per_stage), w.data_ptr(), w.numel(), _stream(stream), rec))
+    records = [{"stage": i, "cutoff": cuts[i], "n_active": grids[i].n_active, "norm_after_remap": rec[4 * i],
+                "norm_end": rec[4 * i + 1], "energy_end": rec[4 * i + 2], "mu_end": rec[4 * i + 3]}
+               for i in range(S)]
+    return grids[-1], psis[-1], records

@@ -184,6 +184,12 @@ struct Problem {
   int64_t max_chunks = 0;
   InstParams* h_inst = nullptr;        // pinned staging
   hipEvent_t upload_done = nullptr;
+  // End of the last call's work on the handle.  The instance table, results,
+  // partial sums and step counter are shared by every call, so a call on
+  // another stream first waits for it (calls on one stream are ordered anyway).
+  hipEvent_t last_done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool has_last = false;
   int config = 0;
   // captured forward-step graphs, keyed by buffer pointers
   struct GraphKey {
@@ -226,6 +232,9 @@ struct Problem {
     (void)hipFree(d_grads);
     if (h_inst) (void)hipHostFree(h_inst);
     if (upload_done) (void)hipEventDestroy(upload_done);
+    if (last_done) (void)hipEventDestroy(last_done);
+    last_done = nullptr;
+    has_last = false;
     d_heads = nullptr;
     d_nbs = nullptr;
     d_inst = nullptr;
@@ -290,8 +299,8 @@ struct Problem {
       release();
       return fail(GPE_ERR_ALLOC, "pinned host allocation failed");
     }
-    if (hipEventCreateWithFlags(&upload_done, hipEventDisableTiming) != hipSuccess) {
-      upload_done = nullptr;
+    if (hipEventCreateWithFlags(&upload_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&last_done, hipEventDisableTiming) != hipSuccess) {
       release();
       return fail(GPE_ERR_DEVICE, "hipEventCreate failed");
     }
@@ -371,13 +380,14 @@ struct Problem {
   }
 
   // chunk table for a chunk capacity and stencil (built on first use)
-  gpe_status chunks_for(int capacity, ChunkSet** out, int points = 7) {
+  gpe_status chunks_for(int capacity, ChunkSet** out, int points = 7, bool build = true) {
     const int key = capacity * 4 + (points == 19 ? 1 : (points == 27 ? 2 : 0));
     auto it = chunksets.find(key);
     if (it != chunksets.end()) {
       *out = &it->second;
       return GPE_OK;
     }
+    if (!build) return fail(GPE_ERR_STATE, "internal: the chunk table of the grid's launch variant is not built");
     const std::vector<SegHead>& heads = points == 19 ? hoc_heads : (points == 27 ? c27_heads : this->heads);
     ChunkSet cs;
     cs.capacity = capacity;
@@ -431,8 +441,9 @@ struct Problem {
   // before or will stream next (same L2), while all XCDs still work on the
   // same few planes at a time.  Which XCDs take the one-larger groups of a
   // plane rotates so the eight lists stay within one chunk of each other.
-  gpe_status order_for(ChunkSet& cs) {
+  gpe_status order_for(ChunkSet& cs, bool build = true) {
     if (cs.d_order) return GPE_OK;
+    if (!build) return fail(GPE_ERR_STATE, "internal: the chunk order of the grid's launch variant is not built");
     std::vector<std::vector<int32_t>> lists(8);
     size_t c = 0;
     const size_t G = (size_t)cs.n_chunks;
@@ -495,8 +506,27 @@ struct Problem {
     return p;
   }
 
+  // Stream order across calls: work on stream s starts after the previous
+  // call's work on this handle (whatever its stream) has ended.  Not applied
+  // while s is being captured into a graph (the caller orders replays).
+  gpe_status enter(hipStream_t s) {
+    if (has_last && last_stream != s && !capturing(s))
+      HIP_TRY(hipStreamWaitEvent(s, last_done, 0));
+    return GPE_OK;
+  }
+  void leave(hipStream_t s) {
+    if (capturing(s)) return;
+    if (hipEventRecord(last_done, s) == hipSuccess) {
+      last_stream = s;
+      has_last = true;
+    }
+  }
+
   // Fill and upload the per-instance parameters.
   gpe_status upload(const ChunkSet& cs, const std::vector<InstParams>& ps, hipStream_t s) {
+    return upload(cs, ps.data(), s);
+  }
+  gpe_status upload(const ChunkSet& cs, const InstParams* ps, hipStream_t s) {
     if (hipEventSynchronize(upload_done) != hipSuccess) return fail(GPE_ERR_DEVICE, "hipEventSynchronize failed");
     for (int i = 0; i < n_inst; ++i) {
       h_inst[i] = ps[i];
@@ -539,6 +569,18 @@ struct Problem {
   }
 };
 
+// Orders a call after the handle's previous call (Problem::enter) and marks
+// its end on the call's stream when it goes out of scope (Problem::leave).
+struct Ordered {
+  Problem* P;
+  hipStream_t s;
+  gpe_status st;
+  Ordered(Problem* p, hipStream_t st_) : P(p), s(st_) { st = P->enter(s); }
+  ~Ordered() { P->leave(s); }
+  Ordered(const Ordered&) = delete;
+  Ordered& operator=(const Ordered&) = delete;
+};
+
 // work buffer carving (256-byte aligned sub-buffers)
 struct Carver {
   char* base;
@@ -549,6 +591,25 @@ struct Carver {
     off += (bytes + 255) & ~size_t(255);
     return p;
   }
+};
+
+// A host array that lives on the stack for up to 8 elements (a single grid's
+// per-instance results), so the single-grid paths make no heap allocation.
+template <typename T>
+struct SmallBuf {
+  T fixed[8];
+  std::vector<T> big;
+  T* p;
+  explicit SmallBuf(size_t n) {
+    if (n <= 8) {
+      p = fixed;
+    } else {
+      big.resize(n);
+      p = big.data();
+    }
+  }
+  T& operator[](size_t i) { return p[i]; }
+  T* data() { return p; }
 };
 
 size_t csize(int dtype) { return dtype == GPE_C128 ? 16 : 8; }
@@ -777,7 +838,7 @@ struct Ctx {
   hipStream_t s;
 };
 
-gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
+gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c, bool build = true) {
   c.P = P;
   c.cfg = config_get(config);
   const bool hoc = P->stencil != 7;
@@ -795,15 +856,23 @@ gpe_status make_ctx(Problem* P, int config, hipStream_t s, Ctx& c) {
     c.cfg.spt = 1;
     c.cfg.stage = 1;
   }
-  gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs, P->stencil);
+  gpe_status st = P->chunks_for(chunk_capacity(c.cfg), &c.cs, P->stencil, build);
   if (st != GPE_OK) return st;
   if (c.cfg.xcd == 4) {
-    st = P->order_for(*c.cs);
+    st = P->order_for(*c.cs, build);
     if (st != GPE_OK) return st;
   }
   c.pl = P->plan(*c.cs, c.cfg);
   c.s = s;
   return GPE_OK;
+}
+
+// Build the chunk table (and chunk order) of the problem's current launch
+// variant and stencil now, so that calls on it allocate no device memory
+// (grid creation and every change of variant or stencil do this).
+gpe_status prepare_tables(Problem* P) {
+  Ctx c;
+  return make_ctx(P, P->config, nullptr, c, true);
 }
 
 #define LTRY(expr)                                          \
@@ -839,7 +908,7 @@ gpe_status rk_step(const Ctx& c, const void* y0, const void* field, void* b1, vo
 template <typename R>
 gpe_status rk_generic_step(const Ctx& c, const MemOptTableau& tb, void* y0, const void* field, void* const* buf,
                            int64_t step) {
-  std::vector<void*> Y(tb.s);
+  void* Y[6];
   Y[0] = y0;
   for (int i = 1; i < tb.s; ++i) Y[i] = buf[i - 1];
   for (int i = 0; i < tb.s; ++i) {
@@ -847,17 +916,18 @@ gpe_status rk_generic_step(const Ctx& c, const MemOptTableau& tb, void* y0, cons
     const double* row = final_stage ? tb.bstar : tb.astar[i];
     // coefficient of the stencil input y^(i) itself, then the earlier states
     const double ccur = row[i];
-    std::vector<const void*> hist;
-    std::vector<double> hc;
+    const void* hist[6];
+    double hc[6];
+    int nh = 0;
     for (int j = 0; j < i; ++j)
       if (row[j] != 0.0) {
-        hist.push_back(Y[j]);
-        hc.push_back(row[j]);
+        hist[nh] = Y[j];
+        hc[nh] = row[j];
+        ++nh;
       }
     const double cdt = final_stage ? tb.bs : tb.asub[i];
     void* out = final_stage ? y0 : Y[i + 1];
-    LTRY(run_rk_generic<R>(c.pl, c.cfg, Y[i], ccur, (int)hist.size(), hist.data(), hc.data(), cdt, tb.c[i], field,
-                           out, step, c.s));
+    LTRY(run_rk_generic<R>(c.pl, c.cfg, Y[i], ccur, nh, hist, hc, cdt, tb.c[i], field, out, step, c.s));
   }
   if (step < 0) LTRY(run_tick(c.pl.step, 1, c.s));
   return GPE_OK;
@@ -915,8 +985,8 @@ gpe_status drive_rt(const Ctx& c, void* psi, const void* field, int64_t nsteps, 
   const size_t st = (size_t)c.P->total * 2 * sizeof(R);
   const MemOptTableau* tb = integrator_tableau(integrator);
   if (tb) {
-    std::vector<void*> buf(tb->s - 1);
-    for (auto& b : buf) b = cv.take(st);
+    void* buf[5];
+    for (int i = 0; i < tb->s - 1; ++i) buf[i] = cv.take(st);
     int64_t k = 0;
     for (int64_t n = 0; n < nsteps; ++n) {
       if (hist && obs_every > 0 && n % obs_every == 0) {
@@ -924,7 +994,7 @@ gpe_status drive_rt(const Ctx& c, void* psi, const void* field, int64_t nsteps, 
         LTRY(run_finalize(c.pl, FIN_OBS, hist + k * c.P->n_inst, c.s));
         ++k;
       }
-      gpe_status r = rk_generic_step<R>(c, *tb, psi, field, buf.data(), n);
+      gpe_status r = rk_generic_step<R>(c, *tb, psi, field, buf, n);
       if (r != GPE_OK) return r;
     }
     return GPE_OK;
@@ -951,7 +1021,7 @@ gpe_status drive_observe(const Ctx& c, const void* psi, const void* field, bool 
 }
 
 gpe_status read_obs(Problem& P, gpe_obs* out_host, hipStream_t s) {
-  std::vector<InstOut> o(P.n_inst);
+  SmallBuf<InstOut> o(P.n_inst);
   HIP_TRY(hipMemcpyAsync(o.data(), P.d_out, sizeof(InstOut) * P.n_inst, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   bool finite = true;
@@ -1120,58 +1190,102 @@ gpe_status read_loss_grad(Problem& P, double* loss_host, double* grad_host, int 
   return GPE_OK;
 }
 
-// device range of the field -> stability bound for RK4
+// Per-instance bounds for the stability checks, from one device pass over the
+// potential field and the state: vmax[i] bounds |V| over the call's time span
+// (for an RF ramp |V| <= sqrt(max_k |U - Delta_k|^2 + omega^2) over the knots
+// Delta_k, since Delta(t) stays between knot values; for a stage
+// interpolation the larger of the two arrays' bounds), dmax[i] is the largest
+// |psi|^2 of the start state.
 template <typename R>
-gpe_status field_vmax(const Ctx& c, const void* field, const std::vector<InstParams>& ps, double* vmax) {
-  LTRY(run_field_range<R>(c.pl, c.cfg, field, c.s));
+gpe_status field_bounds(const Ctx& c, const void* field, const void* psi, bool real_psi, const InstParams* ps,
+                        double* vmax, double* dmax) {
+  const int n = c.P->n_inst;
+  LTRY(run_field_range<R>(c.pl, c.cfg, field, psi, c.s, real_psi));
   LTRY(run_finalize(c.pl, FIN_RANGE, nullptr, c.s));
-  std::vector<InstOut> o(c.P->n_inst);
-  HIP_TRY(hipMemcpyAsync(o.data(), c.P->d_out, sizeof(InstOut) * c.P->n_inst, hipMemcpyDeviceToHost, c.s));
+  SmallBuf<InstOut> o(n);
+  HIP_TRY(hipMemcpyAsync(o.data(), c.P->d_out, sizeof(InstOut) * n, hipMemcpyDeviceToHost, c.s));
   HIP_TRY(hipStreamSynchronize(c.s));
-  double m = 0.0;
-  if (c.P->n_inst == 1 && ps[0].pot_kind == GPE_POT_LERP) {
-    // V is a convex combination of the two stage arrays: |V| <= max of both ranges
-    m = std::max(std::fabs(o[0].fmin), std::fabs(o[0].fmax));
-    LTRY(run_field_range<R>(c.pl, c.cfg, ps[0].field2, c.s));
-    LTRY(run_finalize(c.pl, FIN_RANGE, nullptr, c.s));
-    HIP_TRY(hipMemcpyAsync(o.data(), c.P->d_out, sizeof(InstOut), hipMemcpyDeviceToHost, c.s));
-    HIP_TRY(hipStreamSynchronize(c.s));
-    *vmax = std::max(m, std::max(std::fabs(o[0].fmin), std::fabs(o[0].fmax)));
-    return GPE_OK;
+  for (int i = 0; i < n; ++i) {
+    vmax[i] = 0.0;
+    dmax[i] = 0.0;
   }
-  for (int i = 0; i < c.P->n_inst; ++i) {
+  for (int i = 0; i < n; ++i) {
     const InstParams& ip = ps[i];
+    dmax[i] = o[i].dmax;
     if (ip.pot_kind == GPE_POT_RF_RAMP) {
       for (int k = 0; k < ip.n_knots; ++k) {
         const double d = std::max(std::fabs(o[i].fmax - ip.knot_v[k]), std::fabs(o[i].fmin - ip.knot_v[k]));
-        m = std::max(m, std::sqrt(d * d + ip.omega * ip.omega));
+        vmax[i] = std::max(vmax[i], std::sqrt(d * d + ip.omega * ip.omega));
       }
     } else {
-      m = std::max(m, std::max(std::fabs(o[i].fmin), std::fabs(o[i].fmax)));
+      vmax[i] = std::max(std::fabs(o[i].fmin), std::fabs(o[i].fmax));
     }
   }
-  *vmax = m;
+  if (n == 1 && ps[0].pot_kind == GPE_POT_LERP) {
+    // V is a convex combination of the two stage arrays
+    LTRY(run_field_range<R>(c.pl, c.cfg, ps[0].field2, nullptr, c.s));
+    LTRY(run_finalize(c.pl, FIN_RANGE, nullptr, c.s));
+    HIP_TRY(hipMemcpyAsync(o.data(), c.P->d_out, sizeof(InstOut), hipMemcpyDeviceToHost, c.s));
+    HIP_TRY(hipStreamSynchronize(c.s));
+    vmax[0] = std::max(vmax[0], std::max(std::fabs(o[0].fmin), std::fabs(o[0].fmax)));
+  }
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(vmax[i]) || !std::isfinite(dmax[i]))
+      return fail(GPE_ERR_NONFINITE, "instance %d: the potential or the start state is not finite", i);
   return GPE_OK;
 }
 
 }  // namespace
 
+// Stability of an explicit real-time step (default on; params.skip_stability_check
+// opts out).  For every instance the spectrum of the frozen-coefficient
+// operator T~ + V + g|psi|^2 of eq. (8) is bounded by Gershgorin:
+// lambda = lambda(T~) + max|V| + gfac |g| max|psi|^2 (gfac = 1; the fidelity
+// gradient's linearised operator (T~ + V + 2g|Y|^2) u + g Y^2 conj(u) takes
+// gfac = 3), and dt lambda must stay inside the method's stability interval
+// on the imaginary axis: 2 sqrt 2 for RK4, sqrt 3 for any three-stage
+// third-order method.  The Cash-Karp fifth-order weights have |R(iy)| = 1 +
+// y^6/7200 + O(y^8) > 1 for every y, so no step is strictly stable; the check
+// then caps dt lambda at 1, where the spurious growth per step stays below
+// 2.3e-4.  max|psi|^2 is that of the start state.
 template <typename R>
-static gpe_status rt_stability(const Ctx& c, const std::vector<InstParams>& ps, const void* field, double dt_max_g,
-                               int integrator = GPE_RK4) {
-  double vmax = 0.0;
-  gpe_status st = field_vmax<R>(c, field, ps, &vmax);
+static gpe_status rt_stability(const Ctx& c, const InstParams* ps, const void* field, const void* psi,
+                               int integrator = GPE_RK4, double gfac = 1.0) {
+  SmallBuf<double> vmax(c.P->n_inst), dmax(c.P->n_inst);
+  gpe_status st = field_bounds<R>(c, field, psi, false, ps, vmax.data(), dmax.data());
   if (st != GPE_OK) return st;
-  const double lam = kinetic_bound(*c.P) + vmax;
-  // Imaginary-axis bounds of the stability functions: 2 sqrt 2 for RK4,
-  // sqrt 3 for any three-stage third-order method.  The Cash-Karp fifth-order
-  // weights have |R(iy)| = 1 + y^6/7200 + O(y^8) > 1 for every y, so no step
-  // is strictly stable; the check then caps dt lambda at 1, where the
-  // spurious growth per step stays below 2.3e-4.
+  const double kin = kinetic_bound(*c.P);
   const double bound = integrator == GPE_RKHE3 ? std::sqrt(3.0) : (integrator == GPE_RKCK ? 1.0 : 2.0 * std::sqrt(2.0));
-  if (dt_max_g * lam > bound)
-    return fail(GPE_ERR_UNSTABLE, "dt = %g exceeds the stability bound %g/lambda = %g (lambda = %g)", dt_max_g, bound,
-                bound / lam, lam);
+  for (int i = 0; i < c.P->n_inst; ++i) {
+    const double lam = kin + vmax[i] + gfac * std::fabs(ps[i].g) * dmax[i];
+    if (ps[i].dt * lam > bound)
+      return fail(GPE_ERR_UNSTABLE,
+                  "instance %d: dt = %g exceeds the stability bound %g/lambda = %g (lambda = %g: kinetic %g, max V %g, "
+                  "%g g max|psi|^2 %g)",
+                  i, ps[i].dt, bound, bound / lam, lam, kin, vmax[i], gfac, std::fabs(ps[i].g) * dmax[i]);
+  }
+  return GPE_OK;
+}
+
+// Stability of the imaginary-time step: each forward-Euler kinetic substep of
+// dt/2 needs (dt/2) lambda(T~) <= 2, and the linearised interaction factor
+// 1 - g|psi|^2 dt/2 of the diagonal half-step must stay positive at the start
+// state.
+template <typename R>
+static gpe_status itp_stability(const Ctx& c, const InstParams* ps, const void* field, const void* psi,
+                                bool real) {
+  const double lt = kinetic_bound(*c.P);
+  for (int i = 0; i < c.P->n_inst; ++i)
+    if (ps[i].dt * lt > 4.0)
+      return fail(GPE_ERR_UNSTABLE, "dt = %g exceeds the Euler-substep bound 4/lambda_T = %g", ps[i].dt, 4.0 / lt);
+  SmallBuf<double> vmax(c.P->n_inst), dmax(c.P->n_inst);
+  gpe_status st = field_bounds<R>(c, field, psi, real, ps, vmax.data(), dmax.data());
+  if (st != GPE_OK) return st;
+  for (int i = 0; i < c.P->n_inst; ++i)
+    if (ps[i].g * dmax[i] * ps[i].dt * 0.5 >= 1.0)
+      return fail(GPE_ERR_UNSTABLE,
+                  "dt = %g makes the interaction factor 1 - g|psi|^2 dt/2 non-positive (g max|psi|^2 = %g)", ps[i].dt,
+                  ps[i].g * dmax[i]);
   return GPE_OK;
 }
 
@@ -1220,6 +1334,10 @@ static gpe_status finish_grid(const gpe_geometry* geom, Layout&& lay, int device
     }
     std::vector<const Layout*> lays{&g->lay};
     gpe_status st = g->prob->build(device, lays);
+    if (st == GPE_OK) {
+      DeviceGuard dg(device);
+      st = prepare_tables(g->prob.get());
+    }
     if (st != GPE_OK) {
       g->device = -1;
       delete g;
@@ -1418,6 +1536,9 @@ gpe_status gpe_grid_set_stencil(gpe_grid g, int32_t points) {
       if (st != GPE_OK) return st;
     }
     g->prob->stencil = points;
+    DeviceGuard dg(g->device);
+    gpe_status st = prepare_tables(g->prob.get());
+    if (st != GPE_OK) return st;
   }
   g->stencil = points;
   return GPE_OK;
@@ -1581,19 +1702,21 @@ static gpe_status imag_time_impl(gpe_grid g, gpe_dtype dtype, void* psi, const g
   st = check_work(work, work_bytes,
                   work_bytes_for(g->lay.n_active, dtype, real ? GPE_MODE_ITP_REAL : GPE_MODE_ITP, nsteps, 0));
   if (st != GPE_OK) return st;
-  if (prm->check_stability) {
-    const double lt = kinetic_bound(*g->prob);
-    if (prm->dt * lt > 4.0)
-      return fail(GPE_ERR_UNSTABLE, "dt = %g exceeds the Euler-substep bound 4/lambda_T = %g", prm->dt, 4.0 / lt);
-  }
   DeviceGuard dg(g->device);
   hipStream_t s = (hipStream_t)stream;
   Ctx c;
   st = make_ctx(g->prob.get(), g->prob->config, s, c);
   if (st != GPE_OK) return st;
+  Ordered ord(g->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
   std::vector<InstParams> ps{make_params(pot, prm, 0.0)};
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
+  if (!prm->skip_stability_check) {
+    st = dtype == GPE_C128 ? itp_stability<double>(c, ps.data(), pot->field, psi, real)
+                           : itp_stability<float>(c, ps.data(), pot->field, psi, real);
+    if (st != GPE_OK) return st;
+  }
   st = dtype == GPE_C128 ? drive_itp<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, real)
                          : drive_itp<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, real);
   if (st != GPE_OK) return st;
@@ -1638,12 +1761,14 @@ gpe_status gpe_real_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_poten
   Ctx c;
   st = make_ctx(g->prob.get(), g->prob->config, s, c);
   if (st != GPE_OK) return st;
+  Ordered ord(g->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
   std::vector<InstParams> ps{make_params(pot, prm, t0)};
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
-  if (prm->check_stability) {
-    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, pot->field, prm->dt, prm->integrator)
-                           : rt_stability<float>(c, ps, pot->field, prm->dt, prm->integrator);
+  if (!prm->skip_stability_check) {
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps.data(), pot->field, psi, prm->integrator)
+                           : rt_stability<float>(c, ps.data(), pot->field, psi, prm->integrator);
     if (st != GPE_OK) return st;
   }
   st = dtype == GPE_C128
@@ -1678,6 +1803,8 @@ gpe_status gpe_observe(gpe_grid g, gpe_dtype dtype, const void* psi, const gpe_p
   std::memset(&prm, 0, sizeof prm);
   prm.g = gg;
   prm.dt = 1.0;
+  Ordered ord(g->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
   std::vector<InstParams> ps{make_params(pot, &prm, t)};
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
@@ -1699,6 +1826,8 @@ gpe_status gpe_overlap(gpe_grid g, gpe_dtype dtype, const void* a, const void* b
   Ctx c;
   st = make_ctx(g->prob.get(), g->prob->config, s, c);
   if (st != GPE_OK) return st;
+  Ordered ord(g->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
   std::vector<InstParams> ps{make_params(nullptr, nullptr, 0.0)};
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
@@ -1740,12 +1869,14 @@ gpe_status gpe_fidelity_grad(gpe_grid g, gpe_dtype dtype, const void* psi0, cons
   Ctx c;
   st = make_ctx(g->prob.get(), g->prob->config, s, c);
   if (st != GPE_OK) return st;
+  Ordered ord(g->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
   std::vector<InstParams> ps{make_params(pot, prm, t0)};
   st = g->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
-  if (prm->check_stability) {
-    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, pot->field, prm->dt)
-                           : rt_stability<float>(c, ps, pot->field, prm->dt);
+  if (!prm->skip_stability_check) {
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps.data(), pot->field, psi0, GPE_RK4, 3.0)
+                           : rt_stability<float>(c, ps.data(), pot->field, psi0, GPE_RK4, 3.0);
     if (st != GPE_OK) return st;
   }
   st = dtype == GPE_C128 ? drive_adjoint<double>(c, psi0, psi_target, pot->field, nsteps, ckpt_every, work, psi_final)
@@ -1753,6 +1884,147 @@ gpe_status gpe_fidelity_grad(gpe_grid g, gpe_dtype dtype, const void* psi0, cons
   if (st != GPE_OK) return st;
   HIP_TRY(hipStreamSynchronize(s));
   return read_loss_grad(*g->prob, loss_host, grad_host, pot->n_knots);
+}
+
+// ---- staged ramps (Sec. V) --------------------------------------------------
+
+gpe_status gpe_staged_ramp_grids(const gpe_geometry* geom, gpe_dtype dtype, int32_t n_fields,
+                                 const void* const* fields_box, const double* mus_host, double cutoff_factor,
+                                 int device, gpe_grid* grids_out, double* cutoffs_host) {
+  if (!grids_out) return fail(GPE_ERR_ARG, "grids_out is NULL");
+  if (n_fields < 2) return fail(GPE_ERR_ARG, "a staged ramp needs at least two stage potentials");
+  for (int32_t i = 0; i + 1 < n_fields; ++i) grids_out[i] = nullptr;
+  if (!fields_box || !mus_host) return fail(GPE_ERR_ARG, "fields_box and mus_host are required");
+  for (int32_t i = 0; i < n_fields; ++i)
+    if (!std::isfinite(mus_host[i])) return fail(GPE_ERR_ARG, "mu %d is not finite", i);
+  if (std::isnan(cutoff_factor)) return fail(GPE_ERR_ARG, "cutoff_factor is NaN");
+  // Sec. V: the grid of stage i keeps the points below 5 max(mu_i, mu_{i+1})
+  const double f = cutoff_factor > 0.0 ? cutoff_factor : 5.0;
+  for (int32_t i = 0; i + 1 < n_fields; ++i) {
+    const double cut = f * std::max(mus_host[i], mus_host[i + 1]);
+    if (cutoffs_host) cutoffs_host[i] = cut;
+    gpe_status st = gpe_grid_create_threshold(geom, dtype, fields_box[i], fields_box[i + 1], cut, device,
+                                              &grids_out[i]);
+    if (st != GPE_OK) {
+      const std::string msg = t_err;
+      for (int32_t j = 0; j < i; ++j) {
+        (void)gpe_grid_destroy(grids_out[j]);
+        grids_out[j] = nullptr;
+      }
+      return fail(st, "stage %d: %s", i, msg.c_str());
+    }
+  }
+  return GPE_OK;
+}
+
+static bool same_layout(const Layout& a, const Layout& b) {
+  return a.n_active == b.n_active && a.run_i == b.run_i && a.run_j == b.run_j && a.run_k0 == b.run_k0 &&
+         a.run_k1 == b.run_k1;
+}
+
+static size_t staged_stage_bytes(int64_t n, int dtype, int integrator) {
+  Carver c(nullptr);
+  c.take((size_t)n * rsize(dtype));
+  c.take((size_t)n * rsize(dtype));
+  c.take(work_bytes_for(n, dtype, rt_work_mode(integrator), 0, 0));
+  return c.off;
+}
+
+gpe_status gpe_staged_ramp_work_bytes(int32_t n_stages, const gpe_grid* grids, gpe_dtype dtype, int32_t integrator,
+                                      size_t* bytes) {
+  if (!grids || !bytes || n_stages < 1) return fail(GPE_ERR_ARG, "need n_stages >= 1 grids and bytes");
+  gpe_status st = check_dtype(dtype);
+  if (st != GPE_OK) return st;
+  if (integrator != GPE_RK4 && integrator != GPE_RKHE3 && integrator != GPE_RKCK)
+    return fail(GPE_ERR_ARG, "unknown integrator");
+  size_t m = 0;
+  for (int32_t i = 0; i < n_stages; ++i) {
+    if (!grids[i]) return fail(GPE_ERR_ARG, "grid %d is NULL", i);
+    m = std::max(m, staged_stage_bytes(grids[i]->lay.n_active, dtype, integrator));
+  }
+  *bytes = m;
+  return GPE_OK;
+}
+
+gpe_status gpe_staged_ramp_run(gpe_grid src, const void* psi_src, int32_t n_stages, const gpe_grid* grids,
+                               void* const* psi_stage, gpe_dtype dtype, const void* const* fields_box,
+                               const gpe_params* prm, double t0, int64_t steps_per_stage, void* work,
+                               size_t work_bytes, void* stream, double* records_host) {
+  gpe_status st = check_grid(src);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi_src, "psi_src");
+  if (st == GPE_OK) st = check_params(prm);
+  if (st != GPE_OK) return st;
+  if (n_stages < 1 || !grids || !psi_stage || !fields_box || !records_host)
+    return fail(GPE_ERR_ARG, "need n_stages >= 1, grids, psi_stage, fields_box and records_host");
+  if (steps_per_stage < 1 || !std::isfinite(t0)) return fail(GPE_ERR_ARG, "steps_per_stage must be >= 1, t0 finite");
+  for (int32_t i = 0; i < n_stages; ++i) {
+    st = check_grid(grids[i]);
+    if (st == GPE_OK) st = check_ptr(psi_stage[i], "psi_stage");
+    if (st == GPE_OK) st = check_ptr(fields_box[i], "fields_box");
+    if (st != GPE_OK) return st;
+    if (grids[i]->device != src->device) return fail(GPE_ERR_ARG, "stage %d: grids on different devices", i);
+    for (int d = 0; d < 3; ++d)
+      if (grids[i]->lay.n[d] != src->lay.n[d]) return fail(GPE_ERR_ARG, "stage %d: a different box", i);
+    const void* prev = i == 0 ? psi_src : psi_stage[i - 1];
+    if (psi_stage[i] == prev) return fail(GPE_ERR_ARG, "stage %d: psi buffer aliases the previous one", i);
+  }
+  st = check_ptr(fields_box[n_stages], "fields_box");
+  if (st != GPE_OK) return st;
+  size_t need = 0;
+  st = gpe_staged_ramp_work_bytes(n_stages, grids, dtype, prm->integrator, &need);
+  if (st != GPE_OK) return st;
+  st = check_work(work, work_bytes, need);
+  if (st != GPE_OK) return st;
+  const double dt = prm->dt;
+  const size_t csz = csize(dtype);
+  for (int32_t i = 0; i < n_stages; ++i) {
+    gpe_grid g = grids[i];
+    const gpe_grid prev = i == 0 ? src : grids[i - 1];
+    const void* psi_prev = i == 0 ? psi_src : psi_stage[i - 1];
+    // carry psi over to the stage's grid (an unchanged selection is a plain copy)
+    if (same_layout(prev->lay, g->lay)) {
+      DeviceGuard dg(g->device);
+      HIP_TRY(hipMemcpyAsync(psi_stage[i], psi_prev, (size_t)g->lay.n_active * csz, hipMemcpyDeviceToDevice,
+                             (hipStream_t)stream));
+    } else {
+      st = gpe_remap(prev, g, dtype, psi_prev, psi_stage[i], stream);
+      if (st != GPE_OK) return st;
+    }
+    // the two stage potentials on the stage's grid, then the stage's steps with
+    // V interpolated linearly in time from V_i at t_i to V_{i+1} at t_{i+1}
+    Carver cv(work);
+    void* va = cv.take((size_t)g->lay.n_active * rsize(dtype));
+    void* vb = cv.take((size_t)g->lay.n_active * rsize(dtype));
+    void* rt_work = cv.take(work_bytes_for(g->lay.n_active, dtype, rt_work_mode(prm->integrator), 0, 0));
+    st = gpe_pack_real(g, dtype, fields_box[i], va, stream);
+    if (st == GPE_OK) st = gpe_pack_real(g, dtype, fields_box[i + 1], vb, stream);
+    if (st != GPE_OK) return st;
+    const double ta = t0 + (double)i * (double)steps_per_stage * dt;
+    const double tb = ta + (double)steps_per_stage * dt;
+    const double kt[2] = {ta, tb};
+    gpe_potential pot;
+    std::memset(&pot, 0, sizeof pot);
+    pot.kind = GPE_POT_LERP;
+    pot.n_knots = 2;
+    pot.field = va;
+    pot.field2 = vb;
+    pot.knot_t = kt;
+    gpe_obs kept, end;
+    st = gpe_observe(g, dtype, psi_stage[i], &pot, ta, prm->g, stream, &kept);
+    if (st != GPE_OK) return st;
+    gpe_params p = *prm;
+    p.obs_every = 0;
+    st = gpe_real_time(g, dtype, psi_stage[i], &pot, &p, ta, steps_per_stage, rt_work,
+                       work_bytes - (size_t)((char*)rt_work - (char*)work), stream, &end, nullptr);
+    if (st != GPE_OK) return fail(st, "stage %d: %s", i, std::string(t_err).c_str());
+    double* r = records_host + 4 * (size_t)i;
+    r[0] = kept.norm;
+    r[1] = end.norm;
+    r[2] = end.energy;
+    r[3] = end.mu;
+  }
+  return GPE_OK;
 }
 
 // ---- batches --------------------------------------------------------------
@@ -1779,6 +2051,10 @@ gpe_status gpe_batch_create(int32_t n, const gpe_grid* grids, int device, gpe_ba
     return fail(GPE_ERR_ALLOC, "out of host memory");
   }
   gpe_status st = b->prob->build(device, lays);
+  if (st == GPE_OK) {
+    DeviceGuard dg(device);
+    st = prepare_tables(b->prob.get());
+  }
   if (st != GPE_OK) {
     delete b;
     return st;
@@ -1854,15 +2130,15 @@ gpe_status gpe_batch_real_time(gpe_batch b, gpe_dtype dtype, void* psi, const vo
   Ctx c;
   st = make_ctx(b->prob.get(), b->prob->config, s, c);
   if (st != GPE_OK) return st;
+  Ordered ord(b->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
   st = b->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
   bool check = false;
-  double dtmax = 0.0;
-  for (auto& p : ps) dtmax = std::max(dtmax, p.dt);
-  for (int i = 0; i < b->prob->n_inst; ++i) check = check || prms[i].check_stability;
+  for (int i = 0; i < b->prob->n_inst; ++i) check = check || !prms[i].skip_stability_check;
   if (check) {
-    st = dtype == GPE_C128 ? rt_stability<double>(c, ps, field, dtmax, integ)
-                           : rt_stability<float>(c, ps, field, dtmax, integ);
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps.data(), field, psi, integ)
+                           : rt_stability<float>(c, ps.data(), field, psi, integ);
     if (st != GPE_OK) return st;
   }
   if (use_graph) {
@@ -1907,8 +2183,17 @@ gpe_status gpe_batch_fidelity_grad(gpe_batch b, gpe_dtype dtype, const void* psi
   Ctx c;
   st = make_ctx(b->prob.get(), b->prob->config, s, c);
   if (st != GPE_OK) return st;
+  Ordered ord(b->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
   st = b->prob->upload(*c.cs, ps, s);
   if (st != GPE_OK) return st;
+  bool check = false;
+  for (int i = 0; i < b->prob->n_inst; ++i) check = check || !prms[i].skip_stability_check;
+  if (check) {
+    st = dtype == GPE_C128 ? rt_stability<double>(c, ps.data(), field, psi0, GPE_RK4, 3.0)
+                           : rt_stability<float>(c, ps.data(), field, psi0, GPE_RK4, 3.0);
+    if (st != GPE_OK) return st;
+  }
   st = dtype == GPE_C128
            ? drive_adjoint<double>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr, use_graph != 0)
            : drive_adjoint<float>(c, psi0, psi_target, field, nsteps, ckpt_every, work, nullptr, use_graph != 0);
@@ -1939,7 +2224,8 @@ gpe_status gpe_grid_set_config(gpe_grid g, int32_t config) {
   if (st != GPE_OK) return st;
   if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
   g->prob->config = config;
-  return GPE_OK;
+  DeviceGuard dg(g->device);
+  return prepare_tables(g->prob.get());
 }
 
 gpe_status gpe_grid_get_config(gpe_grid g, int32_t* config) {
@@ -1954,23 +2240,28 @@ gpe_status gpe_batch_set_config(gpe_batch b, int32_t config) {
   if (!b) return fail(GPE_ERR_ARG, "batch is NULL");
   if (config < 0 || config >= config_count()) return fail(GPE_ERR_ARG, "config %d out of range", config);
   b->prob->config = config;
-  return GPE_OK;
+  DeviceGuard dg(b->device);
+  return prepare_tables(b->prob.get());
 }
 
-// Autotuning results, shared by every grid of the process: keyed by the
-// element type, the size class floor(log2 n_active) and the class
-// floor(log2 mean segment length), the two properties that decide which
-// launch variant streams a layout best.
+// Autotuning results, shared by every grid and batch of the process: keyed by
+// the element type, the phase, the size class floor(log2 n_active), the class
+// floor(log2 mean segment length) (the two properties that decide which
+// launch variant streams a layout best) and, for batches, the class
+// floor(log2 instance count) (-1 for single grids).
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int>, int> g_tune_cache;
+static std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;
 
-static std::tuple<int, int, int, int> tune_key(gpe_grid g, int dtype, int mode) {
-  const int64_t n = g->lay.n_active;
-  const double mean_seg = (double)n / (double)std::max<int64_t>(1, g->lay.n_segments());
-  int nb = 0, sb = 0;
-  while ((int64_t(1) << (nb + 1)) <= n) ++nb;
-  while ((double)(int64_t(1) << (sb + 1)) <= mean_seg) ++sb;
-  return std::make_tuple(dtype, mode, nb, sb);
+static int log2_class(double v) {
+  int b = 0;
+  while ((double)(int64_t(1) << (b + 1)) <= v) ++b;
+  return b;
+}
+
+static std::tuple<int, int, int, int, int> tune_key(const Problem& P, int dtype, int mode, int batch) {
+  const double mean_seg = (double)P.total / (double)std::max<int64_t>(1, P.n_segs);
+  return std::make_tuple(dtype, mode, log2_class((double)P.total), log2_class(mean_seg),
+                         batch ? log2_class((double)P.n_inst) : -1);
 }
 
 static gpe_status check_tune_mode(int mode) {
@@ -1978,6 +2269,75 @@ static gpe_status check_tune_mode(int mode) {
     return fail(GPE_ERR_ARG, "mode must be GPE_MODE_RT, GPE_MODE_ITP or GPE_MODE_ITP_REAL");
   return GPE_OK;
 }
+
+// Time every launch variant on `reps` steps: three interleaved rounds over all
+// variants, each variant keeping its fastest round (robust to clock and
+// neighbour noise); one untimed step per variant first builds its tables (and
+// captures its graph).  `run(ctx, steps)` advances the caller's state.  The
+// problem's configuration is set to each variant while it runs (captured
+// graphs are keyed by it) and finally to the fastest one.
+}  // extern "C"
+
+template <typename Params, typename Run>
+static gpe_status tune_variants(Problem* P, hipStream_t s, int reps, Params params, Run run, int* best_out,
+                                double* times_ms) {
+  const int prev = P->config;
+  const int nc = config_count();
+  std::vector<double> tmin(nc, 1e300);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(GPE_ERR_DEVICE, "hipEventCreate failed");
+  }
+  gpe_status st = GPE_OK;
+  for (int round = 0; round < 3 && st == GPE_OK; ++round) {
+    for (int k = 0; k < nc; ++k) {
+      Ctx c;
+      P->config = k;
+      st = make_ctx(P, k, s, c);
+      if (st != GPE_OK) break;
+      std::vector<InstParams> ps = params();
+      st = P->upload(*c.cs, ps, s);
+      if (st != GPE_OK) break;
+      st = run(c, 1);
+      if (st != GPE_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) {
+        st = fail(GPE_ERR_DEVICE, "hipEventRecord");
+        break;
+      }
+      st = run(c, reps);
+      if (st != GPE_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(GPE_ERR_DEVICE, "event timing failed");
+        break;
+      }
+      tmin[k] = std::min(tmin[k], (double)ms / reps);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GPE_OK) {
+    P->config = prev;
+    return st;
+  }
+  double best = 1e300;
+  int bi = prev;
+  for (int k = 0; k < nc; ++k) {
+    if (times_ms) times_ms[k] = tmin[k];
+    if (tmin[k] < best) {
+      best = tmin[k];
+      bi = k;
+    }
+  }
+  P->config = bi;
+  *best_out = bi;
+  return GPE_OK;
+}
+
+extern "C" {
 
 gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, int32_t mode, void* psi, const gpe_potential* pot,
                              const gpe_params* prm, int32_t reps, void* work, size_t work_bytes, void* stream,
@@ -2003,63 +2363,17 @@ gpe_status gpe_grid_autotune(gpe_grid g, gpe_dtype dtype, int32_t mode, void* ps
     return dtype == GPE_C128 ? drive_rt<double>(c, psi, pot->field, steps, work, 0, nullptr, prm->integrator)
                              : drive_rt<float>(c, psi, pot->field, steps, work, 0, nullptr, prm->integrator);
   };
+  auto params = [&]() { return std::vector<InstParams>{make_params(pot, prm, 0.0)}; };
   DeviceGuard dg(g->device);
   hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  const int prev = g->prob->config;
-  const int nc = config_count();
-  std::vector<double> tmin(nc, 1e300);
-  // three interleaved rounds over all variants; each variant keeps its
-  // fastest round (robust to clock and neighbour noise)
-  for (int round = 0; round < 3 && st == GPE_OK; ++round) {
-    for (int k = 0; k < nc; ++k) {
-      Ctx c;
-      st = make_ctx(g->prob.get(), k, s, c);
-      if (st != GPE_OK) break;
-      std::vector<InstParams> ps{make_params(pot, prm, 0.0)};
-      st = g->prob->upload(*c.cs, ps, s);
-      if (st != GPE_OK) break;
-      // one untimed step, then `reps` timed steps
-      st = run(c, 1);
-      if (st != GPE_OK) break;
-      if (hipEventRecord(e0, s) != hipSuccess) {
-        st = fail(GPE_ERR_DEVICE, "hipEventRecord");
-        break;
-      }
-      st = run(c, reps);
-      if (st != GPE_OK) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = fail(GPE_ERR_DEVICE, "event timing failed");
-        break;
-      }
-      tmin[k] = std::min(tmin[k], (double)ms / reps);
-    }
-  }
-  double best = 1e300;
-  int bi = prev;
-  for (int k = 0; k < nc && st == GPE_OK; ++k) {
-    if (times_ms) times_ms[k] = tmin[k];
-    if (tmin[k] < best) {
-      best = tmin[k];
-      bi = k;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st != GPE_OK) {
-    g->prob->config = prev;
-    return st;
-  }
-  g->prob->config = bi;
+  Ordered ord(g->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
+  int bi = 0;
+  st = tune_variants(g->prob.get(), s, reps, params, run, &bi, times_ms);
+  if (st != GPE_OK) return st;
   if (best_config) *best_config = bi;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[tune_key(g, dtype, mode)] = bi;
-  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[tune_key(*g->prob, dtype, mode, 0)] = bi;
   return GPE_OK;
 }
 
@@ -2070,14 +2384,75 @@ gpe_status gpe_grid_apply_tuned(gpe_grid g, gpe_dtype dtype, int32_t mode, int32
   if (st != GPE_OK) return st;
   if (!config) return fail(GPE_ERR_ARG, "config is NULL");
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune_cache.find(tune_key(g, dtype, mode));
+  auto it = g_tune_cache.find(tune_key(*g->prob, dtype, mode, 0));
   if (it == g_tune_cache.end()) {
     *config = -1;
     return GPE_OK;
   }
   g->prob->config = it->second;
   *config = it->second;
+  DeviceGuard dg(g->device);
+  return prepare_tables(g->prob.get());
+}
+
+gpe_status gpe_batch_get_config(gpe_batch b, int32_t* config) {
+  if (!b || !config) return fail(GPE_ERR_ARG, "batch or config is NULL");
+  *config = b->prob->config;
   return GPE_OK;
+}
+
+gpe_status gpe_batch_autotune(gpe_batch b, gpe_dtype dtype, void* psi, const void* field, const gpe_ramp* ramps,
+                              const gpe_params* prms, int32_t reps, int32_t use_graph, void* work, size_t work_bytes,
+                              void* stream, int32_t* best_config, double* times_ms) {
+  if (!b) return fail(GPE_ERR_ARG, "batch is NULL");
+  gpe_status st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi, "psi");
+  if (st == GPE_OK) st = check_ptr(field, "field");
+  if (st != GPE_OK) return st;
+  if (reps < 1) return fail(GPE_ERR_ARG, "reps must be >= 1");
+  std::vector<InstParams> ps;
+  st = batch_params(b, ramps, prms, 0.0, ps);
+  if (st != GPE_OK) return st;
+  const int integ = prms[0].integrator;
+  for (int i = 1; i < b->prob->n_inst; ++i)
+    if (prms[i].integrator != integ) return fail(GPE_ERR_ARG, "every instance must use the same integrator");
+  st = check_work(work, work_bytes, work_bytes_for(b->prob->total, dtype, rt_work_mode(integ), reps, 0));
+  if (st != GPE_OK) return st;
+  auto run = [&](const Ctx& c, int64_t steps) {
+    if (use_graph)
+      return dtype == GPE_C128 ? batch_rt_graph<double>(c, dtype, psi, field, steps, work, integ)
+                               : batch_rt_graph<float>(c, dtype, psi, field, steps, work, integ);
+    return dtype == GPE_C128 ? drive_rt<double>(c, psi, field, steps, work, 0, nullptr, integ)
+                             : drive_rt<float>(c, psi, field, steps, work, 0, nullptr, integ);
+  };
+  auto params = [&]() { return ps; };
+  DeviceGuard dg(b->device);
+  hipStream_t s = (hipStream_t)stream;
+  Ordered ord(b->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
+  int bi = 0;
+  st = tune_variants(b->prob.get(), s, reps, params, run, &bi, times_ms);
+  if (st != GPE_OK) return st;
+  if (best_config) *best_config = bi;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[tune_key(*b->prob, dtype, GPE_MODE_RT, 1)] = bi;
+  return GPE_OK;
+}
+
+gpe_status gpe_batch_apply_tuned(gpe_batch b, gpe_dtype dtype, int32_t* config) {
+  if (!b || !config) return fail(GPE_ERR_ARG, "batch or config is NULL");
+  gpe_status st = check_dtype(dtype);
+  if (st != GPE_OK) return st;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_cache.find(tune_key(*b->prob, dtype, GPE_MODE_RT, 1));
+  if (it == g_tune_cache.end()) {
+    *config = -1;
+    return GPE_OK;
+  }
+  b->prob->config = it->second;
+  *config = it->second;
+  DeviceGuard dg(b->device);
+  return prepare_tables(b->prob.get());
 }
 
 gpe_status gpe_autotune_cache_clear(void) {

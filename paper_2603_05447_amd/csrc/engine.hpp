@@ -51,7 +51,8 @@ struct InstOut {
   double ov_re, ov_im;   // overlap <a|b>
   double loss;
   double fmin, fmax;     // range of the potential field
-  double pad[7];
+  double dmax;           // largest |psi|^2 (stability bound of the nonlinear term)
+  double pad[6];
 };
 
 enum { NPART = 4 };       // partial sums per chunk
@@ -163,8 +164,9 @@ template <typename R> hipError_t run_overlap(const Plan& p, const LaunchConfig& 
                                              const void* b, hipStream_t s);
 template <typename R> hipError_t run_seed_lambda(const Plan& p, const LaunchConfig& cfg, const void* target,
                                                  void* lam, hipStream_t s);
+// range of a real field and (psi != nullptr) the largest |psi|^2, per instance
 template <typename R> hipError_t run_field_range(const Plan& p, const LaunchConfig& cfg, const void* field,
-                                                 hipStream_t s);
+                                                 const void* psi, hipStream_t s, bool real_psi = false);
 // real = true: one R per element (potential fields) instead of a complex pair
 template <typename R> hipError_t run_pack(const int64_t* run_base, const int32_t* run_start, int64_t nruns,
                                           int64_t n_active, const void* src, void* dst, bool to_box,

@@ -986,7 +986,7 @@ template <typename R> struct PointArgs {
 template <typename R, int OP>
 __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R> a) {
   using C = typename CT<R>::T;
-  constexpr int NR = (OP == PT_OVERLAP || OP == PT_RANGE) ? 2 : 1;
+  constexpr int NR = OP == PT_RANGE ? 3 : (OP == PT_OVERLAP ? 2 : 1);
   __shared__ double red[4][NR];
   const int cidx = (int)blockIdx.x;
   const Chunk ch = pl.chunks[cidx];
@@ -1000,6 +1000,7 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   if (OP == PT_RANGE) {
     acc[0] = 1e300;
     acc[1] = -1e300;
+    acc[2] = 0.0;
   } else {
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r] = 0.0;
@@ -1043,6 +1044,15 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
       const double u = (double)a.field[s];
       acc[0] = u < acc[0] ? u : acc[0];
       acc[1] = u > acc[1] ? u : acc[1];
+      // largest density of the state (a: complex, rin: real); NaN propagates
+      double d = 0.0;
+      if (a.a) {
+        const C v = a.a[s];
+        d = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+      } else if (a.rin) {
+        d = (double)a.rin[s] * (double)a.rin[s];
+      }
+      acc[2] = (d > acc[2] || d != d) ? d : acc[2];
     }
   }
   if constexpr (OP == PT_OVERLAP) {
@@ -1052,22 +1062,27 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   } else if constexpr (OP == PT_RANGE) {
     for (int off = 32; off > 0; off >>= 1) {
       const double lo = __shfl_xor(acc[0], off, 64), hi = __shfl_xor(acc[1], off, 64);
+      const double dm = __shfl_xor(acc[2], off, 64);
       acc[0] = lo < acc[0] ? lo : acc[0];
       acc[1] = hi > acc[1] ? hi : acc[1];
+      acc[2] = (dm > acc[2] || dm != dm) ? dm : acc[2];
     }
     if ((threadIdx.x & 63) == 0) {
       red[threadIdx.x >> 6][0] = acc[0];
       red[threadIdx.x >> 6][1] = acc[1];
+      red[threadIdx.x >> 6][2] = acc[2];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double lo = red[0][0], hi = red[0][1];
+      double lo = red[0][0], hi = red[0][1], dm = red[0][2];
       for (int w = 1; w < 4; ++w) {
         lo = red[w][0] < lo ? red[w][0] : lo;
         hi = red[w][1] > hi ? red[w][1] : hi;
+        dm = (red[w][2] > dm || red[w][2] != red[w][2]) ? red[w][2] : dm;
       }
       pl.partials[cidx] = lo;
       pl.partials[(size_t)pl.pstride + cidx] = hi;
+      pl.partials[(size_t)2 * pl.pstride + cidx] = dm;
     }
   }
 }
@@ -1143,9 +1158,12 @@ hipError_t run_seed_lambda(const Plan& p, const LaunchConfig&, const void* targe
 }
 
 template <typename R>
-hipError_t run_field_range(const Plan& p, const LaunchConfig&, const void* field, hipStream_t s) {
+hipError_t run_field_range(const Plan& p, const LaunchConfig&, const void* field, const void* psi, hipStream_t s,
+                           bool real_psi) {
   PointArgs<R> a = point_args<R>();
   a.field = (const R*)field;
+  if (real_psi) a.rin = (const R*)psi;
+  else a.a = (const typename CT<R>::T*)psi;
   return launch_point<R, PT_RANGE>(p, a, s);
 }
 
@@ -1168,7 +1186,7 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const Plan pl, int kind,
   const int c0 = ip.chunk_begin, c1 = ip.chunk_begin + ip.chunk_count;
   const size_t ps = (size_t)pl.pstride;
   const bool range = (kind == FIN_RANGE);
-  const int nr = (kind == FIN_OBS) ? 4 : ((kind == FIN_NORM_SCALE) ? 1 : 2);
+  const int nr = (kind == FIN_OBS) ? 4 : ((kind == FIN_NORM_SCALE) ? 1 : (range ? 3 : 2));
   double acc[NPART];
   acc[0] = range ? 1e300 : 0.0;
   acc[1] = range ? -1e300 : 0.0;
@@ -1182,34 +1200,42 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const Plan pl, int kind,
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int c = base + (int)threadIdx.x + u * FIN_BLOCK;
-        v[u] = (c < c1) ? pl.partials[r * ps + c] : (range ? (r == 0 ? 1e300 : -1e300) : 0.0);
+        v[u] = (c < c1) ? pl.partials[r * ps + c] : (range ? (r == 0 ? 1e300 : (r == 1 ? -1e300 : 0.0)) : 0.0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (range) acc[r] = (r == 0) ? (v[u] < acc[r] ? v[u] : acc[r]) : (v[u] > acc[r] ? v[u] : acc[r]);
-        else acc[r] += v[u];
+        if (range)
+          acc[r] = (r == 0) ? (v[u] < acc[r] ? v[u] : acc[r])
+                            : ((v[u] > acc[r] || (r == 2 && v[u] != v[u])) ? v[u] : acc[r]);
+        else
+          acc[r] += v[u];
       }
     }
   }
   if (range) {
     for (int off = 32; off > 0; off >>= 1) {
       const double lo = __shfl_xor(acc[0], off, 64), hi = __shfl_xor(acc[1], off, 64);
+      const double dm = __shfl_xor(acc[2], off, 64);
       acc[0] = lo < acc[0] ? lo : acc[0];
       acc[1] = hi > acc[1] ? hi : acc[1];
+      acc[2] = (dm > acc[2] || dm != dm) ? dm : acc[2];
     }
     if ((threadIdx.x & 63) == 0) {
       red[threadIdx.x >> 6][0] = acc[0];
       red[threadIdx.x >> 6][1] = acc[1];
+      red[threadIdx.x >> 6][2] = acc[2];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double lo = red[0][0], hi = red[0][1];
+      double lo = red[0][0], hi = red[0][1], dm = red[0][2];
       for (int w = 1; w < FIN_BLOCK / 64; ++w) {
         lo = red[w][0] < lo ? red[w][0] : lo;
         hi = red[w][1] > hi ? red[w][1] : hi;
+        dm = (red[w][2] > dm || red[w][2] != red[w][2]) ? red[w][2] : dm;
       }
       pl.out[inst].fmin = lo;
       pl.out[inst].fmax = hi;
+      pl.out[inst].dmax = dm;
     }
     return;
   }
@@ -1504,7 +1530,8 @@ hipError_t run_fill_zero(void* dst, int64_t n, hipStream_t s) {
   template hipError_t run_apply_scale<R>(const Plan&, const LaunchConfig&, void*, bool, hipStream_t);        \
   template hipError_t run_overlap<R>(const Plan&, const LaunchConfig&, const void*, const void*, hipStream_t); \
   template hipError_t run_seed_lambda<R>(const Plan&, const LaunchConfig&, const void*, void*, hipStream_t); \
-  template hipError_t run_field_range<R>(const Plan&, const LaunchConfig&, const void*, hipStream_t);        \
+  template hipError_t run_field_range<R>(const Plan&, const LaunchConfig&, const void*, const void*,          \
+                                         hipStream_t, bool);                                                 \
   template hipError_t run_pack<R>(const int64_t*, const int32_t*, int64_t, int64_t, const void*, void*, bool, \
                                   hipStream_t, bool);                                                        \
   template hipError_t run_fill_zero<R>(void*, int64_t, hipStream_t);                                         \

@@ -15,6 +15,24 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+# An aggregate relative L2 over many sites can hide a single bad site, so the
+# parity measure also bounds every element: max|a - b| <= ELEMENT_FACTOR *
+# tol * max|b| whenever parity_err(a, b) <= tol.
+ELEMENT_FACTOR = 10.0
+
+
+def max_rel(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def parity_err(a, b) -> float:
+    """The larger of the relative L2 error and the element-wise error
+    max|a - b| / max|b| scaled down by ELEMENT_FACTOR."""
+    return max(rel_l2(a, b), max_rel(a, b) / ELEMENT_FACTOR)
+
+
 class Case:
     """A workload on the GPU (binding objects) and on the CPU (oracle objects)."""
 

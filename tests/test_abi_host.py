@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
         assert n in _lib.SIGNATURES, f"{n} has no ctypes signature"
-    assert lib.gpe_abi_version() == 3
+    assert lib.gpe_abi_version() == 4
     assert lib.gpe_config_count() >= 6
 
 

@@ -7,7 +7,7 @@ import pytest
 from oracle import adjoint as adj, itp, realtime as rt
 from workloads import configs
 
-from gpu_cases import Case, rel_l2
+from gpu_cases import Case, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def test_fidelity_gradient_matches_oracle_adjoint(ckpt):
     oloss, ograd, oy = adj.fidelity_grad(c.T, c.opot, w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV, ckpt)
     _print(f"adjoint ckpt={ckpt}: loss {loss:.15f} vs {oloss:.15f}; grad rel err "
            f"{np.max(np.abs(grad - ograd)) / np.max(np.abs(ograd)):.3e}")
-    assert rel_l2(fin.cpu().numpy(), oy) <= 1e-10
+    assert parity_err(fin.cpu().numpy(), oy) <= 1e-10
     assert abs(loss - oloss) <= 1e-10 * max(abs(oloss), 1e-3)
     assert np.max(np.abs(grad - ograd)) <= 1e-9 * np.max(np.abs(ograd))
 
@@ -127,11 +127,11 @@ def test_batch_matches_single_instances(use_graph, dtype):
         p = c.psi()
         o1 = c.grid.real_time(p, c.pot, w.g, w.dt, steps)
         mine = out[b.offsets[i]:b.offsets[i + 1]]
-        assert rel_l2(mine, p.cpu().numpy()) <= tol, i
+        assert parity_err(mine, p.cpu().numpy()) <= tol, i
         assert abs(obs[i]["norm"] - o1["norm"]) <= tol * 10
         if dtype == "c128":
             ref = rt.real_time(c.T, w.psi0, c.opot, w.g, w.dt, 0.0, steps)
-            assert rel_l2(mine, ref) <= 1e-10
+            assert parity_err(mine, ref) <= 1e-10
 
 
 def test_graph_replay_equals_eager_repeatedly():
@@ -237,7 +237,7 @@ def test_autotune_on_imaginary_time(real):
     psi = c2.psi()
     c2.grid.imag_time(psi, c2.pot, w.g, 2e-3, 10, observe=False)
     ref, _ = itp.imaginary_time(c2.T, w.psi0, w.field, w.g, 2e-3, w.box.dV, 10)
-    assert rel_l2(psi.cpu().numpy(), ref) <= 1e-10
+    assert parity_err(psi.cpu().numpy(), ref) <= 1e-10
     load_library().gpe_autotune_cache_clear()
 
 

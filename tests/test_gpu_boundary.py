@@ -1,0 +1,178 @@
+"""GPU tests of the boundary's conventions: the stability check runs by
+default (with the g max|psi|^2 term) and refuses before any launch, calls on
+one handle from two streams are ordered, and the batch autotuner picks and
+caches a launch variant for a batch's own launches."""
+import numpy as np
+import pytest
+
+from oracle import realtime as rt
+from workloads import configs
+
+from gpu_cases import Case, parity_err, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def test_stability_check_is_the_default():
+    """Without any flag an unstable dt is refused with GPE_ERR_UNSTABLE before
+    a step runs (psi unchanged); the explicit opt-out runs it."""
+    from paper_2603_05447_amd import GPEError, _lib
+    w = configs.small_shell(n=16)
+    c = Case(w, "c128")
+    lam_t = 2 * sum(1 / h ** 2 for h in w.box.h)
+    psi = c.psi()
+    with pytest.raises(GPEError) as e:
+        c.grid.real_time(psi, c.pot, w.g, 3.0 / lam_t, 3)
+    assert e.value.status == _lib.GPE_ERR_UNSTABLE
+    with pytest.raises(GPEError) as e:
+        c.grid.imag_time(psi, c.pot, w.g, 4.5 / lam_t, 3)
+    assert e.value.status == _lib.GPE_ERR_UNSTABLE
+    assert np.array_equal(psi.cpu().numpy(), w.psi0)
+    # the opt-out runs the same unstable step (one step stays finite)
+    c.grid.real_time(psi, c.pot, w.g, 3.0 / lam_t, 1, check_stability=False, observe=False)
+    assert not np.array_equal(psi.cpu().numpy(), w.psi0)
+
+
+def test_stability_bound_includes_the_interaction_term():
+    """dt chosen so that dt (lambda_T + max V) is inside the RK4 interval but
+    dt (lambda_T + max V + g max|psi|^2) is not: refused; the same dt with a
+    state of small density passes.  The fidelity gradient uses 3 g max|psi|^2."""
+    from paper_2603_05447_amd import GPEError, _lib
+    w = configs.small_rf_ramp(n=20, steps=4, g=300.0, n_knots=4)
+    c = Case(w, "c128")
+    lam_t = 2 * sum(1 / h ** 2 for h in w.box.h)
+    V = np.sqrt((w.field[:, None] - np.asarray(w.knot_delta)[None, :]) ** 2 + w.omega ** 2)
+    vmax = float(np.max(V))
+    dmax = float(np.max(np.abs(w.psi0) ** 2))
+    bound = 2.0 * np.sqrt(2.0)
+    base = lam_t + vmax
+    dt = 0.9 * bound / base
+    gbig = 0.5 * base / dmax            # g dmax = base/2: dt * lambda = 1.35 bound
+    psi = c.psi()
+    with pytest.raises(GPEError) as e:
+        c.grid.real_time(psi, c.pot, gbig, dt, 1)
+    assert e.value.status == _lib.GPE_ERR_UNSTABLE and "max|psi|^2" in str(e.value)
+    assert np.array_equal(psi.cpu().numpy(), w.psi0)
+    # a hundred times weaker interaction: inside the bound, runs
+    c.grid.real_time(psi, c.pot, gbig / 100.0, dt, 1, observe=False)
+    # the adjoint's linearised operator: g dmax = 0.04 base passes forward
+    # (dt lambda = 0.936 bound) but 3 g dmax = 0.12 base does not (1.008 bound)
+    gmid = 0.04 * base / dmax
+    tgt = w.psi0 / np.sqrt(np.sum(np.abs(w.psi0) ** 2) * w.box.dV)
+    c.grid.real_time(c.psi(), c.pot, gmid, dt, 1, observe=False)
+    with pytest.raises(GPEError) as e:
+        c.grid.fidelity_grad(c.psi(), c.psi(tgt), c.pot, gmid, dt, 2)
+    assert e.value.status == _lib.GPE_ERR_UNSTABLE
+
+
+def test_imaginary_time_refuses_a_non_positive_interaction_factor():
+    from paper_2603_05447_amd import GPEError, _lib
+    w = configs.small_shell(n=16)
+    c = Case(w, "c128")
+    dmax = float(np.max(np.abs(w.psi0) ** 2))
+    dt = 1e-3
+    g = 2.5 / (dmax * dt)               # g |psi|^2 dt/2 = 1.25 at the peak
+    with pytest.raises(GPEError) as e:
+        c.grid.imag_time(c.psi(), c.pot, g, dt, 1)
+    assert e.value.status == _lib.GPE_ERR_UNSTABLE
+
+
+def test_calls_on_two_streams_are_ordered():
+    """Two real-time calls on one grid with different g and dt, the second on
+    another stream and issued without waiting: each result equals its own
+    serial run (the second call's parameter upload must not reach the first
+    call's kernels)."""
+    import torch
+    w = configs.small_rf_ramp(n=28, steps=30, g=300.0)
+    c = Case(w, "c128")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    steps = 60
+    ref_a, ref_b = c.psi(), c.psi()
+    c.grid.real_time(ref_a, c.pot, w.g, w.dt, steps, observe=False)
+    c.grid.real_time(ref_b, c.pot, 0.5 * w.g, 0.5 * w.dt, steps, observe=False)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        a, b = c.psi(), c.psi()
+        torch.cuda.synchronize()
+        c.grid.real_time(a, c.pot, w.g, w.dt, steps, observe=False, stream=s1)
+        c.grid.real_time(b, c.pot, 0.5 * w.g, 0.5 * w.dt, steps, observe=False, stream=s2)
+        torch.cuda.synchronize()
+        assert torch.equal(a, ref_a), rep
+        assert torch.equal(b, ref_b), rep
+    ref = rt.real_time(c.T, w.psi0, c.opot, w.g, w.dt, 0.0, steps)
+    assert parity_err(ref_a.cpu().numpy(), ref) <= 1e-10
+
+
+def _batch(ws, dtype):
+    import torch
+    from paper_2603_05447_amd import Grid, Batch
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rdt = torch.float64 if dtype == "c128" else torch.float32
+    grids = [Grid.from_box(w.box, runs=w.runs, device=0) for w in ws]
+    b = Batch(grids, device=0)
+    psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=cdt, device="cuda:0")
+    field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=rdt, device="cuda:0")
+    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    return grids, b, psi, field, ramps
+
+
+def _instances(k, steps=10):
+    ws = [configs.c4_instance(i, n_lo=14, n_hi=26, steps=steps) for i in range(k)]
+    for i, w in enumerate(ws):
+        w.g = 10.0 + 7.0 * i
+    return ws
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_autotune_picks_and_caches_a_variant(use_graph, dtype):
+    """The tuner times every launch variant on the batch's own steps, keeps
+    the fastest on the batch and in the cache; the tuned batch still matches
+    the single-grid runs (and the oracle in complex128); a new batch of the
+    same class takes the cached variant."""
+    import torch
+    from paper_2603_05447_amd import Batch, config_count, load_library
+    load_library().gpe_autotune_cache_clear()
+    ws = _instances(5)
+    grids, b, psi, field, ramps = _batch(ws, dtype)
+    gs, dts = [w.g for w in ws], [w.dt for w in ws]
+    scratch = psi.clone()
+    best, times = b.autotune(scratch, field, ramps, gs, dts, reps=2, use_graph=use_graph)
+    _print(f"batch autotune {dtype} graph={use_graph}: best {best}, ms/step "
+           + " ".join(f"{t:.3f}" for t in times))
+    assert 0 <= best < config_count() and b.get_config() == best
+    assert len(times) == config_count() and all(0.0 < t < 1e3 for t in times)
+    assert times[best] == min(times)
+    steps = 10
+    b.real_time(psi, field, ramps, gs, dts, steps, use_graph=use_graph, observe=False)
+    out = psi.cpu().numpy()
+    tol = 1e-13 if dtype == "c128" else 1e-6
+    for i, w in enumerate(ws):
+        c = Case(w, dtype)
+        p = c.psi()
+        c.grid.real_time(p, c.pot, w.g, w.dt, steps, observe=False)
+        mine = out[b.offsets[i]:b.offsets[i + 1]]
+        assert parity_err(mine, p.cpu().numpy()) <= tol, i
+        if dtype == "c128":
+            ref = rt.real_time(c.T, w.psi0, c.opot, w.g, w.dt, 0.0, steps)
+            assert parity_err(mine, ref) <= 1e-10, i
+    # a second batch of the same instances is of the same class
+    b2 = Batch(grids, device=0)
+    from paper_2603_05447_amd import _lib
+    dt_ = _lib.GPE_C128 if dtype == "c128" else _lib.GPE_C64
+    assert b2.apply_tuned(dt_) == best and b2.get_config() == best
+    load_library().gpe_autotune_cache_clear()
+    assert Batch(grids, device=0).apply_tuned(dt_) is None
+    del scratch
+    torch.cuda.synchronize()

@@ -3,8 +3,8 @@ configuration:
 
 * C3 (hollowing ramp, 256^3 box, 3.24M sites): one RK4 step in the middle of
   the ramp against the oracle on patches; the adjoint gradient of the
-  2000-step loss against central differences of the GPU forward loss (a
-  property that holds at any size).
+  2000-step loss against central differences (h = 1e-5, every one of the 8
+  knots) of the GPU forward loss (a property that holds at any size).
 * C4 (64 instances, 34.7M sites): the batched launches equal single-grid
   runs of sampled instances, one instance's three RK4 steps equal the
   oracle run on the whole instance, and the batched forward + adjoint gives
@@ -22,7 +22,7 @@ from oracle import operator as op, realtime as rt
 from oracle.potential import RFRamp
 from workloads import configs, site_linear_index
 
-from gpu_cases import Case, rel_l2
+from gpu_cases import Case, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 R_PATCH = 6
@@ -96,8 +96,8 @@ def _sampled_rk4(w, dtype, t0, tol, seed):
         idx, T, c = ri.patch(s)
         ramp = RFRamp(w.field[idx], w.omega, w.knot_t, w.knot_delta)
         ref.append(rt.rk4_step(T, w.psi0[idx], t0, w.dt, ramp, w.g)[c])
-    err = rel_l2(got, np.array(ref))
-    print(f"{w.name} {dtype}: sampled rel L2 {err:.3e}", flush=True)
+    err = parity_err(got, np.array(ref))
+    print(f"{w.name} {dtype}: sampled parity error {err:.3e}", flush=True)
     assert err <= tol
 
 
@@ -126,15 +126,20 @@ def test_c3_adjoint_gradient_matches_central_differences_at_full_size():
         ov = g.overlap(target, p)
         return 1.0 - abs(ov) ** 2
 
-    k = int(np.argmax(np.abs(grad)))
-    h = 1e-4
-    kp, km = w.knot_delta.copy(), w.knot_delta.copy()
-    kp[k] += h
-    km[k] -= h
-    fd = (loss_at(kp) - loss_at(km)) / (2 * h)
-    print(f"C3 full size: loss {loss:.12f}, knot {k}: adjoint {grad[k]:.6e}, central difference {fd:.6e}",
-          flush=True)
-    assert abs(fd - grad[k]) <= 1e-4 * np.max(np.abs(grad))
+    # central differences on every knot at h = 1e-5: O(h^2) truncation plus
+    # O(eps_loss / h) rounding of the two FP64 losses (measured: at most 4e-12
+    # apart from the adjoint on gradients of 8e-8 to 5.5e-5)
+    h = 1e-5
+    fd = np.zeros(len(w.knot_delta))
+    for k in range(len(w.knot_delta)):
+        kp, km = w.knot_delta.copy(), w.knot_delta.copy()
+        kp[k] += h
+        km[k] -= h
+        fd[k] = (loss_at(kp) - loss_at(km)) / (2 * h)
+        print(f"C3 full size: loss {loss:.12f}, knot {k}: adjoint {grad[k]:+.9e}, central difference {fd[k]:+.9e}, "
+              f"diff {abs(fd[k] - grad[k]):.2e}", flush=True)
+    gmax = np.max(np.abs(grad))
+    assert np.all(np.abs(fd - grad) <= 1e-6 * gmax + 1e-10)
 
 
 def test_c4_batch_equals_single_grids_and_oracle():
@@ -154,15 +159,15 @@ def test_c4_batch_equals_single_grids_and_oracle():
         c = Case(ws[i], "c64")
         p = c.psi()
         c.grid.real_time(p, c.pot, ws[i].g, ws[i].dt, steps, observe=False)
-        assert rel_l2(out[b.offsets[i]:b.offsets[i + 1]], p.cpu().numpy()) <= 1e-6, i
+        assert parity_err(out[b.offsets[i]:b.offsets[i + 1]], p.cpu().numpy()) <= 1e-6, i
     # one whole instance, three RK4 steps in complex128, against the oracle
     w = ws[5]
     c = Case(w, "c128")
     p = c.psi()
     c.grid.real_time(p, c.pot, w.g, w.dt, 3, observe=False)
     ref = rt.real_time(c.T, w.psi0, c.opot, w.g, w.dt, 0.0, 3)
-    err = rel_l2(p.cpu().numpy(), ref)
-    print(f"C4 instance 5 ({w.n_active} sites): rel L2 {err:.3e}", flush=True)
+    err = parity_err(p.cpu().numpy(), ref)
+    print(f"C4 instance 5 ({w.n_active} sites): parity error {err:.3e}", flush=True)
     assert err <= 1e-10
 
 
@@ -234,6 +239,6 @@ def test_c5_twenty_step_prefix_against_the_oracle_on_subdomains():
         ci, cj, ck = ri.site(s)
         near = (np.abs(ii - ci) <= inner) & (np.abs(jj - cj) <= inner) & (np.abs(kk - ck) <= inner)
         for dtype, tol in (("c128", 1e-10), ("c64", 1e-5)):
-            err = rel_l2(out[dtype][idx[near]], ref[near])
-            print(f"C5 20-step prefix, site {s}, {near.sum()} sites near it, {dtype}: rel L2 {err:.3e}", flush=True)
+            err = parity_err(out[dtype][idx[near]], ref[near])
+            print(f"C5 20-step prefix, site {s}, {near.sum()} sites near it, {dtype}: parity error {err:.3e}", flush=True)
             assert err <= tol

@@ -13,7 +13,7 @@ from oracle import adjoint as adj
 from oracle import operator as op
 from workloads import configs, site_linear_index
 
-from gpu_cases import Case, rel_l2
+from gpu_cases import Case, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -50,8 +50,8 @@ def test_hoc_imag_time_matches_oracle(dtype, make):
     psi = c.psi()
     obs = c.grid.imag_time(psi, c.pot, w.g, 2e-3, 20)
     ref, _ = itp.imaginary_time(c.T19, w.psi0, w.field, w.g, 2e-3, w.box.dV, 20)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    print(f"HOC ITP {w.name} {dtype}: rel L2 {err:.3e}", flush=True)
+    err = parity_err(psi.cpu().numpy(), ref)
+    print(f"HOC ITP {w.name} {dtype}: parity error {err:.3e}", flush=True)
     assert err <= TOL[dtype]
     N, E, mu = ob.energy_mu(c.T19, ref, w.field, w.g, w.box.dV)
     assert abs(obs["energy"] - E) <= TOL[dtype] * abs(E) * 10
@@ -67,7 +67,7 @@ def test_hoc_real_state_imag_time_matches_oracle():
     psi = torch.tensor(x, dtype=torch.float64, device="cuda:0")
     c.grid.imag_time(psi, c.pot, w.g, 2e-3, 15, observe=False)
     ref, _ = itp.imaginary_time(c.T19, x.astype(complex), w.field, w.g, 2e-3, w.box.dV, 15)
-    assert rel_l2(psi.cpu().numpy(), ref.real) <= 1e-10
+    assert parity_err(psi.cpu().numpy(), ref.real) <= 1e-10
 
 
 @pytest.mark.parametrize("integrator", ["rk4", "rkhe3", "rkck"])
@@ -82,8 +82,8 @@ def test_hoc_real_time_matches_oracle(integrator, dtype):
     else:
         A, b = (tableau.heun3 if integrator == "rkhe3" else tableau.cash_karp5)()
         ref = rt.real_time_tableau(c.T19, w.psi0, c.opot, w.g, 1e-3, 0.003, 20, A, b)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    print(f"HOC {integrator} {dtype}: rel L2 {err:.3e}", flush=True)
+    err = parity_err(psi.cpu().numpy(), ref)
+    print(f"HOC {integrator} {dtype}: parity error {err:.3e}", flush=True)
     assert err <= TOL[dtype]
     # the 7-point path really differs from the 19-point one here
     ref7 = rt.real_time(c.T, w.psi0, c.opot, w.g, 1e-3, 0.003, 20)
@@ -120,7 +120,7 @@ def test_hoc_switch_back_and_stability_bound():
     psi = c.psi()
     c.grid.real_time(psi, c.pot, w.g, 1e-3, 5, observe=False)
     ref = rt.real_time(c.T, w.psi0, c.opot, w.g, 1e-3, 0.0, 5)
-    assert rel_l2(psi.cpu().numpy(), ref) <= 1e-10
+    assert parity_err(psi.cpu().numpy(), ref) <= 1e-10
 
 
 ISO = [lambda: configs.random_mask_problem(n=(12, 11, 13), density=0.5, seed=43, g=40.0, h=(0.42, 0.42, 0.42)),
@@ -135,8 +135,8 @@ def test_27pt_imag_time_matches_oracle(dtype, make):
     psi = c.psi()
     obs = c.grid.imag_time(psi, c.pot, w.g, 2e-3, 20)
     ref, _ = itp.imaginary_time(c.T19, w.psi0, w.field, w.g, 2e-3, w.box.dV, 20)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    print(f"27pt ITP {w.name} {dtype}: rel L2 {err:.3e}", flush=True)
+    err = parity_err(psi.cpu().numpy(), ref)
+    print(f"27pt ITP {w.name} {dtype}: parity error {err:.3e}", flush=True)
     assert err <= TOL[dtype]
     N, E, mu = ob.energy_mu(c.T19, ref, w.field, w.g, w.box.dV)
     assert abs(obs["energy"] - E) <= TOL[dtype] * abs(E) * 10
@@ -154,8 +154,8 @@ def test_27pt_real_time_matches_oracle(integrator, dtype):
     else:
         A, b = tableau.cash_karp5()
         ref = rt.real_time_tableau(c.T19, w.psi0, c.opot, w.g, 1e-3, 0.003, 20, A, b)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    print(f"27pt {integrator} {dtype}: rel L2 {err:.3e}", flush=True)
+    err = parity_err(psi.cpu().numpy(), ref)
+    print(f"27pt {integrator} {dtype}: parity error {err:.3e}", flush=True)
     assert err <= TOL[dtype]
 
 

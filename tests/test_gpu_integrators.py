@@ -14,7 +14,7 @@ from oracle import realtime as rt
 from oracle import tableau
 from workloads import configs
 
-from gpu_cases import Case, rel_l2
+from gpu_cases import Case, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -53,8 +53,8 @@ def test_integrator_matches_oracle(integrator, dtype, make):
     psi = c.psi()
     obs = c.grid.real_time(psi, c.pot, w.g, dt, steps, t0=t0, integrator=integrator)
     ref = _oracle(c, w, dt, t0, steps, integrator)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    _print(f"  rel L2 = {err:.3e}")
+    err = parity_err(psi.cpu().numpy(), ref)
+    _print(f"  parity error = {err:.3e}")
     assert err <= TOL[dtype]
     N, E, mu = ob.energy_mu(c.T, ref, c.opot(t0 + steps * dt), w.g, w.box.dV)
     assert abs(obs["norm"] - N) <= TOL[dtype] * N * 10
@@ -80,7 +80,7 @@ def test_integrator_history_matches_oracle(integrator):
             assert abs(h[k, 1] - E) <= 1e-10 * abs(E)
             assert abs(h[k, 2] - mu) <= 1e-10 * abs(mu)
         y = rt.rk_step_tableau(c.T, y, n * 1e-3, 1e-3, c.opot, w.g, A, b)
-    assert rel_l2(psi.cpu().numpy(), y) <= 1e-10
+    assert parity_err(psi.cpu().numpy(), y) <= 1e-10
 
 
 def test_rkck_every_launch_config_gives_the_same_result():
@@ -96,7 +96,7 @@ def test_rkck_every_launch_config_gives_the_same_result():
         out = p.cpu().numpy()
         if ref is None:
             ref = _oracle(c, w, 1e-3, 0.0, 8, "rkck")
-        assert rel_l2(out, ref) <= 1e-10, k
+        assert parity_err(out, ref) <= 1e-10, k
 
 
 @pytest.mark.parametrize("integrator", ["rkhe3", "rkck"])
@@ -119,7 +119,7 @@ def test_batch_integrator_matches_single(integrator, use_graph):
     for i, w in enumerate(ws):
         c = Case(w, "c128")
         ref = _oracle(c, w, dts[i], 0.0, 6, integrator)
-        assert rel_l2(out[b.offsets[i]:b.offsets[i + 1]], ref) <= 1e-10, i
+        assert parity_err(out[b.offsets[i]:b.offsets[i + 1]], ref) <= 1e-10, i
 
 
 def test_integrator_arguments_are_checked():
@@ -131,12 +131,13 @@ def test_integrator_arguments_are_checked():
     with pytest.raises(ValueError):
         c.grid.real_time(psi, c.pot, w.g, 1e-3, 1, integrator="euler")
     # stability bounds: sqrt(3) for RKHE3 and 1 for RKCK (times 1/lambda,
-    # lambda = Gershgorin bound of T + max |V| over the ramp's knots); a dt
-    # at 1.9/lambda is accepted by RK4 only
+    # lambda = Gershgorin bound of T + max |V| over the ramp's knots + g
+    # max|psi|^2 at the start state); a dt at 1.9/lambda is accepted by RK4 only
     lam_t = 2 * sum(1 / h ** 2 for h in w.box.h)
     fmin, fmax = float(np.min(w.field)), float(np.max(w.field))
     vmax = max(np.hypot(max(abs(fmax - d), abs(fmin - d)), w.omega) for d in w.knot_delta)
-    dt = 1.9 / (lam_t + vmax)
+    dmax = float(np.max(np.abs(w.psi0) ** 2))
+    dt = 1.9 / (lam_t + vmax + w.g * dmax)
     for integ in ("rkhe3", "rkck"):
         with pytest.raises(GPEError) as e:
             c.grid.real_time(psi, c.pot, w.g, dt, 1, check_stability=True, integrator=integ)

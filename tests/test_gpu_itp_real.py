@@ -9,7 +9,7 @@ import pytest
 from oracle import itp, observables as ob
 from workloads import configs
 
-from gpu_cases import Case, rel_l2
+from gpu_cases import Case, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -52,8 +52,8 @@ def test_real_imag_time_matches_oracle(dtype, make):
     V = w.field if w.kind != "rf" else c.opot(0.0)
     ref, _ = itp.imaginary_time(c.T, x.astype(complex), V, w.g, dt, w.box.dV, steps)
     assert np.all(ref.imag == 0.0)
-    err = rel_l2(psi.cpu().numpy(), ref.real)
-    print(f"  rel L2 = {err:.3e}", flush=True)
+    err = parity_err(psi.cpu().numpy(), ref.real)
+    print(f"  parity error = {err:.3e}", flush=True)
     assert err <= TOL[dtype]
     N, E, mu = ob.energy_mu(c.T, ref, V, w.g, w.box.dV)
     assert abs(obs["norm"] - 1.0) <= (1e-12 if dtype == "c128" else 1e-6)
@@ -76,7 +76,7 @@ def test_real_and_complex_paths_agree_with_history():
     c.grid.imag_time(pc, c.pot, w.g, 1e-3, 20, obs_every=5, history=hc)
     out_c = pc.cpu().numpy()
     assert np.max(np.abs(out_c.imag)) == 0.0
-    assert rel_l2(pr.cpu().numpy(), out_c.real) <= 1e-14
+    assert parity_err(pr.cpu().numpy(), out_c.real) <= 1e-14
     assert np.allclose(hr.cpu().numpy(), hc.cpu().numpy(), rtol=1e-13, atol=0)
 
 
@@ -92,7 +92,7 @@ def test_real_imag_time_every_launch_config():
         if ref is None:
             r, _ = itp.imaginary_time(c.T, x.astype(complex), w.field, w.g, 2e-3, w.box.dV, 10)
             ref = r.real
-        assert rel_l2(p.cpu().numpy(), ref) <= 1e-10, k
+        assert parity_err(p.cpu().numpy(), ref) <= 1e-10, k
 
 
 def test_real_imag_time_single_site_and_zero_steps():

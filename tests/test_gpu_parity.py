@@ -9,7 +9,7 @@ import pytest
 from oracle import itp, realtime as rt, observables as ob
 from workloads import configs
 
-from gpu_cases import Case, rel_l2
+from gpu_cases import Case, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +41,8 @@ def test_imag_time_matches_oracle(dtype, make):
     psi = c.psi()
     obs = c.grid.imag_time(psi, c.pot, w.g, dt, steps)
     ref, _ = itp.imaginary_time(c.T, w.psi0, w.field, w.g, dt, w.box.dV, steps)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    _print(f"  rel L2 = {err:.3e}")
+    err = parity_err(psi.cpu().numpy(), ref)
+    _print(f"  parity error = {err:.3e}")
     assert err <= TOL[dtype]
     N, E, mu = ob.energy_mu(c.T, ref, w.field, w.g, w.box.dV)
     assert abs(obs["norm"] - 1.0) < 1e-12 if dtype == "c128" else abs(obs["norm"] - 1.0) < 1e-6
@@ -61,8 +61,8 @@ def test_c1_imag_time_500_steps_fp64():
     obs = c.grid.imag_time(psi, c.pot, w.g, w.dt, w.steps, obs_every=100, history=hist)
     ohist = []
     ref, ohist = itp.imaginary_time(c.T, w.psi0, w.field, w.g, w.dt, w.box.dV, w.steps, observe_every=100)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    _print(f"C1 ITP 500 steps: rel L2 = {err:.3e}, E = {obs['energy']:.12f}")
+    err = parity_err(psi.cpu().numpy(), ref)
+    _print(f"C1 ITP 500 steps: parity error = {err:.3e}, E = {obs['energy']:.12f}")
     assert err <= 1e-10
     h = hist.cpu().numpy()
     for k, row in enumerate(ohist):
@@ -82,8 +82,8 @@ def test_real_time_matches_oracle(dtype, make):
     psi = c.psi()
     obs = c.grid.real_time(psi, c.pot, w.g, dt, steps, t0=0.005)
     ref = rt.real_time(c.T, w.psi0, c.opot, w.g, dt, 0.005, steps)
-    err = rel_l2(psi.cpu().numpy(), ref)
-    _print(f"  rel L2 = {err:.3e}")
+    err = parity_err(psi.cpu().numpy(), ref)
+    _print(f"  parity error = {err:.3e}")
     assert err <= TOL[dtype]
     N, E, mu = ob.energy_mu(c.T, ref, c.opot(0.005 + steps * dt), w.g, w.box.dV)
     assert abs(obs["norm"] - N) <= TOL[dtype] * N * 10
@@ -137,7 +137,7 @@ def test_every_launch_config_gives_the_same_result():
         if base is None:
             base = out
         else:
-            assert rel_l2(out, base) <= 1e-13, k
+            assert parity_err(out, base) <= 1e-13, k
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -156,7 +156,7 @@ def test_every_launch_config_matches_the_oracle_on_a_fragmented_mask(dtype):
         psi = c.psi()
         c.grid.imag_time(psi, c.pot, w.g, 2e-3, 4, observe=False)
         c.grid.real_time(psi, c.pot, w.g, 1e-3, 4, observe=False)
-        err = rel_l2(psi.cpu().numpy(), ref)
+        err = parity_err(psi.cpu().numpy(), ref)
         assert err <= TOL[dtype], (k, err)
 
 
@@ -174,7 +174,7 @@ def test_small_grid_scale_formed_in_pass1_equals_the_finalize_path(real):
     c.grid.imag_time(a, c.pot, w.g, 2e-3, 30, observe=False)
     hist = torch.zeros((1, 3), dtype=torch.float64, device="cuda:0")
     c.grid.imag_time(b, c.pot, w.g, 2e-3, 30, obs_every=30, history=hist, observe=False)
-    assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-13
+    assert parity_err(a.cpu().numpy(), b.cpu().numpy()) <= 1e-13
 
 
 def test_stream_copy_reference_kernel():
@@ -234,7 +234,7 @@ def test_zero_steps_and_single_site():
     p = c1.psi()
     c1.grid.real_time(p, c1.pot, w1.g, 1e-2, 7, observe=False)
     ref = rt.real_time(c1.T, w1.psi0, c1.opot, w1.g, 1e-2, 0.0, 7)
-    assert rel_l2(p.cpu().numpy(), ref) <= 1e-14
+    assert parity_err(p.cpu().numpy(), ref) <= 1e-14
 
 
 def test_stability_bound_and_nonfinite_watchdog():

@@ -13,7 +13,7 @@ from oracle import itp, realtime as rt, restage
 from oracle import operator as op
 from workloads import Box, configs, runs_from_mask, site_linear_index
 
-from gpu_cases import Case, rel_l2
+from gpu_cases import Case, parity_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +49,7 @@ def test_lerp_stage_real_time_matches_oracle(dtype):
     obs = c.grid.real_time(psi, pot, w.g, dt, steps, t0=t0)
     opot = restage.LerpPotential(w.field, Vb, ta, tb)
     ref = rt.real_time(c.T, w.psi0, opot, w.g, dt, t0, steps)
-    assert rel_l2(psi.cpu().numpy(), ref) <= TOL[dtype]
+    assert parity_err(psi.cpu().numpy(), ref) <= TOL[dtype]
     from oracle import observables as ob
     N, E, mu = ob.energy_mu(c.T, ref, opot(t0 + steps * dt), w.g, w.box.dV)
     assert abs(obs["energy"] - E) <= TOL[dtype] * abs(E) * 10
@@ -57,7 +57,7 @@ def test_lerp_stage_real_time_matches_oracle(dtype):
     p2 = c.psi()
     c.grid.imag_time(p2, pot, w.g, 2e-3, 10, observe=False)
     r2, _ = itp.imaginary_time(c.T, w.psi0, opot(0.0), w.g, 2e-3, w.box.dV, 10)
-    assert rel_l2(p2.cpu().numpy(), r2) <= TOL[dtype]
+    assert parity_err(p2.cpu().numpy(), r2) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("rdt", ["f64", "f32"])
@@ -189,5 +189,5 @@ def test_staged_ramp_matches_oracle(dtype):
         y = rt.real_time(T, y, pot, s.g, s.dt, ta, s.steps_per_stage)
         assert recs[i]["n_active"] == lin.size
     assert np.array_equal(site_linear_index(box, g.runs()[:, :4]), lin)
-    assert rel_l2(out.cpu().numpy(), y) <= TOL[dtype]
+    assert parity_err(out.cpu().numpy(), y) <= TOL[dtype]
     assert recs[0]["norm_after_remap"] < 1.0          # the first selection drops the tail outside the shell

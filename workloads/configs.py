@@ -179,6 +179,31 @@ def c5(box_n=(2048, 2048, 1024), h: float = 0.0306, seed: int = 5) -> Workload:
                     g=1e4, dt=5e-5, steps=20000, psi0=psi)
 
 
+# C5 subdomain: the large thin shell downscaled by `scale` in every direction
+#     at the same spacing h, so the shell keeps its thickness in grid units:
+#     the box side and the shell radius shrink by `scale`, kappa grows by it
+#     (the same dU/dr at the shell, hence the same radial profile of V), Delta
+#     = kappa/2 (0.92 Lx)^2 shrinks by it, and g shrinks by scale^2 (the shell's
+#     area and so its norm-1 density change by scale^2; g |psi|^2, the Thomas-
+#     Fermi thickness and the stable dt stay those of the full shell).
+def c5_subdomain(scale: int = 8, box_n=(2048, 2048, 1024), h: float = 0.0306, seed: int = 5) -> Workload:
+    n = tuple(int(v) // int(scale) for v in box_n)
+    box = Box.centred(n, tuple(0.5 * v * h for v in n))
+    kappa, omega, cut = 12.9 * scale, 2.0, 61.0
+    Lx = 0.5 * n[0] * h
+    delta = 0.5 * kappa * (0.92 * Lx) ** 2
+    g = 1e4 / float(scale) ** 2
+    lo, hi = rf_window(delta, omega, cut)
+    runs = _rf_runs(box, kappa, lo, hi)
+    U = _rf_U(box, runs, kappa)
+    V = np.sqrt((U - delta) ** 2 + omega ** 2)
+    rng = np.random.default_rng(seed)
+    psi = tf_trial(V, omega + 20.0, g, box.dV, rng, 1e-3)
+    return Workload(f"C5 subdomain {n[0]}x{n[1]}x{n[2]} h={h} (C5 / {scale})", box, runs, U, "rf",
+                    omega=omega, knot_t=np.array([0.0]), knot_delta=np.array([delta]),
+                    g=g, dt=5e-5, steps=20000, psi0=psi, extra={"scale": int(scale)})
+
+
 # ----------------------------------------------------------------------------
 # Small seeded problems for tests.
 # ----------------------------------------------------------------------------
