@@ -295,6 +295,29 @@ gpe_status gpe_real_time(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_po
                          const gpe_params* params, double t0, int64_t nsteps, void* work, size_t work_bytes,
                          void* stream, gpe_obs* final_host, gpe_obs* history_dev);
 
+/* gpe_real_time for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same steps, kernels and results as gpe_real_time with the grid's launch
+ * variant, but the stage states live in a library-owned static device array
+ * of gpe_noalloc_scratch_bytes() bytes (64 MiB; each GPU the library runs on
+ * holds its own copy until the process ends) instead of a work argument, and
+ * no device or host memory is allocated on success (the launch tables of the
+ * grid's variant are built when the grid is created or its variant or stencil
+ * is chosen).  A grid whose stage states need more (gpe_work_bytes of the
+ * integrator's mode: 3 state vectors for RK4, 2 for RKHE3, 5 for RKCK, i.e.
+ * about 1.39M active sites in complex128 RK4) gets GPE_ERR_ARG before
+ * anything runs.  Nothing in the array needs to start at zero (every stage
+ * state is written before it is read).  Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (on different streams, or on
+ * different grids) race; calls on one stream are ordered.  Under graph
+ * capture pass final_host = NULL and set params->skip_stability_check (both
+ * synchronise the stream).  Per-kernel timing (gpe_timing_enable) keeps host
+ * bookkeeping and is meant to be off here. */
+gpe_status gpe_real_time_noalloc(gpe_grid grid, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                                 const gpe_params* params, double t0, int64_t nsteps, void* stream,
+                                 gpe_obs* final_host, gpe_obs* history_dev);
+size_t gpe_noalloc_scratch_bytes(void);
+
 /* Particle number (eq. (3)), energy and chemical potential of psi at time t:
  * E = dV[Re psi^H T psi + sum V|psi|^2 + g/2 sum|psi|^4]/N, mu the same with g. */
 gpe_status gpe_observe(gpe_grid grid, gpe_dtype dtype, const void* psi, const gpe_potential* pot, double t,

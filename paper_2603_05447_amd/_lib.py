@@ -71,6 +71,9 @@ SIGNATURES = {
                                      C.c_size_t, _vp, C.POINTER(Obs), _vp]),
     "gpe_real_time": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), C.c_double, _i64,
                                 _vp, C.c_size_t, _vp, C.POINTER(Obs), _vp]),
+    "gpe_real_time_noalloc": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.POINTER(Params), C.c_double,
+                                        _i64, _vp, C.POINTER(Obs), _vp]),
+    "gpe_noalloc_scratch_bytes": (C.c_size_t, []),
     "gpe_observe": (C.c_int, [_vp, C.c_int, _vp, C.POINTER(Potential), C.c_double, C.c_double, _vp,
                               C.POINTER(Obs)]),
     "gpe_overlap": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _pd]),

@@ -1785,6 +1785,91 @@ gpe_status gpe_real_time(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_poten
   return GPE_OK;
 }
 
+}  // extern "C"
+
+// ---- real time without allocation -------------------------------------------
+// The stage states of gpe_real_time_noalloc live in this file-scope device
+// array: every GPU the library runs on holds its own copy from module load
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// so kernels are given the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on `device` (which must be current)
+gpe_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(GPE_ERR_ARG, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(GPE_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[device] = p;
+  }
+  *out = g_scratch_dev[device];
+  return GPE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t gpe_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+gpe_status gpe_real_time_noalloc(gpe_grid g, gpe_dtype dtype, void* psi, const gpe_potential* pot,
+                                 const gpe_params* prm, double t0, int64_t nsteps, void* stream,
+                                 gpe_obs* final_host, gpe_obs* history_dev) {
+  gpe_status st = check_grid(g);
+  if (st == GPE_OK) st = check_dtype(dtype);
+  if (st == GPE_OK) st = check_ptr(psi, "psi");
+  if (st == GPE_OK) st = check_pot(pot);
+  if (st == GPE_OK) st = check_params(prm);
+  if (st != GPE_OK) return st;
+  if (!std::isfinite(t0)) return fail(GPE_ERR_ARG, "t0 must be finite");
+  if (nsteps < 0) return fail(GPE_ERR_ARG, "nsteps must be >= 0");
+  if (prm->obs_every > 0 && !history_dev) return fail(GPE_ERR_ARG, "obs_every > 0 needs history_dev");
+  const size_t need = work_bytes_for(g->lay.n_active, dtype, rt_work_mode(prm->integrator), nsteps, 0);
+  if (need > kNoAllocScratchBytes)
+    return fail(GPE_ERR_ARG, "the stage states need %zu bytes; the allocation-free call holds at most %zu", need,
+                kNoAllocScratchBytes);
+  DeviceGuard dg(g->device);
+  if (!dg.ok) return fail(GPE_ERR_DEVICE, "hipSetDevice(%d) failed", g->device);
+  void* work = nullptr;
+  st = scratch_address(g->device, &work);
+  if (st != GPE_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c;
+  // the launch tables exist since the grid was created or its variant chosen
+  st = make_ctx(g->prob.get(), g->prob->config, s, c, false);
+  if (st != GPE_OK) return st;
+  Ordered ord(g->prob.get(), s);
+  if (ord.st != GPE_OK) return ord.st;
+  const InstParams ip = make_params(pot, prm, t0);
+  st = g->prob->upload(*c.cs, &ip, s);
+  if (st != GPE_OK) return st;
+  if (!prm->skip_stability_check) {
+    st = dtype == GPE_C128 ? rt_stability<double>(c, &ip, pot->field, psi, prm->integrator)
+                           : rt_stability<float>(c, &ip, pot->field, psi, prm->integrator);
+    if (st != GPE_OK) return st;
+  }
+  st = dtype == GPE_C128
+           ? drive_rt<double>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, prm->integrator)
+           : drive_rt<float>(c, psi, pot->field, nsteps, work, prm->obs_every, history_dev, prm->integrator);
+  if (st != GPE_OK) return st;
+  if (final_host) {
+    st = dtype == GPE_C128 ? drive_observe<double>(c, psi, pot->field, false, nsteps)
+                           : drive_observe<float>(c, psi, pot->field, false, nsteps);
+    if (st != GPE_OK) return st;
+    return read_obs(*g->prob, final_host, s);
+  }
+  return GPE_OK;
+}
+
 gpe_status gpe_observe(gpe_grid g, gpe_dtype dtype, const void* psi, const gpe_potential* pot, double t, double gg,
                        void* stream, gpe_obs* out_host) {
   gpe_status st = check_grid(g);
