@@ -10,8 +10,9 @@ configuration:
   oracle run on the whole instance, and the batched forward + adjoint gives
   sampled instances their single-grid loss and gradient.
 * C5 (thin shell, 2048 x 2048 x 1024 box, 59.7M sites): one RK4 step in
-  complex128 and complex64 against the oracle on patches, and a 20-step
-  prefix against the oracle on subdomains of radius 88.
+  complex128 and complex64 against the oracle on patches, a 20-step prefix
+  against the oracle on subdomains of radius 88, and the whole 20,000-step
+  horizon on the shell shrunk 8x per axis against the oracle's stored run.
 
 Patches: the active sites within 6 sites of a sampled site (one RK4 step
 moves information 4 sites), found through the run table."""
@@ -242,3 +243,54 @@ def test_c5_twenty_step_prefix_against_the_oracle_on_subdomains():
             err = parity_err(out[dtype][idx[near]], ref[near])
             print(f"C5 20-step prefix, site {s}, {near.sum()} sites near it, {dtype}: parity error {err:.3e}", flush=True)
             assert err <= tol
+
+
+def test_c5_full_horizon_against_the_oracle_on_the_downscaled_shell():
+    """The precision study over its whole horizon: the 20,000 RK4 steps of
+    the large thin shell, on the geometrically similar shell shrunk 8x per
+    axis (931,864 sites, the same thickness in grid units), against the FP64
+    oracle's stored run (tests/golden/make_c5_subdomain.py): sampled sites
+    after 20, 200, 2,000 and 20,000 steps, and the norm and energy at the end.
+    complex128 stays at the FP64 bound throughout.  complex64 meets the
+    short-run 1e-5 bound after 20 steps; over the horizon its error is a
+    global phase (the state turns at the rate mu and FP32 rounds the phase
+    increment), so the phase-aligned error is held to 1e-5 and the raw one to
+    the bound stated below."""
+    import os
+    import torch
+    from paper_2603_05447_amd import Grid, Potential
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_subdomain_s8.npz")
+    if not os.path.exists(path):
+        pytest.skip("the oracle's stored run is written by tests/golden/make_c5_subdomain.py")
+    ref = np.load(path)
+    w = configs.c5_subdomain(8)
+    assert int(ref["n_active"]) == w.n_active and int(ref["steps"]) == w.steps
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    idx = torch.as_tensor(ref["sample_index"], device="cuda:0")
+    stops = [int(v) for v in ref["sample_steps"]]
+    o_end = ref["obs"][list(ref["obs_steps"]).index(w.steps)]
+    for dtype, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
+        U = torch.tensor(w.field, dtype=rdt, device="cuda:0")
+        psi = torch.tensor(w.psi0, dtype=cdt, device="cuda:0")
+        pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
+        done = 0
+        for k, stop in enumerate(stops):
+            obs = g.real_time(psi, pot, w.g, w.dt, stop - done, t0=done * w.dt)
+            done = stop
+            got = psi[idx].to(torch.complex128).cpu().numpy()
+            want = ref["samples"][k]
+            err = parity_err(got, want)
+            ov = np.vdot(want, got)
+            aligned = 1.0 - abs(ov) / (np.linalg.norm(got) * np.linalg.norm(want))
+            print(f"C5 subdomain {dtype} after {stop} steps: parity error {err:.3e}, phase-aligned {aligned:.3e}, "
+                  f"norm {obs['norm']:.12f} energy {obs['energy']:.10f}", flush=True)
+            if dtype == "c128":
+                assert err <= 1e-10, stop
+            else:
+                assert aligned <= 1e-5, stop
+                assert err <= (1e-5 if stop <= 20 else 2e-2), stop
+        tol_obs = 1e-10 if dtype == "c128" else 1e-5
+        print(f"  oracle norm {o_end[0]:.12f} energy {o_end[1]:.10f}", flush=True)
+        assert abs(obs["norm"] - o_end[0]) <= tol_obs * o_end[0]
+        assert abs(obs["energy"] - o_end[1]) <= tol_obs * abs(o_end[1])
+        del U, psi
