@@ -177,6 +177,29 @@ def test_small_grid_scale_formed_in_pass1_equals_the_finalize_path(real):
     assert parity_err(a.cpu().numpy(), b.cpu().numpy()) <= 1e-13
 
 
+def test_imaginary_time_on_a_grid_of_many_chunks():
+    """Grids of more than 1024 chunks renormalise through the finalize kernel
+    after every step (smaller ones form the scale inside pass 1): 10
+    imaginary-time steps of the downscaled C5 shell (931,864 sites, 1,821
+    chunks) against the oracle, the returned norm, and two runs bitwise
+    equal."""
+    import torch
+    w = configs.c5_subdomain(8)
+    c = Case(w, "c128")
+    V = np.sqrt((w.field - w.knot_delta[0]) ** 2 + w.omega ** 2)
+    from paper_2603_05447_amd import Potential
+    pot = Potential.static(torch.tensor(V, dtype=torch.float64, device="cuda:0"))
+    a, b = c.psi(), c.psi()
+    oa = c.grid.imag_time(a, pot, w.g, w.dt, 10)
+    c.grid.imag_time(b, pot, w.g, w.dt, 10, observe=False)
+    assert torch.equal(a, b)
+    ref, _ = itp.imaginary_time(c.T, w.psi0, V, w.g, w.dt, w.box.dV, 10)
+    err = parity_err(a.cpu().numpy(), ref)
+    _print(f"many-chunk imaginary time, {w.n_active} sites: parity error {err:.3e}, norm {oa['norm']:.15f}")
+    assert err <= 1e-10
+    assert abs(oa["norm"] - 1.0) <= 1e-12
+
+
 def test_stream_copy_reference_kernel():
     import torch
     from paper_2603_05447_amd import GPEError, _lib, stream_copy
