@@ -81,6 +81,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def batch_ramp(w):
+    """(omega, knot_t, knot_values, kind) of a ramped workload for Batch calls."""
+    from paper_2603_05447_amd import GPE_POT_RF_RAMP, GPE_POT_SHELL_RAMP
+    return (w.omega, w.knot_t, w.knot_delta, GPE_POT_SHELL_RAMP if w.kind == "shell" else GPE_POT_RF_RAMP)
+
+
 _WORKLOADS = {}
 
 
@@ -183,16 +189,22 @@ def setup_c2(dev, dtype):
     return w, g, U, psi, pot_itp, pot_rt
 
 
-def run_phase_timed(g, psi, pot_itp, pot_rt, w, k_itp, k_rt):
+def run_phase_timed(g, psi, pot_itp, pot_rt, w, k_itp, k_rt, configs=None):
+    """k_itp imaginary-time then k_rt RK4 steps; configs = (variant for
+    imaginary time, variant for real time) or None for the grid's own."""
     import torch
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record(s)
     if k_itp:
+        if configs:
+            g.set_config(configs[0])
         g.imag_time(psi, pot_itp, w.g, w.dt, k_itp, observe=False)
     e1.record(s)
     if k_rt:
+        if configs:
+            g.set_config(configs[1])
         g.real_time(psi, pot_rt, w.g, w.dt, k_rt, observe=False)
     e2.record(s)
     torch.cuda.synchronize()
@@ -264,21 +276,26 @@ def bench_c2(args, dev, dtype, report):
     if args.config is not None:
         g.set_config(args.config)
     tune = None
-    if args.autotune:
-        from paper_2603_05447_amd import config_describe
+    phase_cfg = None
+    if args.autotune or dtype == "c64":
+        # complex64 runs each phase with the variant the tuner picks for it on
+        # this grid (variant 0, the default, is the complex128 choice)
         scratch = psi.clone()
-        best, times = g.autotune(scratch, pot_rt, w.g, w.dt, reps=10)
+        b_itp, t_itp = g.autotune(scratch, pot_itp, w.g, w.dt, reps=5, phase="itp")
+        b_rt, t_rt = g.autotune(scratch, pot_rt, w.g, w.dt, reps=5)
         del scratch
-        tune = {"best": best, "rk4_ms_per_step": {str(k): times[k] for k in range(len(times))},
-                        "variants": {str(k): config_describe(k) for k in range(len(times))}}
-        log(f"[bench] autotune {dtype}: best variant {best}, ms/step {['%.3f' % t for t in times]}")
+        phase_cfg = (b_itp, b_rt)
+        tune = {"itp": {"best": b_itp, "ms_per_step": {str(k): t for k, t in enumerate(t_itp)}},
+                "rk4": {"best": b_rt, "ms_per_step": {str(k): t for k, t in enumerate(t_rt)}},
+                "variants": {str(k): config_describe(k) for k in range(len(t_rt))}}
+        log(f"[bench] autotune {dtype}: imaginary time variant {b_itp}, RK4 variant {b_rt}")
     # warmup (also builds the chunk tables)
-    run_phase_timed(g, psi, pot_itp, pot_rt, w, max(args.warmup, 1), 2 * max(args.warmup, 1))
+    run_phase_timed(g, psi, pot_itp, pot_rt, w, max(args.warmup, 1), 2 * max(args.warmup, 1), phase_cfg)
     scheme = config_describe(g.get_config())["rk_scheme"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with KernelTimer() as kt:
-        ms_itp, ms_rt = run_phase_timed(g, psi, pot_itp, pot_rt, w, args.steps, 2 * args.steps)
+        ms_itp, ms_rt = run_phase_timed(g, psi, pot_itp, pot_rt, w, args.steps, 2 * args.steps, phase_cfg)
         kern = kt.read()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -299,7 +316,7 @@ def bench_c2(args, dev, dtype, report):
                    "algo_bytes_per_site_step": sum(algo_bytes(f"rk_stage{i}", R, scheme) for i in range(1, 5)),
                    "rk_scheme": scheme},
         "final_norm": obs["norm"],
-        "config": g.get_config(),
+        "config": g.get_config() if phase_cfg is None else {"itp": phase_cfg[0], "rk4": phase_cfg[1]},
         "autotune": tune,
         "step_roofline": {"itp": step_roofline(n, ms_itp / args.steps, "itp", dtype),
                           "rk4": step_roofline(n, ms_rt / (2 * args.steps), "rk4", dtype)},
@@ -565,10 +582,11 @@ def cpu_per_config(report):
     del T, ramp, tgt, w
     # C4: four sampled instances, complex128, 10 RK4 steps each
     sites, el = 0, 0.0
+    from oracle.potential import ShellRamp
     for i in (0, 21, 42, 63):
         w = configs.c4_instance(i)
         T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, w.runs))
-        ramp = RFRamp(w.field, w.omega, w.knot_t, w.knot_delta)
+        ramp = ShellRamp(w.field, w.omega, w.knot_t, w.knot_delta)
         t = time.perf_counter()
         rt.real_time(T, w.psi0, ramp, w.g, w.dt, 0.0, 10)
         el += time.perf_counter() - t
@@ -648,8 +666,9 @@ def bench_adjoint(args, dev, report):
 
 
 def bench_batched(args, dev, report):
-    """64 instances (96^3..192^3 boxes), complex64 storage with FP64
-    reductions, one hipGraph-captured step replayed per step."""
+    """64 instances (96^3..192^3 boxes; harmonic shells whose radius is
+    ramped over 8 knots), complex64 storage with FP64 reductions, one
+    hipGraph-captured step replayed per step."""
     import torch
     from paper_2603_05447_amd import Grid, Batch, GPE_C64, GPE_MODE_RT
     from workloads import configs
@@ -660,7 +679,7 @@ def bench_batched(args, dev, report):
     b = Batch(grids, device=0)
     psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=torch.complex64, device=dev)
     field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=torch.float32, device=dev)
-    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    ramps = [batch_ramp(w) for w in ws]
     gs, dts = [w.g for w in ws], [w.dt for w in ws]
     work = torch.empty(b.work_bytes(GPE_C64, GPE_MODE_RT, 1), dtype=torch.uint8, device=dev)
     from paper_2603_05447_amd import config_describe

@@ -93,6 +93,11 @@ typedef struct gpe_batch_s* gpe_batch;
  *            potential with bare trap U = field; Delta(t) is the
  *            piecewise-linear interpolant of (knot_t[k], knot_delta[k]),
  *            constant before the first and after the last knot.
+ *   SHELL_RAMP: V(x,t) = omega/2 (field[x] - R0(t))^2, a harmonic shell of
+ *            stiffness lambda = omega around the distances r = field (the
+ *            shell of the C1 workload) whose radius R0(t) is ramped like
+ *            Delta(t): the piecewise-linear interpolant of (knot_t[k],
+ *            knot_delta[k] = R0_k).  Used by every call that takes RF_RAMP.
  *   LERP   : one stage of a staged ramp (Sec. V: precomputed potentials,
  *            linear interpolation in time between consecutive ones):
  *            V(x,t) = (1 - l) field[x] + l field2[x], l = clamp((t - knot_t[0]) /
@@ -103,7 +108,7 @@ typedef struct gpe_batch_s* gpe_batch;
  * GPE_C128, float for GPE_C64).  knot_t/knot_delta are host arrays of n_knots
  * (1..GPE_MAX_KNOTS) entries, knot_t strictly increasing; ignored for STATIC.
  * field2 is ignored except for LERP. */
-typedef enum { GPE_POT_STATIC = 0, GPE_POT_RF_RAMP = 1, GPE_POT_LERP = 2 } gpe_pot_kind;
+typedef enum { GPE_POT_STATIC = 0, GPE_POT_RF_RAMP = 1, GPE_POT_LERP = 2, GPE_POT_SHELL_RAMP = 3 } gpe_pot_kind;
 
 typedef struct {
   int32_t kind;
@@ -390,11 +395,11 @@ gpe_status gpe_staged_ramp_run(gpe_grid src, const void* psi_src, int32_t n_stag
  * psi_target) are concatenated the same way.  Batches use the 7-point
  * stencil whatever stencil the member grids have selected. */
 typedef struct {
-  double omega;
+  double omega;              /* Omega (RF_RAMP) or lambda (SHELL_RAMP) */
   int32_t n_knots;
-  int32_t reserved;
+  int32_t kind;              /* GPE_POT_RF_RAMP (0 is read as RF_RAMP) or GPE_POT_SHELL_RAMP */
   const double* knot_t;      /* host */
-  const double* knot_delta;  /* host */
+  const double* knot_delta;  /* host: Delta_k (RF_RAMP) or R0_k (SHELL_RAMP) */
 } gpe_ramp;
 
 gpe_status gpe_batch_create(int32_t n, const gpe_grid* grids, int device, gpe_batch* out);

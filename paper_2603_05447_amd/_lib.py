@@ -13,7 +13,7 @@ STATUS_NAMES = ["GPE_OK", "GPE_ERR_ARG", "GPE_ERR_ALLOC", "GPE_ERR_DEVICE", "GPE
 GPE_C128, GPE_C64 = 0, 1
 GPE_MODE_ITP, GPE_MODE_RT, GPE_MODE_ADJ, GPE_MODE_RT_RKHE3, GPE_MODE_RT_RKCK, GPE_MODE_ITP_REAL = range(6)
 GPE_RK4, GPE_RKHE3, GPE_RKCK = 0, 1, 2
-GPE_POT_STATIC, GPE_POT_RF_RAMP, GPE_POT_LERP = 0, 1, 2
+GPE_POT_STATIC, GPE_POT_RF_RAMP, GPE_POT_LERP, GPE_POT_SHELL_RAMP = 0, 1, 2, 3
 GPE_MAX_KNOTS = 32
 
 
@@ -36,7 +36,7 @@ class Obs(C.Structure):
 
 
 class Ramp(C.Structure):
-    _fields_ = [("omega", C.c_double), ("n_knots", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("omega", C.c_double), ("n_knots", C.c_int32), ("kind", C.c_int32),
                 ("knot_t", C.POINTER(C.c_double)), ("knot_delta", C.POINTER(C.c_double))]
 
 

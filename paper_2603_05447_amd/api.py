@@ -75,6 +75,12 @@ class Potential:
         return Potential(L.GPE_POT_RF_RAMP, U, omega, knot_t, knot_delta)
 
     @staticmethod
+    def shell(r: torch.Tensor, lam: float, knot_t, knot_radius) -> "Potential":
+        """Harmonic shell lam/2 (r - R0(t))^2 around the per-site distances r,
+        with the radius R0(t) ramped through (knot_t, knot_radius)."""
+        return Potential(L.GPE_POT_SHELL_RAMP, r, lam, knot_t, knot_radius)
+
+    @staticmethod
     def lerp(Va: torch.Tensor, Vb: torch.Tensor, t_a: float, t_b: float) -> "Potential":
         """Stage potential interpolated linearly in time from Va (at t_a) to Vb (at t_b)."""
         return Potential(L.GPE_POT_LERP, Va, 0.0, [t_a, t_b], None, field2=Vb)
@@ -91,7 +97,7 @@ class Potential:
         p.field = self.field.data_ptr()
         p.omega = self.omega
         keep = []
-        if self.kind == L.GPE_POT_RF_RAMP:
+        if self.kind in (L.GPE_POT_RF_RAMP, L.GPE_POT_SHELL_RAMP):
             kt, kd = _dbl(self.knot_t), _dbl(self.knot_delta)
             keep = [kt, kd]
             p.n_knots = len(self.knot_t)
@@ -488,15 +494,19 @@ class Batch:
 
     @staticmethod
     def _ramps(ramps):
+        """ramps[i] = (omega, knot_t, knot_values) for an RF ramp, or
+        (omega, knot_t, knot_values, kind) with kind GPE_POT_RF_RAMP or
+        GPE_POT_SHELL_RAMP."""
         n = len(ramps)
         arr = (L.Ramp * n)()
         keep = []
-        for i, (omega, kt, kd) in enumerate(ramps):
+        for i, rp in enumerate(ramps):
+            omega, kt, kd = rp[:3]
             a, b = _dbl(kt), _dbl(kd)
             keep += [a, b]
             arr[i].omega = float(omega)
             arr[i].n_knots = len(kt)
-            arr[i].reserved = 0
+            arr[i].kind = int(rp[3]) if len(rp) > 3 else L.GPE_POT_RF_RAMP
             arr[i].knot_t = C.cast(a, C.POINTER(C.c_double))
             arr[i].knot_delta = C.cast(b, C.POINTER(C.c_double))
         return arr, keep
@@ -550,9 +560,10 @@ class FidelityGrad(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, knots: torch.Tensor, grid: Grid, psi0: torch.Tensor, target: torch.Tensor, U: torch.Tensor,
-                omega: float, knot_t, g: float, dt: float, steps: int, ckpt_every: int = 0):
+                omega: float, knot_t, g: float, dt: float, steps: int, ckpt_every: int = 0,
+                kind: int = L.GPE_POT_RF_RAMP):
         kd = knots.detach().to("cpu", torch.float64).numpy()
-        pot = Potential.rf(U, omega, knot_t, kd)
+        pot = Potential(kind, U, omega, knot_t, kd)
         loss, grad = grid.fidelity_grad(psi0, target, pot, g, dt, steps, 0.0, ckpt_every)
         ctx.save_for_backward(torch.as_tensor(grad, dtype=knots.dtype, device=knots.device))
         return torch.tensor(loss, dtype=knots.dtype, device=knots.device)
@@ -560,7 +571,7 @@ class FidelityGrad(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         (grad,) = ctx.saved_tensors
-        return (grad_out * grad,) + (None,) * 10
+        return (grad_out * grad,) + (None,) * 11
 
 
 class BatchFidelityGrad(torch.autograd.Function):
@@ -572,11 +583,12 @@ class BatchFidelityGrad(torch.autograd.Function):
     @staticmethod
     def forward(ctx, knots: torch.Tensor, batch: "Batch", psi0: torch.Tensor, target: torch.Tensor,
                 field: torch.Tensor, omegas, knot_ts, gs, dts, steps: int, ckpt_every: int = 0,
-                use_graph: bool = False):
+                use_graph: bool = False, kinds=None):
         kd = knots.detach().to("cpu", torch.float64).numpy()
         if kd.ndim != 2 or kd.shape[0] != len(batch.grids):
             raise ValueError("knots must be (n_instances, n_knots)")
-        ramps = [(omegas[i], knot_ts[i], kd[i]) for i in range(kd.shape[0])]
+        ramps = [(omegas[i], knot_ts[i], kd[i], L.GPE_POT_RF_RAMP if kinds is None else kinds[i])
+                 for i in range(kd.shape[0])]
         loss, grads = batch.fidelity_grad(psi0, target, field, ramps, gs, dts, steps, 0.0, ckpt_every,
                                           use_graph=use_graph)
         ctx.save_for_backward(torch.as_tensor(np.stack(grads), dtype=knots.dtype, device=knots.device))
@@ -585,7 +597,7 @@ class BatchFidelityGrad(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         (grad,) = ctx.saved_tensors
-        return (grad_out[:, None] * grad,) + (None,) * 11
+        return (grad_out[:, None] * grad,) + (None,) * 12
 
 
 def stream_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:

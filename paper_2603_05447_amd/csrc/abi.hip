@@ -740,7 +740,8 @@ gpe_status check_knots(int32_t n, const double* kt, const double* kv, const char
 
 gpe_status check_pot(const gpe_potential* pot) {
   if (!pot) return fail(GPE_ERR_ARG, "potential is NULL");
-  if (pot->kind != GPE_POT_STATIC && pot->kind != GPE_POT_RF_RAMP && pot->kind != GPE_POT_LERP)
+  if (pot->kind != GPE_POT_STATIC && pot->kind != GPE_POT_RF_RAMP && pot->kind != GPE_POT_LERP &&
+      pot->kind != GPE_POT_SHELL_RAMP)
     return fail(GPE_ERR_ARG, "unknown potential kind");
   gpe_status st = check_ptr(pot->field, "potential field");
   if (st != GPE_OK) return st;
@@ -752,7 +753,7 @@ gpe_status check_pot(const gpe_potential* pot) {
       return fail(GPE_ERR_ARG, "LERP stage times must be finite and increasing");
     return GPE_OK;
   }
-  if (pot->kind == GPE_POT_RF_RAMP) {
+  if (pot->kind == GPE_POT_RF_RAMP || pot->kind == GPE_POT_SHELL_RAMP) {
     if (!std::isfinite(pot->omega)) return fail(GPE_ERR_ARG, "omega must be finite");
     return check_knots(pot->n_knots, pot->knot_t, pot->knot_delta, "potential");
   }
@@ -784,7 +785,8 @@ InstParams make_params(const gpe_potential* pot, const gpe_params* prm, double t
   ip.t0 = t0;
   ip.norm_target = (prm && prm->norm_target > 0.0) ? prm->norm_target : 1.0;
   ip.pot_kind = pot ? pot->kind : GPE_POT_STATIC;
-  ip.omega = (pot && pot->kind == GPE_POT_RF_RAMP) ? pot->omega : 0.0;
+  const bool ramp = pot && (pot->kind == GPE_POT_RF_RAMP || pot->kind == GPE_POT_SHELL_RAMP);
+  ip.omega = ramp ? pot->omega : 0.0;
   ip.n_knots = 1;
   ip.field2 = nullptr;
   if (pot && pot->kind == GPE_POT_LERP) {
@@ -793,7 +795,7 @@ InstParams make_params(const gpe_potential* pot, const gpe_params* prm, double t
     ip.knot_t[1] = pot->knot_t[1];
     ip.field2 = pot->field2;
   }
-  if (pot && pot->kind == GPE_POT_RF_RAMP) {
+  if (ramp) {
     ip.n_knots = pot->n_knots;
     for (int k = 0; k < pot->n_knots; ++k) {
       ip.knot_t[k] = pot->knot_t[k];
@@ -1212,10 +1214,14 @@ gpe_status field_bounds(const Ctx& c, const void* field, const void* psi, bool r
   for (int i = 0; i < n; ++i) {
     const InstParams& ip = ps[i];
     dmax[i] = o[i].dmax;
-    if (ip.pot_kind == GPE_POT_RF_RAMP) {
+    if (ip.pot_kind == GPE_POT_RF_RAMP || ip.pot_kind == GPE_POT_SHELL_RAMP) {
+      // the ramp parameter stays between knot values, where |field - it| is
+      // largest at an end of the field's range
       for (int k = 0; k < ip.n_knots; ++k) {
         const double d = std::max(std::fabs(o[i].fmax - ip.knot_v[k]), std::fabs(o[i].fmin - ip.knot_v[k]));
-        vmax[i] = std::max(vmax[i], std::sqrt(d * d + ip.omega * ip.omega));
+        const double v = ip.pot_kind == GPE_POT_SHELL_RAMP ? 0.5 * std::fabs(ip.omega) * d * d
+                                                           : std::sqrt(d * d + ip.omega * ip.omega);
+        vmax[i] = std::max(vmax[i], v);
       }
     } else {
       vmax[i] = std::max(std::fabs(o[i].fmin), std::fabs(o[i].fmax));
@@ -1938,7 +1944,8 @@ gpe_status gpe_fidelity_grad(gpe_grid g, gpe_dtype dtype, const void* psi0, cons
   if (st == GPE_OK) st = check_pot(pot);
   if (st == GPE_OK) st = check_params(prm);
   if (st != GPE_OK) return st;
-  if (pot->kind != GPE_POT_RF_RAMP) return fail(GPE_ERR_ARG, "fidelity gradient needs an RF_RAMP potential");
+  if (pot->kind != GPE_POT_RF_RAMP && pot->kind != GPE_POT_SHELL_RAMP)
+    return fail(GPE_ERR_ARG, "the fidelity gradient needs a ramped potential (RF_RAMP or SHELL_RAMP)");
   if (prm->integrator != GPE_RK4) return fail(GPE_ERR_ARG, "the fidelity gradient is the adjoint of RK4 only");
   if (!loss_host || !grad_host) return fail(GPE_ERR_ARG, "loss_host and grad_host are required");
   if (psi_final) {
@@ -2181,8 +2188,10 @@ static gpe_status batch_params(gpe_batch b, const gpe_ramp* ramps, const gpe_par
     st = check_knots(ramps[i].n_knots, ramps[i].knot_t, ramps[i].knot_delta, "ramp");
     if (st != GPE_OK) return st;
     if (!std::isfinite(ramps[i].omega)) return fail(GPE_ERR_ARG, "ramp %d: omega must be finite", i);
+    if (ramps[i].kind != 0 && ramps[i].kind != GPE_POT_RF_RAMP && ramps[i].kind != GPE_POT_SHELL_RAMP)
+      return fail(GPE_ERR_ARG, "ramp %d: kind must be GPE_POT_RF_RAMP (or 0) or GPE_POT_SHELL_RAMP", i);
     gpe_potential pot;
-    pot.kind = GPE_POT_RF_RAMP;
+    pot.kind = ramps[i].kind == GPE_POT_SHELL_RAMP ? GPE_POT_SHELL_RAMP : GPE_POT_RF_RAMP;
     pot.n_knots = ramps[i].n_knots;
     pot.field = nullptr;
     pot.omega = ramps[i].omega;

@@ -141,29 +141,41 @@ __device__ __forceinline__ double stage_lambda(const InstParams& ip, double t) {
 // the time parameter of a potential kind: Delta(t) for RF_RAMP, the stage
 // fraction for LERP, unused for STATIC
 __device__ __forceinline__ double pot_param(const InstParams& ip, double t) {
-  if (ip.pot_kind == GPE_POT_RF_RAMP) return delta_at(ip, t);
+  if (ip.pot_kind == GPE_POT_RF_RAMP || ip.pot_kind == GPE_POT_SHELL_RAMP) return delta_at(ip, t);
   if (ip.pot_kind == GPE_POT_LERP) return stage_lambda(ip, t);
   return 0.0;
 }
 
-// V at a site: u = field, u2 = second field (LERP only), p = pot_param
+// The constant of a potential kind: omega^2 for the RF-dressed form, lambda/2
+// for the harmonic shell
+__device__ __forceinline__ double pot_const(const InstParams& ip) {
+  return ip.pot_kind == GPE_POT_SHELL_RAMP ? 0.5 * ip.omega : ip.omega * ip.omega;
+}
+
+// V at a site: u = field, u2 = second field (LERP only), p = pot_param,
+// c = pot_const
 template <typename R>
-__device__ __forceinline__ R potential(int kind, R u, R u2, R p, R omega2) {
+__device__ __forceinline__ R potential(int kind, R u, R u2, R p, R c) {
   if (kind == GPE_POT_RF_RAMP) {
     const R d = u - p;
-    return sqrt(d * d + omega2);
+    return sqrt(d * d + c);
+  }
+  if (kind == GPE_POT_SHELL_RAMP) {
+    const R d = u - p;
+    return c * d * d;
   }
   if (kind == GPE_POT_LERP) return (R(1) - p) * u + p * u2;
   return u;
 }
 
-// dV/dDelta of the RF-dressed potential
+// dV/dDelta of the RF-dressed potential, dV/dR0 of the harmonic shell
 template <typename R>
-__device__ __forceinline__ R dpot_ddelta(int kind, R u, R delta, R omega2) {
+__device__ __forceinline__ R dpot_ddelta(int kind, R u, R delta, R c) {
   if (kind == GPE_POT_RF_RAMP) {
     const R d = u - delta;
-    return -d / sqrt(d * d + omega2);
+    return -d / sqrt(d * d + c);
   }
+  if (kind == GPE_POT_SHELL_RAMP) return R(-2) * c * (u - delta);
   return R(0);
 }
 
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const R g = (R)ip.g, dt = (R)ip.dt;
   const R cx = (R)ip.cx, cy = (R)ip.cy, cz = (R)ip.cz, cd = (R)ip.cd;
   const int kind = ip.pot_kind;
-  const R omega2 = (R)(ip.omega * ip.omega);
+  const R omega2 = (R)pot_const(ip);
   const int64_t step = a.step >= 0 ? a.step : *pl.step;
   const double tstage = ip.t0 + ((double)step + a.c_stage) * ip.dt;
   const R delta = (R)pot_param(ip, tstage);
@@ -690,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     if (threadIdx.x == 0) {
       if constexpr (ADJ) {
         // dL/dDelta_k += dt * phi_k(t_i) * q  (hat functions of the ramp knots)
-        if (kind == GPE_POT_RF_RAMP) {
+        if (kind == GPE_POT_RF_RAMP || kind == GPE_POT_SHELL_RAMP) {
           const int n = ip.n_knots;
           const double q = ip.dt * acc[0];
           double* ka = pl.knot_acc + (size_t)cidx * GPE_MAX_KNOTS;
@@ -992,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_point(const Plan pl, const PointArgs<R>
   const Chunk ch = pl.chunks[cidx];
   const InstParams& ip = pl.inst[ch.inst];
   const int kind = ip.pot_kind;
-  const R omega2 = (R)(ip.omega * ip.omega);
+  const R omega2 = (R)pot_const(ip);
   const double t = ip.t0 + (double)(*pl.step) * ip.dt;
   const R delta = (R)pot_param(ip, t);
   const R* const field2 = reinterpret_cast<const R*>(ip.field2);
@@ -1191,9 +1203,11 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const Plan pl, int kind,
   acc[0] = range ? 1e300 : 0.0;
   acc[1] = range ? -1e300 : 0.0;
   acc[2] = acc[3] = 0.0;
-  // component-major partials: each pass of the loop is a coalesced read; 8
-  // independent loads are issued before they are added in a fixed order
-  constexpr int U = 8;
+  // component-major partials: each pass of the loop is a coalesced read; 32
+  // independent loads are issued before they are added in a fixed order (one
+  // pass covers the 31k chunks of the headline grid, so the latency of a
+  // single round trip is paid once)
+  constexpr int U = 32;
   for (int base = c0; base < c1; base += FIN_BLOCK * U) {
     for (int r = 0; r < nr; ++r) {
       double v[U];

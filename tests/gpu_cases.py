@@ -5,7 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 from oracle import operator as op
-from oracle.potential import StaticPotential, RFRamp
+from oracle.potential import StaticPotential, RFRamp, ShellRamp
 from workloads import site_linear_index
 
 
@@ -33,6 +33,30 @@ def parity_err(a, b) -> float:
     return max(rel_l2(a, b), max_rel(a, b) / ELEMENT_FACTOR)
 
 
+def ramp_of(w):
+    """The batch ramp tuple (omega, knot_t, knot_values, kind) of a workload."""
+    from paper_2603_05447_amd import GPE_POT_RF_RAMP, GPE_POT_SHELL_RAMP
+    return (w.omega, w.knot_t, w.knot_delta, GPE_POT_SHELL_RAMP if w.kind == "shell" else GPE_POT_RF_RAMP)
+
+
+def oracle_ramp(w, field=None, knot_delta=None):
+    """The oracle's potential of a ramped workload (optionally on a subset of
+    its field and with other knot values)."""
+    f = w.field if field is None else field
+    kd = w.knot_delta if knot_delta is None else knot_delta
+    if w.kind == "shell":
+        return ShellRamp(f, w.omega, w.knot_t, kd)
+    return RFRamp(f, w.omega, w.knot_t, kd)
+
+
+def device_ramp(w, field):
+    """The binding's potential of a ramped workload on a device field."""
+    from paper_2603_05447_amd import Potential
+    if w.kind == "shell":
+        return Potential.shell(field, w.omega, w.knot_t, w.knot_delta)
+    return Potential.rf(field, w.omega, w.knot_t, w.knot_delta)
+
+
 class Case:
     """A workload on the GPU (binding objects) and on the CPU (oracle objects)."""
 
@@ -48,9 +72,9 @@ class Case:
         if config is not None:
             self.grid.set_config(config)
         self.field = torch.tensor(w.field, dtype=self.rdt, device=self.dev)
-        if w.kind == "rf":
-            self.pot = Potential.rf(self.field, w.omega, w.knot_t, w.knot_delta)
-            self.opot = RFRamp(w.field, w.omega, w.knot_t, w.knot_delta)
+        if w.kind in ("rf", "shell"):
+            self.pot = device_ramp(w, self.field)
+            self.opot = oracle_ramp(w)
         else:
             self.pot = Potential.static(self.field)
             self.opot = StaticPotential(w.field)

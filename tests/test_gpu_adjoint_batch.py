@@ -7,7 +7,7 @@ import pytest
 from oracle import adjoint as adj, itp, realtime as rt
 from workloads import configs
 
-from gpu_cases import Case, parity_err, rel_l2
+from gpu_cases import Case, parity_err, rel_l2, ramp_of
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +44,35 @@ def test_fidelity_gradient_matches_oracle_adjoint(ckpt):
     assert parity_err(fin.cpu().numpy(), oy) <= 1e-10
     assert abs(loss - oloss) <= 1e-10 * max(abs(oloss), 1e-3)
     assert np.max(np.abs(grad - ograd)) <= 1e-9 * np.max(np.abs(ograd))
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-9), ("c64", 1e-3)])
+def test_shell_ramp_gradient_matches_oracle_adjoint(dtype, tol):
+    """The ramped parameter is the radius of a harmonic shell (the C4 sweep's
+    potential, GPE_POT_SHELL_RAMP): loss, final state and knot gradient
+    against the oracle's adjoint; the autograd wrapper passes the kind on."""
+    import torch
+    from paper_2603_05447_amd import FidelityGrad, GPE_POT_SHELL_RAMP
+    w = configs.c4_instance(2, n_lo=22, n_hi=22, steps=16)
+    w.g = 60.0
+    c = Case(w, dtype)
+    tgt = _target(w, 11)
+    psi0, target = c.psi(), c.psi(tgt)
+    fin = torch.empty_like(psi0)
+    loss, grad = c.grid.fidelity_grad(psi0, target, c.pot, w.g, w.dt, w.steps, psi_final=fin)
+    oloss, ograd, oy = adj.fidelity_grad(c.T, c.opot, w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV)
+    err = np.max(np.abs(grad - ograd)) / np.max(np.abs(ograd))
+    _print(f"shell ramp adjoint {dtype}: loss {loss:.15f} vs {oloss:.15f}; grad rel err {err:.3e}")
+    assert parity_err(fin.cpu().numpy(), oy) <= (1e-10 if dtype == "c128" else 1e-5)
+    assert abs(loss - oloss) <= (1e-10 if dtype == "c128" else 1e-5)
+    assert err <= tol
+    if dtype == "c128":
+        knots = torch.tensor(w.knot_delta, dtype=torch.float64, requires_grad=True)
+        l2 = FidelityGrad.apply(knots, c.grid, psi0, target, c.field, w.omega, w.knot_t, w.g, w.dt, w.steps, 0,
+                                GPE_POT_SHELL_RAMP)
+        l2.backward()
+        assert abs(l2.item() - oloss) <= 1e-10
+        assert np.max(np.abs(knots.grad.numpy() - ograd)) <= 1e-9 * np.max(np.abs(ograd))
 
 
 def test_fidelity_gradient_matches_central_differences_on_gpu():
@@ -109,7 +138,7 @@ def _batch(ws, dtype):
     b = Batch(grids, device=0)
     psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=cdt, device="cuda:0")
     field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=rdt, device="cuda:0")
-    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    ramps = [ramp_of(w) for w in ws]
     return b, psi, field, ramps
 
 
@@ -250,7 +279,7 @@ def test_batch_autograd_function():
     target = torch.tensor(np.concatenate(tg), dtype=torch.complex128, device="cuda:0")
     knots = torch.tensor(np.stack([w.knot_delta for w in ws]), dtype=torch.float64, requires_grad=True)
     loss = BatchFidelityGrad.apply(knots, b, psi, target, field, [w.omega for w in ws], [w.knot_t for w in ws],
-                                   [w.g for w in ws], [w.dt for w in ws], 8)
+                                   [w.g for w in ws], [w.dt for w in ws], 8, 0, False, [ramp_of(w)[3] for w in ws])
     weights = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64)
     (weights * loss).sum().backward()
     for i, w in enumerate(ws):

@@ -8,7 +8,7 @@ import pytest
 from oracle import realtime as rt
 from workloads import configs
 
-from gpu_cases import Case, parity_err, rel_l2
+from gpu_cases import Case, parity_err, rel_l2, ramp_of
 
 pytestmark = pytest.mark.gpu
 
@@ -123,7 +123,7 @@ def _batch(ws, dtype):
     b = Batch(grids, device=0)
     psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=cdt, device="cuda:0")
     field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=rdt, device="cuda:0")
-    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    ramps = [ramp_of(w) for w in ws]
     return grids, b, psi, field, ramps
 
 

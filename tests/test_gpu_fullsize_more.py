@@ -23,7 +23,7 @@ from oracle import operator as op, realtime as rt
 from oracle.potential import RFRamp
 from workloads import configs, site_linear_index
 
-from gpu_cases import Case, parity_err, rel_l2
+from gpu_cases import Case, device_ramp, parity_err, rel_l2, ramp_of
 
 pytestmark = pytest.mark.gpu
 R_PATCH = 6
@@ -151,7 +151,7 @@ def test_c4_batch_equals_single_grids_and_oracle():
     b = Batch(grids, device=0)
     psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=torch.complex64, device="cuda:0")
     field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=torch.float32, device="cuda:0")
-    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    ramps = [ramp_of(w) for w in ws]
     steps = 20
     b.real_time(psi, field, ramps, [w.g for w in ws], [w.dt for w in ws], steps, use_graph=True, observe=False)
     out = psi.cpu().numpy()
@@ -189,7 +189,7 @@ def test_c4_batched_forward_adjoint_equals_single_grids():
     psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=torch.complex64, device="cuda:0")
     target = torch.tensor(np.concatenate(tg), dtype=torch.complex64, device="cuda:0")
     field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=torch.float32, device="cuda:0")
-    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    ramps = [ramp_of(w) for w in ws]
     steps = 60
     loss, grads = b.fidelity_grad(psi, target, field, ramps, [w.g for w in ws], [w.dt for w in ws], steps,
                                   use_graph=True)
@@ -199,7 +199,7 @@ def test_c4_batched_forward_adjoint_equals_single_grids():
         U = torch.tensor(w.field, dtype=torch.float32, device="cuda:0")
         p0 = torch.tensor(w.psi0, dtype=torch.complex64, device="cuda:0")
         t0 = torch.tensor(tg[i], dtype=torch.complex64, device="cuda:0")
-        l1, g1 = grids[i].fidelity_grad(p0, t0, Potential.rf(U, w.omega, w.knot_t, w.knot_delta), w.g, w.dt, steps)
+        l1, g1 = grids[i].fidelity_grad(p0, t0, device_ramp(w, U), w.g, w.dt, steps)
         assert abs(loss[i] - l1) <= 1e-6, i
         assert np.max(np.abs(grads[i] - g1)) <= 1e-5 * np.max(np.abs(g1)), i
 

@@ -14,7 +14,7 @@ from oracle import realtime as rt
 from oracle import tableau
 from workloads import configs
 
-from gpu_cases import Case, parity_err, rel_l2
+from gpu_cases import Case, parity_err, rel_l2, ramp_of
 
 pytestmark = pytest.mark.gpu
 
@@ -111,7 +111,7 @@ def test_batch_integrator_matches_single(integrator, use_graph):
     b = Batch(grids, device=0)
     psi = torch.tensor(np.concatenate([w.psi0 for w in ws]), dtype=torch.complex128, device="cuda:0")
     field = torch.tensor(np.concatenate([w.field for w in ws]), dtype=torch.float64, device="cuda:0")
-    ramps = [(w.omega, w.knot_t, w.knot_delta) for w in ws]
+    ramps = [ramp_of(w) for w in ws]
     dts = [1e-3, 7e-4, 1.3e-3]
     b.real_time(psi, field, ramps, [w.g for w in ws], dts, 6, use_graph=use_graph, integrator=integrator,
                 observe=False)

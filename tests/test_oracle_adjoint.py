@@ -3,7 +3,7 @@ import numpy as np
 
 from oracle import operator as op
 from oracle import adjoint as adj, realtime as rt
-from oracle.potential import RFRamp, hat_weights
+from oracle.potential import RFRamp, ShellRamp, hat_weights
 from workloads import configs, site_linear_index
 
 
@@ -73,3 +73,45 @@ def test_checkpoint_interval_does_not_change_result():
         assert loss == outs[0][0]
         assert np.array_equal(grad, outs[0][1])
         assert np.array_equal(y, outs[0][2])
+
+
+def _shell_problem(steps=10, n=12):
+    w = configs.c4_instance(3, n_lo=n, n_hi=n, steps=steps)
+    w.g = 40.0
+    lin = site_linear_index(w.box, w.runs)
+    T = op.kinetic_direct(w.box.n, w.box.h, lin)
+    ramp = ShellRamp(w.field, w.omega, w.knot_t, w.knot_delta)
+    rng = np.random.default_rng(78)
+    tgt = w.psi0 * np.exp(1j * rng.uniform(0, 0.3, w.psi0.size)) + 0.05 * rng.standard_normal(w.psi0.size)
+    tgt = tgt / np.sqrt(np.sum(np.abs(tgt) ** 2) * w.box.dV)
+    return w, T, ramp, tgt
+
+
+def test_shell_ramp_potential_and_radius_derivative():
+    """V = lambda/2 (r - R0(t))^2 with R0(t) the knot interpolant, and dV/dR0
+    equal to a central difference of V in the radius."""
+    w, _, ramp, _ = _shell_problem()
+    t = 0.37 * w.knot_t[-1]
+    R0 = np.interp(t, w.knot_t, w.knot_delta)
+    assert np.allclose(ramp(t), 0.5 * w.omega * (w.field - R0) ** 2, rtol=1e-15, atol=0)
+    eps = 1e-6
+    up = ShellRamp(w.field, w.omega, w.knot_t, w.knot_delta + eps)(t)
+    dn = ShellRamp(w.field, w.omega, w.knot_t, w.knot_delta - eps)(t)
+    assert np.max(np.abs((up - dn) / (2 * eps) - ramp.dV_ddelta(t))) <= 1e-6 * np.max(np.abs(ramp.dV_ddelta(t)))
+
+
+def test_shell_ramp_gradient_matches_central_differences():
+    """The same discrete adjoint with the radius of a harmonic shell as the
+    ramped parameter."""
+    w, T, ramp, tgt = _shell_problem()
+    loss, grad, _ = adj.fidelity_grad(T, ramp, w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV)
+    assert 0.0 < loss < 1.0
+    h = 1e-5
+    fd = np.zeros(ramp.knot_t.size)
+    for k in range(ramp.knot_t.size):
+        kp = ramp.knot_delta.copy(); kp[k] += h
+        km = ramp.knot_delta.copy(); km[k] -= h
+        lp, _ = adj.fidelity_loss(T, ramp.with_knots(kp), w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV)
+        lm, _ = adj.fidelity_loss(T, ramp.with_knots(km), w.g, w.dt, 0.0, w.steps, w.psi0, tgt, w.box.dV)
+        fd[k] = (lp - lm) / (2 * h)
+    assert np.max(np.abs(fd - grad)) <= 1e-6 * np.max(np.abs(grad))

@@ -5,7 +5,8 @@ that defines its potential, and a seeded initial state.  The paper measures
 on ab initio atom-chip RF-dressed potentials (Sec. V); those are not
 available, so analytic shells of the same shape class stand in for them:
 
-* a radial harmonic shell V = lambda/2 (r - R0)^2, and
+* a radial harmonic shell V = lambda/2 (r - R0)^2 (its radius R0 ramped in
+  time for the batched sweep), and
 * the RF-dressed form of eq. (10) written as V = sqrt((U - Delta)^2 + Omega^2)
   with a bare trap U = kappa/2 (x^2 + y^2 + 4 z^2).
 
@@ -30,8 +31,8 @@ class Workload:
     name: str
     box: Box
     runs: np.ndarray                 # (nruns, 4) int64: i, j, k0, k1
-    field: np.ndarray                # per-site float64: V (static) or U (RF form)
-    kind: str                        # "static" or "rf"
+    field: np.ndarray                # per-site float64: V (static), U (RF form) or r (shell ramp)
+    kind: str                        # "static", "rf" or "shell"
     omega: float = 0.0
     knot_t: Optional[np.ndarray] = None
     knot_delta: Optional[np.ndarray] = None
@@ -135,29 +136,36 @@ def c3(box_n: int = 256, half_width: float = 12.8, steps: int = 2000, seed: int 
                     knot_t=kt, knot_delta=kd, g=1000.0, dt=dt, steps=steps, psi0=psi)
 
 
-# C4: 64 instances, cubic side n ~ U{96..192}, h = 0.1, per-instance seeded
-#     RF shells (kappa scaled with the box, Omega, Delta ramp), g ~ U[100, 3000].
+# C4: 64 instances, cubic side n ~ U{96..192}, h = 0.1, rng(1000 + i):
+#     harmonic shells V = lambda/2 (r - R0(t))^2 with lambda ~ U[20, 60] and the
+#     radius R0 ramped linearly from 0.3 L to 0.6 L over 8 knots (field = r,
+#     knot values = R0); the mask is the union over the ramp of V < 20, i.e.
+#     r within sqrt(40 / lambda) of [0.3 L, 0.6 L]; g ~ U[100, 3000]; dt = 1e-3.
+#     Start: the radial oscillator ground state of the first shell plus 1e-3
+#     complex noise, normalised.
 def c4_instance(i: int, n_lo: int = 96, n_hi: int = 192, h: float = 0.1, steps: int = 1000) -> Workload:
     rng = np.random.default_rng(1000 + i)
     n = int(rng.integers(n_lo, n_hi + 1))
     L = 0.5 * n * h
-    kappa = float(rng.uniform(0.8, 1.2)) * (8.0 / L) ** 2
-    omega = float(rng.uniform(1.5, 3.0))
-    d0 = float(rng.uniform(-10.0, -5.0))
-    d1 = 0.5 * kappa * (0.5 * L) ** 2 * float(rng.uniform(0.9, 1.1))
+    lam = float(rng.uniform(20.0, 60.0))
     g = float(rng.uniform(100.0, 3000.0))
-    cut = omega + 12.0
+    r0, r1 = 0.3 * L, 0.6 * L
+    wd = np.sqrt(2.0 * 20.0 / lam)
     box = Box.centred(n, L)
-    lo, _ = rf_window(d0, omega, cut)
-    _, hi = rf_window(d1, omega, cut)
-    runs = _rf_runs(box, kappa, lo, hi)
-    U = _rf_U(box, runs, kappa)
+
+    def active(x, y, z):
+        r = np.sqrt(x * x + y * y + z * z)
+        return (r > r0 - wd) & (r < r1 + wd)
+
+    runs = runs_from_predicate(box, active)
+    x, y, z = site_coords(box, runs)
+    r = np.sqrt(x * x + y * y + z * z)
+    psi = np.exp(-np.sqrt(lam) * (r - r0) ** 2 / 2.0) + complex_noise(rng, r.size, 1e-3)
+    psi = normalise_input(psi, box.dV)
     dt = 1e-3
     T = dt * steps
-    V0 = np.sqrt((U - d0) ** 2 + omega ** 2)
-    psi = tf_trial(V0, np.min(V0) + 8.0, g, box.dV, rng, 1e-3)
-    return Workload(f"C4 instance {i} n={n}", box, runs, U, "rf", omega=omega,
-                    knot_t=np.linspace(0.0, T, 8), knot_delta=np.linspace(d0, d1, 8),
+    return Workload(f"C4 instance {i} n={n}", box, runs, r, "shell", omega=lam,
+                    knot_t=np.linspace(0.0, T, 8), knot_delta=np.linspace(r0, r1, 8),
                     g=g, dt=dt, steps=steps, psi0=psi)
 
 
