@@ -179,6 +179,28 @@ __device__ __forceinline__ R dpot_ddelta(int kind, R u, R delta, R c) {
   return R(0);
 }
 
+// x / 3 with the constant split into a rounded part and its exact residual
+// (1 - 3 t_hi, an exact FMA, divided by 3): x t_hi + x t_lo is rounded once,
+// so the stage combinations of App. A, whose coefficients of the stage states
+// sum to one, carry no systematic factor 1 + (3 t_hi - 1) per step (in FP32
+// t_hi = 0.33333334 is 3e-8 too large, which turned into a steady norm
+// growth of 6e-8 per RK4 step).
+template <typename R>
+__device__ __forceinline__ R div3(R x) {
+  const R hi = R(1) / R(3);
+  const R lo = fma(R(-3), hi, R(1)) / R(3);
+  return fma(x, hi, x * lo);
+}
+
+// c x for a coefficient c given in FP64: in FP32 the coefficient is split
+// into its rounding and the remainder, so the product is rounded once
+template <typename R>
+__device__ __forceinline__ R mulc(double c, R x) {
+  const R hi = (R)c;
+  const R lo = (R)(c - (double)hi);
+  return fma(x, hi, x * lo);
+}
+
 // Sum NR doubles over the workgroup; thread 0 gets the result.
 template <int BLOCK, int NR>
 __device__ __forceinline__ void block_sum(double (&v)[NR], double (*red)[NR]) {
@@ -418,8 +440,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
       for (int j = 0; j < RKG_MAX_HIST; ++j) {
         if (j < a.nh) {
           const C v = at1(a.h[j], sc);
-          hr += (R)a.hc[j] * v.x;
-          hi += (R)a.hc[j] * v.y;
+          hr += mulc<R>(a.hc[j], v.x);
+          hi += mulc<R>(a.hc[j], v.y);
         }
       }
       rhist[m] = cmk<R>(hr, hi);
@@ -468,14 +490,17 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   int js[SPT], tym[SPT], typ[SPT];
   S xm[SPT], xp[SPT], ym[SPT], yp[SPT];
   R wxm[SPT], wxp[SPT], wym[SPT], wyp[SPT];
-  // HOC: value, LDS slot (-1: loaded from global) and weight of every tap
+  // HOC: value and LDS slot (-1: loaded from global) of every tap, and a
+  // bit per tap for its presence (the weight is its class's, uniform over the
+  // workgroup, so no per-tap weight is kept in registers)
   constexpr int NT16 = STN == 27 ? C27_TAPS : (STN == 19 ? HOC_TAPS : 1);
   S hv[SPT][NT16];
   int hs[SPT][NT16];
-  R hw[SPT][NT16];
+  unsigned hmask[SPT];
+  // tap weights by class: faces x, y; xz, yz, xy edges; corners
+  const R cls[6] = {(R)ip.qx, (R)ip.qy, (R)ip.qxz, (R)ip.qyz, (R)ip.qxy, (R)ip.qc};
+  auto tap_class = [](int t) { return t < 2 ? 0 : (t < 4 ? 1 : (t < 8 ? 2 : (t < 12 ? 3 : (t < 16 ? 4 : 5)))); };
   if constexpr (HOC) {
-    // tap weights by class: faces x, y; xz, yz, xy edges; corners
-    const R cls[6] = {(R)ip.qx, (R)ip.qy, (R)ip.qxz, (R)ip.qyz, (R)ip.qxy, (R)ip.qc};
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       const int s = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
@@ -485,6 +510,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         if (cand < nseg && sh[cand].start <= s) j = cand;
       }
       js[m] = j;
+      unsigned mask = 0u;
 #pragma unroll
       for (int t = 0; t < NT16; ++t) {
         const int o = snb[j].off[t];
@@ -495,10 +521,10 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         const bool lds = ((ytap_mask >> t) & 1) && win >= 0 && win < ch.count + 2;
         hs[m][t] = lds ? win : -1;
         hv[m][t] = zero;
-        if (!lds) hv[m][t] = load(s + o);
-        const int c = t < 2 ? 0 : (t < 4 ? 1 : (t < 8 ? 2 : (t < 12 ? 3 : (t < 16 ? 4 : 5))));
-        hw[m][t] = o ? cls[c] : R(0);
+        if (!lds && o != 0) hv[m][t] = load(s + o);
+        mask |= (o != 0 ? 1u : 0u) << t;
       }
+      hmask[m] = mask;
     }
   } else {
 #pragma unroll
@@ -564,11 +590,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 #pragma unroll
         for (int t = 0; t < NT16; ++t) {
           if (hs[m][t] >= 0) hv[m][t] = sy[hs[m][t]];
+          const R wt = ((hmask[m] >> t) & 1u) ? cls[tap_class(t)] : R(0);
           if constexpr (REAL) {
-            latr += hw[m][t] * hv[m][t];
+            latr += wt * hv[m][t];
           } else {
-            latr += hw[m][t] * hv[m][t].x;
-            lati += hw[m][t] * hv[m][t].y;
+            latr += wt * hv[m][t].x;
+            lati += wt * hv[m][t].y;
           }
         }
       } else {
@@ -642,28 +669,29 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         } else if constexpr (OP == OP_RK2F) {
           const C y0 = ra[m];
           const R y3r = y0.x + R(0.5) * dt * fr, y3i = y0.y + R(0.5) * dt * fi;
-          const R third = R(1) / R(3);
           put(a.out, s, cmk<R>(y3r, y3i));
-          put(a.out2, s, cmk<R>(third * (yc.x - y0.x) + R(2) * third * y3r, third * (yc.y - y0.y) + R(2) * third * y3i));
+          put(a.out2, s, cmk<R>(div3<R>((yc.x - y0.x) + R(2) * y3r), div3<R>((yc.y - y0.y) + R(2) * y3i)));
         } else if constexpr (OP == OP_RK4F) {
           const C A = ra[m];
-          const R third = R(1) / R(3), c6 = dt / R(6);
-          put(a.out, s, cmk<R>(A.x + third * yc.x + c6 * fr, A.y + third * yc.y + c6 * fi));
+          const R c6 = dt / R(6);
+          put(a.out, s, cmk<R>(A.x + div3<R>(yc.x) + c6 * fr, A.y + div3<R>(yc.y) + c6 * fi));
         } else if constexpr (OP == OP_RKG) {
-          const R cc = (R)a.ccur, cdt = (R)a.cdt * dt;
-          put(a.out, s, cmk<R>(rhist[m].x + cc * yc.x + cdt * fr, rhist[m].y + cc * yc.y + cdt * fi));
+          const R cdt = (R)a.cdt * dt;
+          put(a.out, s, cmk<R>(rhist[m].x + mulc<R>(a.ccur, yc.x) + cdt * fr,
+                               rhist[m].y + mulc<R>(a.ccur, yc.y) + cdt * fi));
         } else {
           const C y0 = ra[m], y2 = rb[m], y3 = rc[m];
-          const R third = R(1) / R(3), c6 = dt / R(6);
-          const R orr = third * (y2.x - y0.x + yc.x) + R(2) * third * y3.x + c6 * fr;
-          const R oi = third * (y2.y - y0.y + yc.y) + R(2) * third * y3.y + c6 * fi;
+          const R c6 = dt / R(6);
+          const R orr = div3<R>((y2.x - y0.x) + yc.x + R(2) * y3.x) + c6 * fr;
+          const R oi = div3<R>((y2.y - y0.y) + yc.y + R(2) * y3.y) + c6 * fi;
           put(a.out, s, cmk<R>(orr, oi));
         }
       } else if constexpr (ADJ) {
         // u = f X, T u = f T X  (stage 4: X = lambda, f = b_4 = 1/6)
-        const R fx = (OP == OP_ADJ4) ? R(1) / R(6) : R(1);
-        const R ur = fx * yc.x, ui = fx * yc.y;
-        const R tur = fx * lr, tui = fx * li;
+        const R ur = (OP == OP_ADJ4) ? R(0.5) * div3<R>(yc.x) : yc.x;
+        const R ui = (OP == OP_ADJ4) ? R(0.5) * div3<R>(yc.y) : yc.y;
+        const R tur = (OP == OP_ADJ4) ? R(0.5) * div3<R>(lr) : lr;
+        const R tui = (OP == OP_ADJ4) ? R(0.5) * div3<R>(li) : li;
         const C Y = ra[m];
         const R u0 = rf[m];
         const R V = potential<R>(kind, u0, R(0), delta, omega2);
@@ -679,14 +707,14 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         acc[0] += (double)dVd * ((double)ur * (double)Y.y - (double)ui * (double)Y.x);
         if constexpr (OP == OP_ADJ4) {
           // lambda = X;  u_3 = lambda/3 + theta_4;  running lambda = lambda + theta_4
-          const R third = R(1) / R(3);
-          put(a.out, s, cmk<R>(third * yc.x + thr, third * yc.y + thi));
+          put(a.out, s, cmk<R>(div3<R>(yc.x) + thr, div3<R>(yc.y) + thi));
           put(a.out2, s, cmk<R>(yc.x + thr, yc.y + thi));
         } else if constexpr (OP == OP_ADJ3 || OP == OP_ADJ2) {
           const C lam = rb[m];
           const C lacc = rl[m];
-          const R bl = (OP == OP_ADJ3) ? R(1) / R(3) : R(1) / R(6);
-          put(a.out, s, cmk<R>(bl * lam.x + R(0.5) * thr, bl * lam.y + R(0.5) * thi));
+          // b_3 = 1/3, b_2 = 1/6
+          const R bf = (OP == OP_ADJ3) ? R(1) : R(0.5);
+          put(a.out, s, cmk<R>(bf * div3<R>(lam.x) + R(0.5) * thr, bf * div3<R>(lam.y) + R(0.5) * thi));
           put(a.out2, s, cmk<R>(lacc.x + thr, lacc.y + thi));
         } else {
           const C lacc = rl[m];

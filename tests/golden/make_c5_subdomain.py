@@ -13,8 +13,8 @@ steps of dt = 5e-5 and records
 in `c5_subdomain_s<scale>.npz` beside this script.
 
 Usage: OMP_NUM_THREADS=1 python tests/golden/make_c5_subdomain.py [scale]
-(scale 8: 931,864 sites, about 25 minutes on one core; scale 4: 3,732,680
-sites, about 1.7 hours).
+(scale 8: 931,864 sites, about 80 minutes on one core; scale 4: 3,732,680
+sites, about 5 hours).
 """
 from __future__ import annotations
 

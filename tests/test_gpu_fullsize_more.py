@@ -251,11 +251,12 @@ def test_c5_full_horizon_against_the_oracle_on_the_downscaled_shell():
     axis (931,864 sites, the same thickness in grid units), against the FP64
     oracle's stored run (tests/golden/make_c5_subdomain.py): sampled sites
     after 20, 200, 2,000 and 20,000 steps, and the norm and energy at the end.
-    complex128 stays at the FP64 bound throughout.  complex64 meets the
-    short-run 1e-5 bound after 20 steps; over the horizon its error is a
-    global phase (the state turns at the rate mu and FP32 rounds the phase
-    increment), so the phase-aligned error is held to 1e-5 and the raw one to
-    the bound stated below."""
+    complex128 stays at the FP64 bound and complex64 at the FP32 bound 1e-5
+    over the whole horizon (measured 1.5e-14 and 7.6e-6 after 20,000 steps;
+    complex64 phase-aligned 2.7e-11, norm 4e-9 and energy 4e-8 from the
+    oracle's).  The App. A combinations divide the stage states by 3 with a
+    compensated constant: with 1/3 rounded to FP32 the complex64 norm grew
+    by 6e-8 per step (7.4e-4 over the horizon) and the state was 7e-3 off."""
     import os
     import torch
     from paper_2603_05447_amd import Grid, Potential
@@ -287,9 +288,9 @@ def test_c5_full_horizon_against_the_oracle_on_the_downscaled_shell():
             if dtype == "c128":
                 assert err <= 1e-10, stop
             else:
-                assert aligned <= 1e-5, stop
-                assert err <= (1e-5 if stop <= 20 else 2e-2), stop
-        tol_obs = 1e-10 if dtype == "c128" else 1e-5
+                assert err <= 1e-5, stop
+                assert aligned <= 1e-9, stop
+        tol_obs = 1e-10 if dtype == "c128" else 1e-7
         print(f"  oracle norm {o_end[0]:.12f} energy {o_end[1]:.10f}", flush=True)
         assert abs(obs["norm"] - o_end[0]) <= tol_obs * o_end[0]
         assert abs(obs["energy"] - o_end[1]) <= tol_obs * abs(o_end[1])
