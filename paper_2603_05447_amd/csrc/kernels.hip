@@ -490,13 +490,14 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   int js[SPT], tym[SPT], typ[SPT];
   S xm[SPT], xp[SPT], ym[SPT], yp[SPT];
   R wxm[SPT], wxp[SPT], wym[SPT], wyp[SPT];
-  // HOC: value and LDS slot (-1: loaded from global) of every tap, and a
-  // bit per tap for its presence (the weight is its class's, uniform over the
-  // workgroup, so no per-tap weight is kept in registers)
+  // HOC: value, LDS slot (-1: loaded from global) and weight of every tap.
+  // An absent tap (offset 0) gets weight 0 and still loads the site itself:
+  // the unconditional load is faster than a per-lane skip, whose divergent
+  // loads cost more than the bytes they save
   constexpr int NT16 = STN == 27 ? C27_TAPS : (STN == 19 ? HOC_TAPS : 1);
   S hv[SPT][NT16];
   int hs[SPT][NT16];
-  unsigned hmask[SPT];
+  R hw[SPT][NT16];
   // tap weights by class: faces x, y; xz, yz, xy edges; corners
   const R cls[6] = {(R)ip.qx, (R)ip.qy, (R)ip.qxz, (R)ip.qyz, (R)ip.qxy, (R)ip.qc};
   auto tap_class = [](int t) { return t < 2 ? 0 : (t < 4 ? 1 : (t < 8 ? 2 : (t < 12 ? 3 : (t < 16 ? 4 : 5)))); };
@@ -510,7 +511,6 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         if (cand < nseg && sh[cand].start <= s) j = cand;
       }
       js[m] = j;
-      unsigned mask = 0u;
 #pragma unroll
       for (int t = 0; t < NT16; ++t) {
         const int o = snb[j].off[t];
@@ -521,10 +521,9 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
         const bool lds = ((ytap_mask >> t) & 1) && win >= 0 && win < ch.count + 2;
         hs[m][t] = lds ? win : -1;
         hv[m][t] = zero;
-        if (!lds && o != 0) hv[m][t] = load(s + o);
-        mask |= (o != 0 ? 1u : 0u) << t;
+        if (!lds) hv[m][t] = load(s + o);
+        hw[m][t] = o ? cls[tap_class(t)] : R(0);
       }
-      hmask[m] = mask;
     }
   } else {
 #pragma unroll
@@ -590,7 +589,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 #pragma unroll
         for (int t = 0; t < NT16; ++t) {
           if (hs[m][t] >= 0) hv[m][t] = sy[hs[m][t]];
-          const R wt = ((hmask[m] >> t) & 1u) ? cls[tap_class(t)] : R(0);
+          const R wt = hw[m][t];
           if constexpr (REAL) {
             latr += wt * hv[m][t];
           } else {
@@ -1231,11 +1230,10 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_finalize(const Plan pl, int kind,
   acc[0] = range ? 1e300 : 0.0;
   acc[1] = range ? -1e300 : 0.0;
   acc[2] = acc[3] = 0.0;
-  // component-major partials: each pass of the loop is a coalesced read; 32
-  // independent loads are issued before they are added in a fixed order (one
-  // pass covers the 31k chunks of the headline grid, so the latency of a
-  // single round trip is paid once)
-  constexpr int U = 32;
+  // component-major partials: each pass of the loop is a coalesced read; 8
+  // independent loads are issued before they are added in a fixed order
+  // (with 32 the 1024-lane block runs out of registers and spills)
+  constexpr int U = 8;
   for (int base = c0; base < c1; base += FIN_BLOCK * U) {
     for (int r = 0; r < nr; ++r) {
       double v[U];
