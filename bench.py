@@ -294,11 +294,15 @@ def bench_c2(args, dev, dtype, report):
     scheme = config_describe(g.get_config())["rk_scheme"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with KernelTimer() as kt:
-        ms_itp, ms_rt = run_phase_timed(g, psi, pot_itp, pot_rt, w, args.steps, 2 * args.steps, phase_cfg)
-        kern = kt.read()
+    ms_itp, ms_rt = run_phase_timed(g, psi, pot_itp, pot_rt, w, args.steps, 2 * args.steps, phase_cfg)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # kernel durations: the same K steps again with a HIP event pair around
+    # every launch on the launch stream (kept out of the timed region above:
+    # the event pairs serialise the launches and add about 5 % to a step)
+    with KernelTimer() as kt:
+        ms_itp_k, ms_rt_k = run_phase_timed(g, psi, pot_itp, pot_rt, w, args.steps, 2 * args.steps, phase_cfg)
+        kern = kt.read()
     total_ms = ms_itp + ms_rt
     # untimed check: the state is still normalised / finite
     obs = g.observe(psi, pot_rt, 0.0, w.g)
@@ -320,6 +324,9 @@ def bench_c2(args, dev, dtype, report):
         "autotune": tune,
         "step_roofline": {"itp": step_roofline(n, ms_itp / args.steps, "itp", dtype),
                           "rk4": step_roofline(n, ms_rt / (2 * args.steps), "rk4", dtype)},
+        "kernel_timing": {"note": "per-launch durations from a second pass of the same steps with an event "
+                                  "pair around every launch; that pass's step times:",
+                          "itp_ms_per_step": ms_itp_k / args.steps, "rk4_ms_per_step": ms_rt_k / (2 * args.steps)},
     }
     res["kernels"] = kernel_table(kern, R, scheme, n)
     report[dtype] = res

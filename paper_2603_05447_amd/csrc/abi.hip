@@ -150,6 +150,7 @@ struct ChunkSet {
   int n_chunks = 0;
   int max_seg = 1;
   Chunk* d_chunks = nullptr;
+  GroupSegs* d_groups = nullptr;       // capacity / 64 per chunk
   int32_t* d_order = nullptr;          // workgroup -> chunk for order mode 4 (built on first use)
   std::vector<int> inst_begin, inst_count;
   std::vector<int32_t> site_begin;     // host copy of each chunk's first site
@@ -211,6 +212,7 @@ struct Problem {
     graphs.clear();
     for (auto& kv : chunksets) {
       (void)hipFree(kv.second.d_chunks);
+      (void)hipFree(kv.second.d_groups);
       (void)hipFree(kv.second.d_order);
     }
     chunksets.clear();
@@ -423,12 +425,43 @@ struct Problem {
     }
     cs.n_chunks = (int)tab.size();
     if ((int64_t)cs.n_chunks > max_chunks) return fail(GPE_ERR_STATE, "internal: chunk count exceeds scratch");
+    if (capacity % 64 != 0) return fail(GPE_ERR_STATE, "internal: chunk capacity is not a multiple of 64");
+    // segment starts of every 64-site group of every chunk
+    const int G = capacity / 64;
+    std::vector<GroupSegs> groups((size_t)cs.n_chunks * G);
+    for (size_t c = 0; c < tab.size(); ++c) {
+      const Chunk& ch = tab[c];
+      GroupSegs* gs = &groups[c * G];
+      for (int q = 0; q < G; ++q) gs[q] = GroupSegs{0ull, ch.seg_count - 1, 0};
+      int k = 0;   // chunk-relative segment holding the current group's first site
+      for (int q = 0; q < G && 64 * q < ch.count; ++q) {
+        const int64_t b = (int64_t)ch.site_begin + 64 * q;
+        const int64_t e = std::min<int64_t>(b + 64, (int64_t)ch.site_begin + ch.count);
+        while (k + 1 < ch.seg_count && heads[ch.seg_begin + k + 1].start <= b) ++k;
+        gs[q].first = k;
+        for (int j = k; j < ch.seg_count; ++j) {
+          const int64_t st = heads[ch.seg_begin + j].start;
+          if (st >= e) break;
+          if (st >= b) gs[q].starts |= 1ull << (st - b);
+        }
+      }
+    }
     DeviceGuard g(device);
     if (dalloc(&cs.d_chunks, tab.size()) != hipSuccess) return fail(GPE_ERR_ALLOC, "chunk table allocation failed");
     hipError_t e = hipMemcpy(cs.d_chunks, tab.data(), sizeof(Chunk) * tab.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(cs.d_chunks);
       return hip_fail(e, "chunk table upload");
+    }
+    if (dalloc(&cs.d_groups, groups.size()) != hipSuccess) {
+      (void)hipFree(cs.d_chunks);
+      return fail(GPE_ERR_ALLOC, "chunk group table allocation failed");
+    }
+    e = hipMemcpy(cs.d_groups, groups.data(), sizeof(GroupSegs) * groups.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(cs.d_chunks);
+      (void)hipFree(cs.d_groups);
+      return hip_fail(e, "chunk group table upload");
     }
     auto res = chunksets.emplace(key, std::move(cs));
     *out = &res.first->second;
@@ -490,6 +523,7 @@ struct Problem {
     p.hocnb = d_hoc_nbs;
     p.c27nb = d_c27_nbs;
     p.chunks = cs.d_chunks;
+    p.groups = cs.d_groups;
     p.inst = d_inst;
     p.partials = d_partials;
     p.knot_acc = d_knot_acc;

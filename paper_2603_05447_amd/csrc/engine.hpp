@@ -25,6 +25,16 @@ struct Chunk {
   int32_t pad[3];
 };
 
+// Segment starts of one 64-site group of a chunk: group g holds the chunk's
+// sites 64 g .. 64 g + 63, which one wave covers in one site slot.  A lane's
+// segment is `first` plus the number of starts after the group's first site
+// up to its own, so the kernels find it with a popcount instead of a search.
+struct GroupSegs {
+  uint64_t starts;      // bit l: the group's site l begins a segment (0 past the chunk end)
+  int32_t first;        // chunk-relative segment holding the group's first site (the last one past the end)
+  int32_t pad;
+};
+
 // Per-instance constants, in device memory (read by every workgroup).
 struct InstParams {
   double g, dt, t0, dV;
@@ -76,6 +86,7 @@ struct Plan {
   int32_t hoc;            // 0: 7-point stencil; 19 / 27: heads/chunks are that stencil's segments
   const SegHoc* hocnb;    // 19-point lateral taps
   const SegC27* c27nb;    // 27-point lateral taps
+  const GroupSegs* groups;  // chunk_capacity / 64 per chunk, in chunk order
 };
 
 // Compiled launch variants (workgroup size x sites per lane, chunk capacity

@@ -390,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   //   1. segment heads / lateral offsets (small)          -> LDS
   //   2. own-site streams (y0, y2, y3, A, lambda, U, P)   -> registers
   //   3. the chunk's stencil input plus one site each side -> registers
-  //   barrier (LDS only): segment search, 4. lateral neighbour loads
+  //   barrier (LDS only): segment lookup, 4. lateral neighbour loads
   //   registers of 3 -> LDS (waits for 2 and 3 only), barrier (LDS only),
   //   arithmetic.
   constexpr int NSTG = SPT + 1;    // staging slots per lane: ceil((CH + 2) / BLOCK)
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 
-  // ---- segment search and the lateral loads of all of the lane's sites ----
+  // ---- segment lookup and the lateral loads of all of the lane's sites ----
   // An absent lateral neighbour (offset 0) stands for the site itself and
   // gets stencil weight 0, so there is no divergence on presence.  The j-1 /
   // j+1 neighbours lie a column away in compact order, usually inside the
@@ -484,8 +484,16 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // t < count + 2): those are read from LDS after the staging barrier, and
   // only the rest are loaded from global memory here.  The i-1 / i+1
   // neighbours are a plane away and always loaded.
-  const int nseg = ch.seg_count;
-  const int top = nseg > 1 ? (1 << (31 - __clz(nseg - 1))) : 0;
+  // the lane's segment in site slot m: the group table gives the segment of
+  // the wave's first site there and the segment starts after it
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const unsigned lane = threadIdx.x & 63u;
+  const uint64_t upto = (2ull << lane) - 1ull;   // bits 0 .. lane
+  const GroupSegs* gtab = pl.groups + (size_t)cidx * (size_t)(BLOCK * SPT / 64);
+  auto seg_of = [&](int m) -> int {
+    const GroupSegs gs = gtab[wave + m * (BLOCK / 64)];
+    return gs.first + __popcll(gs.starts & upto & ~1ull);
+  };
   const int wbase = ch.site_begin - 1;
   int js[SPT], tym[SPT], typ[SPT];
   S xm[SPT], xp[SPT], ym[SPT], yp[SPT];
@@ -505,11 +513,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 #pragma unroll
     for (int m = 0; m < SPT; ++m) {
       const int s = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
-      int j = 0;
-      for (int st = top; st > 0; st >>= 1) {
-        const int cand = j + st;
-        if (cand < nseg && sh[cand].start <= s) j = cand;
-      }
+      const int j = seg_of(m);
       js[m] = j;
 #pragma unroll
       for (int t = 0; t < NT16; ++t) {
@@ -529,11 +533,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 #pragma unroll
   for (int m = 0; m < SPT; ++m) {
     const int s = min(ch.site_begin + (int)threadIdx.x + m * BLOCK, last);
-    int j = 0;
-    for (int st = top; st > 0; st >>= 1) {
-      const int cand = j + st;
-      if (cand < nseg && sh[cand].start <= s) j = cand;
-    }
+    const int j = seg_of(m);
     js[m] = j;
     const SegNb nb = snb[j];
     xm[m] = load(s + nb.xm);
