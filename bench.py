@@ -767,12 +767,17 @@ def bench_c5(args, dev, report):
     n0 = float(np.sum(np.abs(w.psi0) ** 2)) * w.box.dV
     res = {}
     from paper_2603_05447_amd import KernelTimer
-    scheme = config_describe(g.get_config())["rk_scheme"]
     for dtype, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
         R = 8 if dtype == "c128" else 4
         U = torch.tensor(w.field, dtype=rdt, device=dev)
         psi = torch.tensor(w.psi0, dtype=cdt, device=dev)
         pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
+        # each precision runs the launch variant the tuner picks for it on this grid
+        scratch = psi.clone()
+        best, times = g.autotune(scratch, pot, w.g, w.dt, reps=5)
+        del scratch
+        scheme = config_describe(best)["rk_scheme"]
+        log(f"[bench] C5 {dtype} autotune: variant {best} ({config_describe(best)})")
         g.real_time(psi, pot, w.g, w.dt, 2, observe=False)
         # a short leg with per-kernel HIP-event timing on the launch stream
         with KernelTimer() as kt:
@@ -796,6 +801,8 @@ def bench_c5(args, dev, report):
                       * w.n_active * args.c5 / el / 1e9,
                       "step_roofline": step_roofline(w.n_active, ms_step, "rk4", dtype),
                       "kernels": kern,
+                      "launch_variant": best,
+                      "autotune_ms_per_step": {str(k): v for k, v in enumerate(times)},
                       "roofline": dominant_roofline(kern, f"c5_{dtype}", use_profile=g.get_config() == 0),
                       "norm_drift": obs["norm"] - n0, "energy_start": e0, "energy": obs["energy"]}
         del U, psi
