@@ -115,11 +115,11 @@ def step_roofline(n: int, ms_per_step: float, phase: str, dtype: str) -> dict:
             "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS}
 
 
-def profiled_traffic(family: str, workload: str = "c2_c128"):
-    """Calibrated HBM bytes per launch of `family` on `workload` from the
-    committed rocprofv3 summaries (profiles/*.txt, FETCH_SIZE + WRITE_SIZE
-    scaled by a copy kernel of known size), or None when no summary was taken
-    on the current kernel source."""
+def profiled_traffic(family: str, workload: str = "c2_c128", variant: int = 0):
+    """Calibrated HBM bytes per launch of `family` on `workload` under launch
+    variant `variant` from the committed rocprofv3 summaries (profiles/*.txt,
+    FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size), or None
+    when no summary was taken on the current kernel source."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2603_05447_amd", "csrc", "kernels.hip")
@@ -129,7 +129,8 @@ def profiled_traffic(family: str, workload: str = "c2_c128"):
             if not line.startswith("TRAFFIC "):
                 continue
             kv = dict(item.split("=", 1) for item in line.split()[1:])
-            if kv.get("family") == family and kv.get("sha256") == sha and kv.get("workload", "c2_c128") == workload:
+            if (kv.get("family") == family and kv.get("sha256") == sha and kv.get("workload", "c2_c128") == workload
+                    and kv.get("variant", "0") == str(variant)):
                 return int(kv["fetch_bytes"]) + int(kv["write_bytes"]), os.path.basename(f)
     return None, None
 
@@ -251,11 +252,11 @@ def kernel_table(kern: dict, R: int, scheme: int, n: int) -> dict:
     return kernels
 
 
-def dominant_roofline(kern: dict, workload: str, copy_gbps=None, use_profile: bool = True) -> dict:
+def dominant_roofline(kern: dict, workload: str, copy_gbps=None, variant=0) -> dict:
     """Roofline of the kernel family that takes the most time."""
     dom = max((f for f in kern if kern[f]["GBps"] is not None), key=lambda f: kern[f]["total_ms"])
     k = kern[dom]
-    traffic, tsrc = profiled_traffic(dom, workload) if use_profile else (None, None)
+    traffic, tsrc = profiled_traffic(dom, workload, variant) if isinstance(variant, int) else (None, None)
     r = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
          "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": traffic, "traffic_unit": "bytes/launch",
          "traffic_source": tsrc, "algo_bytes_per_launch": k["algo_bytes_per_launch"],
@@ -803,7 +804,7 @@ def bench_c5(args, dev, report):
                       "kernels": kern,
                       "launch_variant": best,
                       "autotune_ms_per_step": {str(k): v for k, v in enumerate(times)},
-                      "roofline": dominant_roofline(kern, f"c5_{dtype}", use_profile=g.get_config() == 0),
+                      "roofline": dominant_roofline(kern, f"c5_{dtype}", variant=g.get_config()),
                       "norm_drift": obs["norm"] - n0, "energy_start": e0, "energy": obs["energy"]}
         del U, psi
         g.release_work()
@@ -1018,7 +1019,7 @@ def main():
 
     main_res = report["c128"]
     kern = main_res["kernels"]
-    roofline = dominant_roofline(kern, "c2_c128", copy_gbps, use_profile=main_res["config"] == 0)
+    roofline = dominant_roofline(kern, "c2_c128", copy_gbps, variant=main_res["config"])
     line = {
         "metric": METRIC,
         "value": main_res["site_updates_per_s"],

@@ -5,7 +5,7 @@ configuration:
   the ramp against the oracle on patches; the adjoint gradient of the
   2000-step loss against central differences (h = 1e-5, every one of the 8
   knots) of the GPU forward loss (a property that holds at any size).
-* C4 (64 instances, 34.7M sites): the batched launches equal single-grid
+* C4 (64 harmonic shells, 46.2M sites): the batched launches equal single-grid
   runs of sampled instances, one instance's three RK4 steps equal the
   oracle run on the whole instance, and the batched forward + adjoint gives
   sampled instances their single-grid loss and gradient.
