@@ -1,21 +1,25 @@
 """Benchmark of the hot path on one MI355X.
 
-Headline workload (the configuration the metric is quoted on): the
-anisotropic RF-dressed bubble on a 1024 x 1024 x 512 bounding grid
-(h = 0.0612, U = (x^2 + y^2 + 4 z^2)/2, Delta = 60, Omega = 2, mask
-V < 27 -> 16,028,656 active sites, g = 2000, dt = 2e-4), complex128.  The
-job is imaginary time followed by RK4 real time in the ratio 5k : 10k, so
-one bench step is one imaginary-time step plus two RK4 steps; `value` counts
-site updates of both phases per second, inputs resident in HBM.
+Headline workload: the largest configuration, the thin anisotropic
+RF-dressed shell in a 2048 x 2048 x 1024 bounding box (h = 0.0306, kappa =
+12.9, mask V < 61 -> 59,748,872 active sites, g = 1e4, dt = 5e-5).  One bench
+step is one RK4 step of the whole shell in complex128 (FP64 throughout);
+`value` counts site updates per second over exactly --steps timed steps,
+inputs resident in HBM.  The same steps in complex64 (FP32 stencil, FP64
+reductions) and the difference between the two states are reported beside
+it, as in the precision study.
 
-Also reported: the complex64 form (FP32 stencil, FP64 reductions), the
+Also reported: the RF bubble (1024 x 1024 x 512, 16,028,656 active sites)
+in both precisions, one bench step there being one imaginary-time step plus
+two RK4 steps (the 5k : 10k ratio of its job), with the job end to end; the
 adjoint gradient rate on the 256^3 hollowing ramp (grads/s vs plain FP64
-forward runs), the 64-instance batched sweep (hipGraph; forward, and forward
-plus adjoint in complex64 against complex128), per-kernel timing
-(HIP events on the launch stream) with the roofline of the dominant kernel,
-the FP64 CPU oracle timed on a bounded sample of the same workload, the
-headline job end to end (5k imaginary-time + 10k RK4 steps, both
-precisions) and 200 steps of the 60M-site precision study.
+forward runs); the 64-instance batched sweep (hipGraph; forward, and forward
+plus adjoint in complex64 against complex128); the integrators, the
+real-state imaginary time, the staged ramp, the 19/27-point stencils, the
+tiny shell; the full 20,000-step precision study on the downscaled shell
+against the oracle's stored run; per-kernel timing (HIP events on the launch
+stream) with the roofline of the dominant kernel; and the FP64 CPU oracle
+timed on bounded samples of the workloads.
 """
 from __future__ import annotations
 
@@ -514,9 +518,39 @@ def bench_c1(args, dev, report):
 
 def cpu_baseline(args):
     """The FP64 oracle, single-threaded, on a slab of the headline workload:
-    the active sites of x-planes [448, 576) of the 1024 x 1024 x 512 grid
-    (the same shell, Dirichlet at the slab faces), one imaginary-time step
-    plus two RK4 steps per repeat."""
+    the active sites of x-planes [960, 1088) of the 2048 x 2048 x 1024 shell
+    (the same shell, Dirichlet at the slab faces), one RK4 step per repeat."""
+    from oracle import operator as op, realtime as rt
+    from oracle.potential import RFRamp
+    from workloads import site_linear_index
+    w = workload("c5")
+    runs, idx = _slab(w, 960, 1088)
+    t = time.perf_counter()
+    T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, runs))
+    t_build = time.perf_counter() - t
+    ramp = RFRamp(w.field[idx], w.omega, w.knot_t, w.knot_delta)
+    psi = w.psi0[idx]
+    reps, times = 0, []
+    t_all = time.perf_counter()
+    while True:
+        t = time.perf_counter()
+        psi = rt.rk4_step(T, psi, reps * w.dt, w.dt, ramp, w.g)
+        times.append(time.perf_counter() - t)
+        reps += 1
+        if reps >= 3 and (time.perf_counter() - t_all > args.cpu_seconds or reps >= 60):
+            break
+    med = float(np.median(times))
+    return {"value": idx.size / med, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy/SciPy oracle, single thread, on x-planes [960,1088) of the headline shell "
+                      f"({idx.size} active sites); median of {reps} repeats of 1 RK4 step "
+                      f"(operator build {t_build:.1f}s not counted)",
+            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count(), "threads": cpu_threads()}
+
+
+def cpu_c2_slab(args):
+    """The FP64 oracle, single-threaded, on x-planes [448, 576) of the RF
+    bubble (1024 x 1024 x 512): one imaginary-time step plus two RK4 steps
+    per repeat."""
     from oracle import operator as op, itp, realtime as rt
     from oracle.potential import RFRamp
     from workloads import configs, site_linear_index
@@ -540,14 +574,12 @@ def cpu_baseline(args):
         psi = rt.rk4_step(T, psi, w.dt, w.dt, ramp, w.g)
         times.append(time.perf_counter() - t)
         reps += 1
-        if reps >= 3 and (time.perf_counter() - t_all > args.cpu_seconds or reps >= 50):
+        if reps >= 3 and (time.perf_counter() - t_all > args.cpu_seconds / 2 or reps >= 50):
             break
     med = float(np.median(times))
-    return {"value": idx.size * 3 / med, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 NumPy/SciPy oracle, single thread, on x-planes [448,576) of the headline grid "
-                      f"({idx.size} active sites); median of {reps} repeats of 1 imaginary-time + 2 RK4 steps "
-                      f"(operator build {t_build:.1f}s not counted)",
-            "host_cpu": cpu_model(), "host_threads_available": os.cpu_count(), "threads": cpu_threads()}
+    return {"sample": f"x-planes [448,576) of the RF bubble ({idx.size} active sites); median of {reps} repeats "
+                      f"of 1 imaginary-time + 2 RK4 steps (operator build {t_build:.1f}s not counted)",
+            "site_updates_per_s": idx.size * 3 / med}
 
 
 def _slab(w, i_lo, i_hi):
@@ -559,16 +591,20 @@ def _slab(w, i_lo, i_hi):
     return runs, np.concatenate([np.arange(s, s + l) for s, l in zip(starts, lens)])
 
 
-def cpu_per_config(report):
+def cpu_per_config(args, report):
     """The FP64 oracle (one thread) on the other workloads, each on a bounded
     sample, beside the GPU rate of the same work where the report has it:
-    C3 loss + gradient over a 4-step prefix of the ramp on the whole grid,
-    C4 10 RK4 steps of four sampled instances, C5 two RK4 steps on the active
-    sites of x-planes [960, 1088) (Dirichlet at the slab faces)."""
+    the RF bubble on x-planes [448, 576), C3 loss + gradient over a 4-step
+    prefix of the ramp on the whole grid, C4 10 RK4 steps of four sampled
+    instances, and a 20-step prefix of the downscaled shell."""
     from oracle import operator as op, realtime as rt, adjoint as adj
     from oracle.potential import RFRamp
     from workloads import configs, site_linear_index
     out = {}
+    c2 = cpu_c2_slab(args)
+    if "c128" in report:
+        c2["gpu_site_updates_per_s_c128"] = report["c128"]["site_updates_per_s"]
+    out["c2_slab"] = c2
     # C3: forward + adjoint, 10 steps, whole grid
     w = configs.c3()
     T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, w.runs))
@@ -603,20 +639,6 @@ def cpu_per_config(report):
     if "batched_c4" in report:
         c4["gpu_site_updates_per_s_c64_batched"] = report["batched_c4"]["graph"]["site_updates_per_s"]
     out["c4_sampled"] = c4
-    # C5: slab of x-planes, two RK4 steps
-    w = workload("c5")
-    runs, idx = _slab(w, 960, 1088)
-    T = op.kinetic_direct(w.box.n, w.box.h, site_linear_index(w.box, runs))
-    ramp = RFRamp(w.field[idx], w.omega, w.knot_t, w.knot_delta)
-    psi = w.psi0[idx]
-    t = time.perf_counter()
-    rt.real_time(T, psi, ramp, w.g, w.dt, 0.0, 2)
-    el = time.perf_counter() - t
-    c5 = {"sample": f"x-planes [960, 1088) of the 2048 x 2048 x 1024 shell ({idx.size} sites), 2 RK4 steps",
-          "site_updates_per_s": idx.size * 2 / el}
-    if "precision_c5" in report:
-        c5["gpu_site_updates_per_s_c128"] = report["precision_c5"]["c128"]["site_updates_per_s"]
-    out["c5_slab"] = c5
     # C5 subdomain (the shell shrunk 8x per axis, same thickness in grid
     # units): a 20-step prefix of the 20,000-step study
     w = workload("c5_subdomain", 8)
@@ -756,56 +778,62 @@ def bench_batched(args, dev, report):
 
 
 def bench_c5(args, dev, report):
-    """Large thin shell (2048 x 2048 x 1024, ~60M active sites): RK4 in
-    complex64 (FP32 stencil, FP64 reductions) against complex128 from the
-    same start; relative L2 difference and norm drift of each."""
+    """The headline workload, the largest configuration: the thin RF-dressed
+    shell in a 2048 x 2048 x 1024 box (59,748,872 active sites).  In each
+    precision (complex128, FP64 throughout; complex64, FP32 stencil with FP64
+    reductions) from the same seeded start: the grid tuner picks the launch
+    variant, W warm-up steps run on a copy, the timed region is exactly K RK4
+    steps of the state, and a second pass of K steps with an event pair around
+    every launch gives the per-kernel durations.  Then the complex64 state is
+    compared with the complex128 one after the same K steps."""
     import torch
-    from paper_2603_05447_amd import Grid, Potential, config_describe
-    from workloads import configs
+    from paper_2603_05447_amd import Grid, Potential, KernelTimer, config_describe
     w = workload("c5")
     g = Grid.from_box(w.box, runs=w.runs, device=0)
-    out = {"workload": w.name, "n_active": w.n_active, "steps": args.c5}
+    K = args.c5 if args.c5 else args.steps
+    out = {"workload": w.name, "n_active": w.n_active, "steps": K, "warmup": args.warmup}
     n0 = float(np.sum(np.abs(w.psi0) ** 2)) * w.box.dV
     res = {}
-    from paper_2603_05447_amd import KernelTimer
     for dtype, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
         R = 8 if dtype == "c128" else 4
         U = torch.tensor(w.field, dtype=rdt, device=dev)
         psi = torch.tensor(w.psi0, dtype=cdt, device=dev)
         pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
-        # each precision runs the launch variant the tuner picks for it on this grid
+        # the launch variant the tuner picks for this precision on this grid
         scratch = psi.clone()
         best, times = g.autotune(scratch, pot, w.g, w.dt, reps=5)
-        del scratch
         scheme = config_describe(best)["rk_scheme"]
         log(f"[bench] C5 {dtype} autotune: variant {best} ({config_describe(best)})")
-        g.real_time(psi, pot, w.g, w.dt, 2, observe=False)
-        # a short leg with per-kernel HIP-event timing on the launch stream
-        with KernelTimer() as kt:
-            g.real_time(psi, pot, w.g, w.dt, 20, observe=False, check_stability=False)
-            kern = kernel_table(kt.read(), R, scheme, w.n_active)
-        psi.copy_(torch.tensor(w.psi0, dtype=cdt, device=dev))
+        g.real_time(scratch, pot, w.g, w.dt, max(args.warmup, 1), observe=False)
+        del scratch
         e0 = g.observe(psi, pot, 0.0, w.g)["energy"]
+        # timed region: exactly K steps
         torch.cuda.synchronize()
         s_ = torch.cuda.current_stream()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t = time.perf_counter()
         ev0.record(s_)
-        obs = g.real_time(psi, pot, w.g, w.dt, args.c5)
+        g.real_time(psi, pot, w.g, w.dt, K, observe=False)
         ev1.record(s_)
         torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        ms_step = ev0.elapsed_time(ev1) / args.c5
+        wall = time.perf_counter() - t
+        ms_step = ev0.elapsed_time(ev1) / K
+        obs = g.observe(psi, pot, K * w.dt, w.g)
         res[dtype] = psi.to(torch.complex128).cpu().numpy()
-        out[dtype] = {"s": el, "site_updates_per_s": w.n_active * args.c5 / el,
+        # per-kernel durations: K more steps with an event pair around every launch
+        with KernelTimer() as kt:
+            g.real_time(psi, pot, w.g, w.dt, K, t0=K * w.dt, observe=False, check_stability=False)
+            kern = kernel_table(kt.read(), R, scheme, w.n_active)
+        out[dtype] = {"ms_per_step": ms_step, "wall_s": wall, "site_updates_per_s": w.n_active / (ms_step * 1e-3),
                       "eff_GBps": sum(algo_bytes(f"rk_stage{i}", R, scheme) for i in range(1, 5))
-                      * w.n_active * args.c5 / el / 1e9,
+                      * w.n_active / (ms_step * 1e-3) / 1e9,
                       "step_roofline": step_roofline(w.n_active, ms_step, "rk4", dtype),
                       "kernels": kern,
                       "launch_variant": best,
                       "autotune_ms_per_step": {str(k): v for k, v in enumerate(times)},
                       "roofline": dominant_roofline(kern, f"c5_{dtype}", variant=g.get_config()),
                       "norm_drift": obs["norm"] - n0, "energy_start": e0, "energy": obs["energy"]}
+        log(f"[bench] C5 {dtype}: {out[dtype]['site_updates_per_s']:.4g} site-updates/s over {K} RK4 steps")
         del U, psi
         g.release_work()
         torch.cuda.empty_cache()
@@ -923,23 +951,22 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--int-steps", type=int, default=100, help="steps per integrator in the RKHE3/RK4/RKCK leg")
-    ap.add_argument("--c5", type=int, default=None,
-                    help="steps of the 60M-site FP32-vs-FP64 study (default 200, 0 with --no-extras; "
-                         "the full study is 20000)")
+    ap.add_argument("--c5", type=int, default=0,
+                    help="timed RK4 steps on the large shell, the headline workload (default: --steps; the "
+                         "full precision study is 20000)")
     ap.add_argument("--job", action=argparse.BooleanOptionalAction, default=None,
                     help="run the headline job end to end (imaginary then real time) in both precisions "
                          "(default: on, off with --no-extras)")
     ap.add_argument("--job-itp", type=int, default=5000)
     ap.add_argument("--job-rt", type=int, default=10000)
     ap.add_argument("--legs", default="all",
-                    help="comma list of legs to run (for profiling one workload): c2, c64, adjoint, batched, "
-                         "integrators, itp_real, restage, hoc, c1, c5, c5_subdomain, job; 'all' runs every leg. "
-                         "Without c2 no headline line is printed, only the legs' report")
+                    help="comma list of legs to run (for profiling one workload): c5, c2, c64, adjoint, "
+                         "batched, integrators, itp_real, restage, hoc, c1, c5_subdomain, job; 'all' runs every "
+                         "leg. Without c5 (the headline workload) no headline line is printed, only the legs' "
+                         "report")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain elementwise copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
-    if args.c5 is None:
-        args.c5 = 0 if args.no_extras else 200
     if args.job is None:
         args.job = not args.no_extras
     if args.gpus != 1:
@@ -969,15 +996,17 @@ def main():
         return legs is None or name in legs
 
     copy_gbps = None
-    if leg("c2"):
-        bench_c2(args, dev, "c128", report)
-        log(f"[bench] c128 done: {report['c128']['site_updates_per_s']:.4g} site-updates/s")
+    if leg("c5"):
+        bench_c5(args, dev, report)
         copy_gbps = achievable_copy_gbps(dev)
         log(f"[bench] streaming copy: {copy_gbps:.0f} GB/s")
+    if leg("c2"):
+        bench_c2(args, dev, "c128", report)
+        log(f"[bench] RF bubble c128 done: {report['c128']['site_updates_per_s']:.4g} site-updates/s")
     if not args.no_extras:
         if leg("c64"):
             bench_c2(args, dev, "c64", report)
-            log(f"[bench] c64 done: {report['c64']['site_updates_per_s']:.4g} site-updates/s")
+            log(f"[bench] RF bubble c64 done: {report['c64']['site_updates_per_s']:.4g} site-updates/s")
         if leg("adjoint"):
             bench_adjoint(args, dev, report)
             log(f"[bench] adjoint done: {report['adjoint_c3']['grads_per_s']:.3g} grads/s")
@@ -998,15 +1027,12 @@ def main():
             log("[bench] 19-point stencil done")
         if leg("c1"):
             bench_c1(args, dev, report)
-    if args.c5 > 0 and leg("c5"):
-        bench_c5(args, dev, report)
-        log("[bench] C5 precision study done")
-    if args.c5 > 0 and leg("c5_subdomain"):
-        bench_c5_subdomain(args, dev, report)
+        if leg("c5_subdomain"):
+            bench_c5_subdomain(args, dev, report)
     if args.job and leg("job"):
         bench_c2_job(args, dev, report)
-        log("[bench] headline job done")
-    if not leg("c2"):
+        log("[bench] RF bubble job done")
+    if not leg("c5"):
         print(json.dumps({"legs": sorted(legs), "report": report}, default=float), flush=True)
         return
     cpu = None
@@ -1014,18 +1040,22 @@ def main():
         cpu = cpu_baseline(args)
         log(f"[bench] cpu baseline: {cpu['value']:.4g} site-updates/s")
     if not args.no_cpu and not args.no_cpu_all and not args.no_extras:
-        report["cpu_oracle_per_config"] = cpu_per_config(report)
+        report["cpu_oracle_per_config"] = cpu_per_config(args, report)
         log("[bench] oracle on the other workloads done")
 
-    main_res = report["c128"]
+    c5 = report["precision_c5"]
+    main_res = c5["c128"]
     kern = main_res["kernels"]
-    roofline = dominant_roofline(kern, "c2_c128", copy_gbps, variant=main_res["config"])
+    roofline = dominant_roofline(kern, "c5_c128", copy_gbps, variant=main_res["launch_variant"])
+    roofline_steps = {f"c5_rk4_{dt}": c5[dt]["step_roofline"] for dt in ("c128", "c64")}
+    roofline_steps.update({f"c2_{ph}_{dt}": report[dt]["step_roofline"][ph]
+                           for dt in ("c128", "c64") if dt in report for ph in ("itp", "rk4")})
     line = {
         "metric": METRIC,
         "value": main_res["site_updates_per_s"],
         "unit": "site-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": c5["steps"],
         "warmup": args.warmup,
         "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True,
@@ -1033,27 +1063,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "rf-bubble 1024x1024x512 h=0.0612, Delta=60 (ITP) / 62 (RK4), Omega=2, "
-                               "mask V<27, 16,028,656 active sites, g=2000, dt=2e-4, complex128; "
-                               "one step = 1 imaginary-time step + 2 RK4 steps",
-                   "n_active": main_res["n_active"], "launch_config": main_res["config"]},
+        "config": {"workload": "large thin shell: 2048x2048x1024 box, h=0.0306, anisotropic RF-dressed shell "
+                               "(kappa=12.9), mask V<61, 59,748,872 active sites (1.39 %), g=1e4, dt=5e-5, "
+                               "complex128 (FP64 throughout); one step = 1 RK4 step; the complex64 run of the "
+                               "same steps is in precision_c5",
+                   "n_active": c5["n_active"], "launch_config": main_res["launch_variant"]},
         "roofline": roofline,
-        "roofline_steps": {f"{ph}_{dt}": report[dt]["step_roofline"][ph]
-                           for dt in ("c128", "c64") if dt in report for ph in ("itp", "rk4")},
+        "roofline_steps": roofline_steps,
         "cpu_baseline": cpu,
-        "phases": {"c128": {k2: v for k2, v in main_res.items() if k2 != "kernels"}},
-        "kernels_c128": kern,
+        "precision_c5": c5,
         "wall_s": time.time() - t_start,
     }
+    if "c128" in report:
+        line["phases_c2"] = {"c128": {k2: v for k2, v in report["c128"].items() if k2 != "kernels"}}
+        line["kernels_c2_c128"] = report["c128"]["kernels"]
+        line["roofline_c2"] = dominant_roofline(report["c128"]["kernels"], "c2_c128", copy_gbps,
+                                                variant=report["c128"]["config"])
     if "c64" in report:
-        line["phases"]["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
-        line["kernels_c64"] = report["c64"]["kernels"]
-    if "precision_c5" in report:
-        c5 = report["precision_c5"]
-        line["roofline_c5"] = {dt: {"kernel": c5[dt]["roofline"], "rk4_step": c5[dt]["step_roofline"]}
-                               for dt in ("c128", "c64") if dt in c5}
+        line.setdefault("phases_c2", {})["c64"] = {k2: v for k2, v in report["c64"].items() if k2 != "kernels"}
+        line["kernels_c2_c64"] = report["c64"]["kernels"]
     for key in ("adjoint_c3", "batched_c4", "integrators_c2", "itp_real_c2", "restage_c2", "hoc19_c2", "c1",
-                "precision_c5", "c5_subdomain", "job_c2", "cpu_oracle_per_config"):
+                "c5_subdomain", "job_c2", "cpu_oracle_per_config"):
         if key in report:
             line[key] = report[key]
     print(json.dumps(line), flush=True)
