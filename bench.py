@@ -800,10 +800,15 @@ def bench_c5(args, dev, report):
         psi = torch.tensor(w.psi0, dtype=cdt, device=dev)
         pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
         # the launch variant the tuner picks for this precision on this grid
+        # (or the one --c5-config names)
         scratch = psi.clone()
-        best, times = g.autotune(scratch, pot, w.g, w.dt, reps=5)
+        if args.c5_config is None:
+            best, times = g.autotune(scratch, pot, w.g, w.dt, reps=5)
+            log(f"[bench] C5 {dtype} autotune: variant {best} ({config_describe(best)})")
+        else:
+            best, times = args.c5_config, []
+            g.set_config(best)
         scheme = config_describe(best)["rk_scheme"]
-        log(f"[bench] C5 {dtype} autotune: variant {best} ({config_describe(best)})")
         g.real_time(scratch, pot, w.g, w.dt, max(args.warmup, 1), observe=False)
         del scratch
         e0 = g.observe(psi, pot, 0.0, w.g)["energy"]
@@ -951,6 +956,8 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--int-steps", type=int, default=100, help="steps per integrator in the RKHE3/RK4/RKCK leg")
+    ap.add_argument("--c5-config", type=int, default=None,
+                    help="launch variant for the large shell (default: the grid tuner picks one per precision)")
     ap.add_argument("--c5", type=int, default=0,
                     help="timed RK4 steps on the large shell, the headline workload (default: --steps; the "
                          "full precision study is 20000)")
