@@ -426,28 +426,13 @@ struct Problem {
     cs.n_chunks = (int)tab.size();
     if ((int64_t)cs.n_chunks > max_chunks) return fail(GPE_ERR_STATE, "internal: chunk count exceeds scratch");
     if (capacity % 64 != 0) return fail(GPE_ERR_STATE, "internal: chunk capacity is not a multiple of 64");
-    // z-run starts of every compact position (positions past the last site
-    // count as starts, so the last site of every run ends it)
-    const int64_t nbits = total + 2 * capacity + 128;
-    std::vector<uint64_t> rbeg((size_t)(nbits + 63) / 64 + 1, 0ull);
-    for (size_t k = 0; k + 1 < heads.size(); ++k)
-      if (heads[k].flags & SEG_RUN_BEGIN) rbeg[(size_t)heads[k].start >> 6] |= 1ull << (heads[k].start & 63);
-    for (int64_t p = total; p < nbits; ++p) rbeg[(size_t)p >> 6] |= 1ull << (p & 63);
-    auto run_bits = [&](int64_t p) -> uint64_t {   // bits p .. p + 63
-      const size_t w = (size_t)p >> 6;
-      const int sh = (int)(p & 63);
-      return sh ? (rbeg[w] >> sh) | (rbeg[w + 1] << (64 - sh)) : rbeg[w];
-    };
     // segment starts of every 64-site group of every chunk
     const int G = capacity / 64;
     std::vector<GroupSegs> groups((size_t)cs.n_chunks * G);
     for (size_t c = 0; c < tab.size(); ++c) {
       const Chunk& ch = tab[c];
       GroupSegs* gs = &groups[c * G];
-      for (int q = 0; q < G; ++q) {
-        const int64_t b = (int64_t)ch.site_begin + 64 * q;
-        gs[q] = GroupSegs{0ull, run_bits(b), ch.seg_count - 1, (int32_t)(run_bits(b + 64) & 1ull)};
-      }
+      for (int q = 0; q < G; ++q) gs[q] = GroupSegs{0ull, ch.seg_count - 1, 0};
       int k = 0;   // chunk-relative segment holding the current group's first site
       for (int q = 0; q < G && 64 * q < ch.count; ++q) {
         const int64_t b = (int64_t)ch.site_begin + 64 * q;

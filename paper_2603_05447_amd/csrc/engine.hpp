@@ -25,17 +25,14 @@ struct Chunk {
   int32_t pad[3];
 };
 
-// Segment starts and z-run starts of one 64-site group of a chunk: group g
-// holds the chunk's sites 64 g .. 64 g + 63, which one wave covers in one
-// site slot.  A lane's segment is `first` plus the number of segment starts
-// after the group's first site up to its own, so the kernels find it with a
-// popcount instead of a search; whether its k-1 / k+1 neighbours exist is
-// whether it and the next position begin a z-run.
+// Segment starts of one 64-site group of a chunk: group g holds the chunk's
+// sites 64 g .. 64 g + 63, which one wave covers in one site slot.  A lane's
+// segment is `first` plus the number of starts after the group's first site
+// up to its own, so the kernels find it with a popcount instead of a search.
 struct GroupSegs {
   uint64_t starts;      // bit l: the group's site l begins a segment (0 past the chunk end)
-  uint64_t run_begin;   // bit l: compact position (group start + l) begins a z-run (1 past the last site)
   int32_t first;        // chunk-relative segment holding the group's first site (the last one past the end)
-  int32_t next_begin;   // 1: the position after the group's last one begins a z-run (or is past the end)
+  int32_t pad;
 };
 
 // Per-instance constants, in device memory (read by every workgroup).

@@ -7,9 +7,8 @@
 // from HBM once per site with coalesced loads:
 //   * the chunk's own values plus one site on either side (the k-1 / k+1
 //     neighbours along the z-runs) are staged in LDS;
-//   * the lateral offsets of the segments overlapping the chunk are staged
-//     in LDS; each lane finds its segment, and whether its site begins or
-//     ends a z-run, from per-wave bit masks of the chunk table (a popcount);
+//   * the heads of the segments overlapping the chunk are staged in LDS and
+//     each lane finds its segment by a fixed-length binary search;
 //   * the four lateral neighbours (i+-1, j+-1) are read from global memory
 //     at the segment's constant offset; adjacent lanes read adjacent
 //     addresses, and those planes were (or will be) streamed as some other
@@ -302,9 +301,10 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   __shared__ double red[BLOCK / 64][NR > 0 ? NR : 1];
   const S* const Yin = reinterpret_cast<const S*>(a.Y);
   S* const Yout = reinterpret_cast<S*>(a.out);
-  // dynamic LDS: the lateral offsets of the chunk's segments (max_seg)
+  // dynamic LDS: lateral offsets (max_seg) then segment heads (max_seg + 1)
   extern __shared__ __align__(16) unsigned char dyn_lds[];
   D* snb = reinterpret_cast<D*>(dyn_lds);
+  SegHead* sh = reinterpret_cast<SegHead*>(dyn_lds + (size_t)pl.max_seg * sizeof(D));
 
   const int cidx = pl.xcd_map == 4 ? pl.order[blockIdx.x] : chunk_index((int)blockIdx.x, (int)gridDim.x, pl.xcd_map);
   const Chunk ch = pl.chunks[cidx];
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // Load schedule.  Global loads return in issue order, and the barriers
   // below wait for LDS traffic only, so the large streams stay in flight
   // while the workgroup exchanges the small segment tables:
-  //   1. segment lateral offsets (small)                 -> LDS
+  //   1. segment heads / lateral offsets (small)          -> LDS
   //   2. own-site streams (y0, y2, y3, A, lambda, U, P)   -> registers
   //   3. the chunk's stencil input plus one site each side -> registers
   //   barrier (LDS only): segment lookup, 4. lateral neighbour loads
@@ -396,6 +396,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   constexpr int NSTG = SPT + 1;    // staging slots per lane: ceil((CH + 2) / BLOCK)
   // Segment-table slots past the end re-load the last entry (same value to
   // the same LDS slot), so these loads are unconditional and issue first.
+  const SegHead* hsrc = pl.heads + ch.seg_begin;
   const D* nsrc;
   if constexpr (STN == 27) nsrc = pl.c27nb + ch.seg_begin;
   else if constexpr (STN == 19) nsrc = pl.hocnb + ch.seg_begin;
@@ -407,6 +408,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
 #pragma unroll
   for (int q = 0; q < TBL; ++q) {
     const int t = t0 + q * BLOCK;
+    sh[min(t, ch.seg_count)] = hsrc[min(t, ch.seg_count)];
     snb[min(t, ch.seg_count - 1)] = nsrc[min(t, ch.seg_count - 1)];
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -488,14 +490,8 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   const unsigned lane = threadIdx.x & 63u;
   const uint64_t upto = (2ull << lane) - 1ull;   // bits 0 .. lane
   const GroupSegs* gtab = pl.groups + (size_t)cidx * (size_t)(BLOCK * SPT / 64);
-  // zf[m]: bit 0 the site begins its z-run (no k-1 neighbour), bit 1 it ends
-  // it (no k+1 neighbour)
-  unsigned zf[SPT];
   auto seg_of = [&](int m) -> int {
     const GroupSegs gs = gtab[wave + m * (BLOCK / 64)];
-    const unsigned b = (unsigned)(gs.run_begin >> lane) & 1u;
-    const unsigned e = lane < 63u ? (unsigned)(gs.run_begin >> (lane + 1u)) & 1u : (unsigned)gs.next_begin & 1u;
-    zf[m] = b | (e << 1);
     return gs.first + __popcll(gs.starts & upto & ~1ull);
   };
   const int wbase = ch.site_begin - 1;
@@ -579,12 +575,14 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     const int l = threadIdx.x + m * BLOCK;
     if (l < ch.count) {
       const int s = ch.site_begin + l;
+      const SegHead hd = sh[js[m]];
+      const int send = sh[js[m] + 1].start;
       const S yc = STG ? sy[l + 1] : own[m];
       const S zm = STG ? sy[l] : kmv[m], zp = STG ? sy[l + 2] : kpv[m];
       // own-column k-1 / k+1 weight and the centre weight of the stencil
       const R wz = HOC ? (R)ip.qz : cz, wc = HOC ? (R)ip.qd : cd;
-      const R wzm = (zf[m] & 1u) ? R(0) : wz;
-      const R wzp = (zf[m] & 2u) ? R(0) : wz;
+      const R wzm = (s == hd.start && (hd.flags & SEG_RUN_BEGIN)) ? R(0) : wz;
+      const R wzp = (s == send - 1 && (hd.flags & SEG_RUN_END)) ? R(0) : wz;
       // sum of the weighted lateral taps (both stencils)
       R latr = R(0), lati = R(0);
       if constexpr (HOC) {
@@ -762,7 +760,7 @@ template <int BLOCK, int SPT, typename R, int OP, bool REAL>
 static hipError_t launch_pass(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   constexpr bool BOTH_NT = BLOCK >= 256 && SPT <= 4;
   constexpr bool NO_STAGE = BLOCK == 256 && (SPT == 2 || SPT == 4);
-  const size_t dyn = (size_t)p.max_seg * sizeof(SegNb);
+  const size_t dyn = (size_t)p.max_seg * sizeof(SegNb) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
   if (!p.off32) {
     hipLaunchKernelGGL((k_pass<R, 256, 2, OP, false, false, REAL, 7, true>), dim3(p.n_chunks), dim3(256), dyn, s, p,
                        a);
@@ -793,7 +791,7 @@ template <typename R, int OP, bool REAL, int STN>
 static hipError_t launch_pass_hoc(const Plan& p, const LaunchConfig& cfg, const PassArgs<R>& a, hipStream_t s) {
   using D = typename std::conditional<STN == 27, SegC27, SegHoc>::type;
   if (!p.off32 || cfg.block != 256 || cfg.spt != 1) return hipErrorInvalidValue;
-  const size_t dyn = (size_t)p.max_seg * sizeof(D);
+  const size_t dyn = (size_t)p.max_seg * sizeof(D) + (size_t)(p.max_seg + 1) * sizeof(SegHead);
   if (cfg.nt)
     hipLaunchKernelGGL((k_pass<R, 256, 1, OP, true, true, REAL, STN, true>), dim3(p.n_chunks), dim3(256), dyn, s, p,
                        a);

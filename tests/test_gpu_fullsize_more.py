@@ -295,3 +295,45 @@ def test_c5_full_horizon_against_the_oracle_on_the_downscaled_shell():
         assert abs(obs["norm"] - o_end[0]) <= tol_obs * o_end[0]
         assert abs(obs["energy"] - o_end[1]) <= tol_obs * abs(o_end[1])
         del U, psi
+
+
+@pytest.mark.gpu
+def test_every_launch_variant_agrees_on_the_downscaled_shell():
+    """Every launch variant computes the same steps on the thin downscaled
+    shell (931,864 sites, z-runs of 10.7 sites on average, about 100
+    segments per 512-site chunk), twice in a row: RK4 in complex128 and
+    complex64 and imaginary time in complex128.  Small grids have too few
+    segments per chunk to exercise the per-wave segment tables of the wide
+    shapes."""
+    import torch
+    from paper_2603_05447_amd import Grid, Potential, config_count
+    w = configs.c5_subdomain(8)
+    g = Grid.from_box(w.box, runs=w.runs, device=0)
+    for cdt, rdt, tol in ((torch.complex128, torch.float64, 1e-12), (torch.complex64, torch.float32, 1e-5)):
+        U = torch.tensor(w.field, dtype=rdt, device="cuda")
+        pot = Potential.rf(U, w.omega, w.knot_t, w.knot_delta)
+        ref = None
+        for rep in range(2):
+            for k in range(config_count()):
+                psi = torch.tensor(w.psi0, dtype=cdt, device="cuda")
+                g.set_config(k)
+                g.real_time(psi, pot, w.g, w.dt, 3, observe=False)
+                x = psi.cpu().numpy().astype(np.complex128)
+                if ref is None:
+                    ref = x
+                err = float(np.abs(x - ref).max() / np.abs(ref).max())
+                print(f"RK4 {cdt} variant {k} repeat {rep}: max |diff| / max |psi| = {err:.2e}", flush=True)
+                assert err <= tol, (str(cdt), k, rep)
+    V = torch.tensor(np.sqrt((w.field - w.knot_delta[0]) ** 2 + w.omega ** 2), dtype=torch.float64, device="cuda")
+    ref = None
+    for rep in range(2):
+        for k in range(config_count()):
+            psi = torch.tensor(w.psi0, dtype=torch.complex128, device="cuda")
+            g.set_config(k)
+            g.imag_time(psi, Potential.static(V), w.g, w.dt, 3, observe=False)
+            x = psi.cpu().numpy()
+            if ref is None:
+                ref = x
+            err = float(np.abs(x - ref).max() / np.abs(ref).max())
+            print(f"ITP variant {k} repeat {rep}: max |diff| / max |psi| = {err:.2e}", flush=True)
+            assert err <= 1e-12, ("itp", k, rep)
