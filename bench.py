@@ -341,7 +341,7 @@ def bench_c2(args, dev, dtype, report):
 
 
 def bench_integrators(args, dev, report):
-    """Real time at the headline size with each explicit integrator (Sec.
+    """Real time on the RF bubble with each explicit integrator (Sec.
     II.A): ms per step and effective bandwidth of the memory-optimised forms."""
     import torch
     from paper_2603_05447_amd import config_describe
@@ -374,7 +374,7 @@ def bench_integrators(args, dev, report):
 
 
 def bench_itp_real(args, dev, report):
-    """Imaginary time at the headline size on a real state (Sec. II.A: a
+    """Imaginary time on the RF bubble on a real state (Sec. II.A: a
     real start stays real) against the complex form of the same step."""
     import torch
     w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, "c128")
@@ -403,7 +403,7 @@ def bench_itp_real(args, dev, report):
 
 
 def bench_restage(args, dev, report):
-    """One stage of a staged ramp at the headline size (Sec. V): post-selection
+    """One stage of a staged ramp on the RF bubble (Sec. V): post-selection
     on the device from two box potentials, the carry-over of psi to the new
     grid, and real time with the potential interpolated between the stage
     arrays (two field reads per stage instead of one)."""
@@ -451,7 +451,7 @@ def bench_restage(args, dev, report):
 
 def bench_hoc(args, dev, report):
     """The 19-point HOC stencil (App. B eq. (B2)) and the cubic 27-point one
-    at the headline size: the same passes as the 7-point path with 16 / 24
+    on the RF bubble: the same passes as the 7-point path with 16 / 24
     lateral taps per site."""
     import torch
     w, g, U, psi, pot_itp, pot_rt = setup_c2(dev, "c128")
@@ -906,7 +906,7 @@ def bench_c5_subdomain(args, dev, report):
 
 
 def bench_c2_job(args, dev, report):
-    """The headline job end to end, in complex128 and complex64: the ground
+    """The RF bubble job end to end, in complex128 and complex64: the ground
     state by imaginary time at Delta = 60, then RK4 real time after the
     quench to Delta = 62 (dt = 2e-4 for both), with observables at the phase
     boundaries and the complex64 final state against the complex128 one."""
@@ -962,7 +962,7 @@ def main():
                     help="timed RK4 steps on the large shell, the headline workload (default: --steps; the "
                          "full precision study is 20000)")
     ap.add_argument("--job", action=argparse.BooleanOptionalAction, default=None,
-                    help="run the headline job end to end (imaginary then real time) in both precisions "
+                    help="run the RF bubble job end to end (imaginary then real time) in both precisions "
                          "(default: on, off with --no-extras)")
     ap.add_argument("--job-itp", type=int, default=5000)
     ap.add_argument("--job-rt", type=int, default=10000)

@@ -1,4 +1,4 @@
-"""Full-size parity on the headline workload (1024 x 1024 x 512 RF bubble,
+"""Full-size parity on the RF bubble workload (1024 x 1024 x 512,
 16,028,656 active sites) in the launch configuration the benchmark uses.
 
 The oracle cannot run the whole grid in a test, so it is evaluated on local
@@ -104,7 +104,7 @@ def test_c2_rk4_step_sampled(c2, dtype, tol):
 
 @pytest.mark.parametrize("integrator", ["rkhe3", "rkck"])
 def test_c2_rkhe3_rkck_step_sampled(c2, integrator):
-    """One step of each of the other integrators on the whole headline grid
+    """One step of each of the other integrators on the whole RF bubble grid
     (complex128) against the oracle's Butcher-form step on patches (RKCK has
     six stages, so its patches reach 7 sites)."""
     import torch
@@ -131,7 +131,7 @@ def test_c2_rkhe3_rkck_step_sampled(c2, integrator):
 
 @pytest.mark.parametrize("points", [19, 27])
 def test_c2_hoc_rk4_and_imag_time_steps_sampled(c2, points):
-    """The 19- and 27-point stencils on the whole headline grid (complex128):
+    """The 19- and 27-point stencils on the whole RF bubble grid (complex128):
     one RK4 step and one imaginary-time step against the oracle's operator of
     the same stencil on patches (the imaginary-time result up to its global
     renormalisation factor)."""

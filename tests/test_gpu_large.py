@@ -4,7 +4,7 @@ kernels compiled with 64-bit addressing.
 
 The inputs are closed-form functions of the coordinates, evaluated on the
 device for the whole box and on the host for each oracle patch (no 5.6 GB
-host arrays).  As in the headline full-size test, the oracle runs on the
+host arrays).  As in the RF bubble full-size test, the oracle runs on the
 active sites of a 13^3 patch around each sampled site (one RK4 step moves
 information 4 sites, one imaginary-time step 2); the imaginary-time result
 is compared up to its global renormalisation factor."""
