@@ -63,19 +63,26 @@ def _samples(w, ijk, count=40, seed=0):
     return sorted(set(int(x) for x in s))
 
 
-@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-5)])
-def test_c2_rk4_step_sampled(c2, dtype, tol):
+# complex128 runs the default variant in the benchmark, complex64 the one the
+# grid tuner keeps for each phase; both are checked at full size
+@pytest.mark.parametrize("dtype,tol,tuned", [("c128", 1e-10, False), ("c64", 1e-5, False), ("c64", 1e-5, True)])
+def test_c2_rk4_step_sampled(c2, dtype, tol, tuned):
     import torch
     from paper_2603_05447_amd import Grid, Potential
     w, ijk = c2
     cdt = torch.complex128 if dtype == "c128" else torch.complex64
     rdt = torch.float64 if dtype == "c128" else torch.float32
-    print(f"C2 full size RK4 sampled parity {dtype}: {w.n_active} sites", flush=True)
     g = Grid.from_box(w.box, runs=w.runs, device=0)
     U = torch.tensor(w.field, dtype=rdt, device="cuda:0")
     psi = torch.tensor(w.psi0, dtype=cdt, device="cuda:0")
     d = w.extra["delta_rt"]
     pot = Potential.rf(U, w.omega, [0.0], [d])
+    variant = 0
+    if tuned:
+        scratch = psi.clone()
+        variant, _ = g.autotune(scratch, pot, w.g, w.dt, reps=2)
+        del scratch
+    print(f"C2 full size RK4 sampled parity {dtype}, launch variant {variant}: {w.n_active} sites", flush=True)
     g.real_time(psi, pot, w.g, w.dt, 1, observe=False)
     out = psi.cpu().numpy()
     got, ref = [], []
@@ -165,8 +172,8 @@ def test_c2_hoc_rk4_and_imag_time_steps_sampled(c2, points):
     assert err_rt <= 1e-10 and scale > 0 and err_itp <= 1e-10
 
 
-@pytest.mark.parametrize("dtype,tol", [("c128", 1e-10), ("c64", 1e-5)])
-def test_c2_imag_time_step_sampled(c2, dtype, tol):
+@pytest.mark.parametrize("dtype,tol,tuned", [("c128", 1e-10, False), ("c64", 1e-5, False), ("c64", 1e-5, True)])
+def test_c2_imag_time_step_sampled(c2, dtype, tol, tuned):
     import torch
     from paper_2603_05447_amd import Grid, Potential
     w, ijk = c2
@@ -174,7 +181,14 @@ def test_c2_imag_time_step_sampled(c2, dtype, tol):
     U = torch.tensor(w.field, dtype=torch.float64 if dtype == "c128" else torch.float32, device="cuda:0")
     psi = torch.tensor(w.psi0, dtype=torch.complex128 if dtype == "c128" else torch.complex64, device="cuda:0")
     d = w.extra["delta_itp"]
-    obs = g.imag_time(psi, Potential.rf(U, w.omega, [0.0], [d]), w.g, w.dt, 1)
+    pot = Potential.rf(U, w.omega, [0.0], [d])
+    variant = 0
+    if tuned:
+        scratch = psi.clone()
+        variant, _ = g.autotune(scratch, pot, w.g, w.dt, reps=2, phase="itp")
+        del scratch
+    print(f"C2 ITP {dtype}: launch variant {variant}", flush=True)
+    obs = g.imag_time(psi, pot, w.g, w.dt, 1)
     assert abs(obs["norm"] - 1.0) < (1e-12 if dtype == "c128" else 1e-6)
     out = psi.cpu().numpy()
     got, ref = [], []
