@@ -77,7 +77,7 @@ template <bool NT, typename T> __device__ __forceinline__ void st(T* p, const T&
 // ---------------------------------------------------------------------------
 // launch variants
 // ---------------------------------------------------------------------------
-// Variant 0 is the default.  Measured on the 16M-site headline grid: the
+// Variant 0 is the default.  Measured on the 16M-site RF bubble grid: the
 // plane-eighths order (mode 4) turns the i-1 / i+1 neighbour reads into L2
 // hits and beats array order by about 3 %; the contiguous-eighths order also
 // removes those misses but is slower, and non-temporal single-use streams
@@ -387,12 +387,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // Load schedule.  Global loads return in issue order, and the barriers
   // below wait for LDS traffic only, so the large streams stay in flight
   // while the workgroup exchanges the small segment tables:
-  //   1. segment heads / lateral offsets (small)          -> LDS
+  //   1. segment heads / lateral offsets (small)          -> registers or LDS
   //   2. own-site streams (y0, y2, y3, A, lambda, U, P)   -> registers
   //   3. the chunk's stencil input plus one site each side -> registers
-  //   barrier (LDS only): segment lookup, 4. lateral neighbour loads
-  //   registers of 3 -> LDS (waits for 2 and 3 only), barrier (LDS only),
-  //   arithmetic.
+  //   registers of 1 -> LDS (waits for 1 only), barrier (LDS only): segment
+  //   lookup, 4. lateral neighbour loads, registers of 3 -> LDS (waits for 2
+  //   and 3 only), barrier (LDS only), arithmetic.
   constexpr int NSTG = SPT + 1;    // staging slots per lane: ceil((CH + 2) / BLOCK)
   // Segment-table slots past the end re-load the last entry (same value to
   // the same LDS slot), so these loads are unconditional and issue first.
@@ -405,11 +405,43 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // a chunk holds at most MAX_CHUNK_SEGS (255) segments: one slot per lane
   // covers its table for 256 lanes or more, TBL slots for fewer
   constexpr int TBL = BLOCK > MAX_CHUNK_SEGS ? 1 : (MAX_CHUNK_SEGS + BLOCK) / BLOCK;
-#pragma unroll
-  for (int q = 0; q < TBL; ++q) {
+  // The 7-point tables are held in registers and written to LDS only after
+  // the streams below are issued: loads return in issue order, so that write
+  // waits for the table loads alone while the streams stay in flight.  This
+  // pays in single precision and, in double, in the passes that read one
+  // stream besides their stencil input; the heavier double-precision passes
+  // (measured slightly slower that way) and the 19/27-point descriptors (too
+  // large to hold) write the tables to LDS at once.
+  constexpr bool LATE_TBL = STN == 7 && (sizeof(R) == 4 || OP == OP_ITP1 || OP == OP_ITP1R || OP == OP_ITP2 ||
+                                         OP == OP_RK1 || OP == OP_RK1_OBS || OP == OP_OBS);
+  static_assert(sizeof(SegHead) == sizeof(int2) && sizeof(SegNb) == sizeof(int4), "table entry sizes");
+  static_assert(TBL <= 4, "table slots per lane");
+  // named registers (not an array, which the compiler would keep in scratch
+  // memory for more than one slot)
+  int2 h0, h1, h2, h3;
+  int4 n0, n1, n2, n3;
+  auto tbl_load = [&](int q, int2& h, int4& n) {
     const int t = t0 + q * BLOCK;
-    sh[min(t, ch.seg_count)] = hsrc[min(t, ch.seg_count)];
-    snb[min(t, ch.seg_count - 1)] = nsrc[min(t, ch.seg_count - 1)];
+    h = *reinterpret_cast<const int2*>(hsrc + min(t, ch.seg_count));
+    n = *reinterpret_cast<const int4*>(nsrc + min(t, ch.seg_count - 1));
+  };
+  auto tbl_store = [&](int q, const int2& h, const int4& n) {
+    const int t = t0 + q * BLOCK;
+    *reinterpret_cast<int2*>(sh + min(t, ch.seg_count)) = h;
+    *reinterpret_cast<int4*>(snb + min(t, ch.seg_count - 1)) = n;
+  };
+  if constexpr (LATE_TBL) {
+    tbl_load(0, h0, n0);
+    if constexpr (TBL > 1) tbl_load(1, h1, n1);
+    if constexpr (TBL > 2) tbl_load(2, h2, n2);
+    if constexpr (TBL > 3) tbl_load(3, h3, n3);
+  } else {
+#pragma unroll
+    for (int q = 0; q < TBL; ++q) {
+      const int t = t0 + q * BLOCK;
+      sh[min(t, ch.seg_count)] = hsrc[min(t, ch.seg_count)];
+      snb[min(t, ch.seg_count - 1)] = nsrc[min(t, ch.seg_count - 1)];
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
 
@@ -471,6 +503,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     }
   }
   __builtin_amdgcn_sched_barrier(0);
+  if constexpr (LATE_TBL) {
+    tbl_store(0, h0, n0);
+    if constexpr (TBL > 1) tbl_store(1, h1, n1);
+    if constexpr (TBL > 2) tbl_store(2, h2, n2);
+    if constexpr (TBL > 3) tbl_store(3, h3, n3);
+  }
 
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
