@@ -405,19 +405,20 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
   // a chunk holds at most MAX_CHUNK_SEGS (255) segments: one slot per lane
   // covers its table for 256 lanes or more, TBL slots for fewer
   constexpr int TBL = BLOCK > MAX_CHUNK_SEGS ? 1 : (MAX_CHUNK_SEGS + BLOCK) / BLOCK;
-  // The 7-point tables are held in registers and written to LDS only after
-  // the streams below are issued: loads return in issue order, so that write
+  // The tables are held in registers and written to LDS only after the
+  // streams below are issued: loads return in issue order, so that write
   // waits for the table loads alone while the streams stay in flight.  This
-  // pays in single precision and, in double, in the passes that read one
-  // stream besides their stencil input; the heavier double-precision passes
-  // (measured slightly slower that way) and the 19/27-point descriptors (too
-  // large to hold) write the tables to LDS at once.
+  // pays for the 19/27-point passes (one slot per lane, their registers are
+  // free again before the lateral taps need them) and for the 7-point passes
+  // in single precision and, in double, those that read one stream besides
+  // their stencil input; the heavier double-precision 7-point passes
+  // (measured slightly slower that way) write the tables to LDS at once.
   constexpr bool LATE_TBL = STN == 7 && (sizeof(R) == 4 || OP == OP_ITP1 || OP == OP_ITP1R || OP == OP_ITP2 ||
                                          OP == OP_RK1 || OP == OP_RK1_OBS || OP == OP_OBS);
   static_assert(sizeof(SegHead) == sizeof(int2) && sizeof(SegNb) == sizeof(int4), "table entry sizes");
   static_assert(TBL <= 4, "table slots per lane");
-  // named registers (not an array, which the compiler would keep in scratch
-  // memory for more than one slot)
+  // named registers (not arrays, which the compiler would keep in scratch
+  // memory)
   int2 h0, h1, h2, h3;
   int4 n0, n1, n2, n3;
   auto tbl_load = [&](int q, int2& h, int4& n) {
@@ -430,7 +431,22 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     *reinterpret_cast<int2*>(sh + min(t, ch.seg_count)) = h;
     *reinterpret_cast<int4*>(snb + min(t, ch.seg_count - 1)) = n;
   };
-  if constexpr (LATE_TBL) {
+  // 19/27-point descriptors: HQ 16-byte pieces
+  constexpr bool LATE_HOC = STN != 7 && TBL == 1;
+  constexpr int HQ = (int)(sizeof(D) / 16);
+  static_assert(!LATE_HOC || (sizeof(D) % 16 == 0 && HQ <= 6), "descriptor size");
+  int4 q0, q1, q2, q3, q4, q5;
+  int2 hh;
+  if constexpr (LATE_HOC) {
+    const int4* src4 = reinterpret_cast<const int4*>(nsrc + min(t0, ch.seg_count - 1));
+    hh = *reinterpret_cast<const int2*>(hsrc + min(t0, ch.seg_count));
+    q0 = src4[0];
+    if constexpr (HQ > 1) q1 = src4[1];
+    if constexpr (HQ > 2) q2 = src4[2];
+    if constexpr (HQ > 3) q3 = src4[3];
+    if constexpr (HQ > 4) q4 = src4[4];
+    if constexpr (HQ > 5) q5 = src4[5];
+  } else if constexpr (LATE_TBL) {
     tbl_load(0, h0, n0);
     if constexpr (TBL > 1) tbl_load(1, h1, n1);
     if constexpr (TBL > 2) tbl_load(2, h2, n2);
@@ -503,6 +519,16 @@ __global__ __launch_bounds__(BLOCK) void k_pass(const Plan pl, const PassArgs<R>
     }
   }
   __builtin_amdgcn_sched_barrier(0);
+  if constexpr (LATE_HOC) {
+    int4* dst4 = reinterpret_cast<int4*>(snb + min(t0, ch.seg_count - 1));
+    *reinterpret_cast<int2*>(sh + min(t0, ch.seg_count)) = hh;
+    dst4[0] = q0;
+    if constexpr (HQ > 1) dst4[1] = q1;
+    if constexpr (HQ > 2) dst4[2] = q2;
+    if constexpr (HQ > 3) dst4[3] = q3;
+    if constexpr (HQ > 4) dst4[4] = q4;
+    if constexpr (HQ > 5) dst4[5] = q5;
+  }
   if constexpr (LATE_TBL) {
     tbl_store(0, h0, n0);
     if constexpr (TBL > 1) tbl_store(1, h1, n1);
