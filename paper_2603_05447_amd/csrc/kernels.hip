@@ -7,14 +7,17 @@
 // from HBM once per site with coalesced loads:
 //   * the chunk's own values plus one site on either side (the k-1 / k+1
 //     neighbours along the z-runs) are staged in LDS;
-//   * the heads of the segments overlapping the chunk are staged in LDS and
-//     each lane finds its segment by a fixed-length binary search;
-//   * the four lateral neighbours (i+-1, j+-1) are read from global memory
-//     at the segment's constant offset; adjacent lanes read adjacent
-//     addresses, and those planes were (or will be) streamed as some other
-//     chunk's centre, so they are served from L2.  Chunks are handed to
-//     workgroups so that each XCD (own L2) walks one contiguous eighth of the
-//     array, which keeps the i-1 / i+1 planes inside the same L2.
+//   * the segments overlapping the chunk (heads and lateral offsets) are
+//     staged in LDS, and each lane finds its segment from the chunk's group
+//     table: per 64 sites, the segment holding the first one and a mask of
+//     the sites that begin a segment (one popcount);
+//   * the lateral neighbours are taken at the segment's constant offsets:
+//     j-1 / j+1 (a column away in compact order) from the staged window when
+//     they fall inside it, else from global memory, and i-1 / i+1 (a plane
+//     away) from global memory, where adjacent lanes read adjacent addresses
+//     of planes that were (or will be) streamed as some other chunk's centre.
+//     In the default chunk order each XCD (own L2) takes the same eighth of
+//     every x-plane, plane after plane, so those reads hit its L2.
 // The path is bandwidth bound (a 7-point stencil plus pointwise work), so
 // no matrix cores are used.  Reductions (norm, energy, overlaps, knot
 // gradients) accumulate in FP64 per lane, are reduced across the wavefront
